@@ -1,0 +1,188 @@
+"""Pins of the oracle's fixed point (Section 2, eqs. 1-2) and effective tensor."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import filter as F, rules, solver
+from workloads import lame, random_fraction_case, small_sphere_case
+
+PH = (lame(1.0, 0.3), lame(10.0, 0.3))
+
+
+def test_homogeneous_cell():
+    n = (5, 7, 3)
+    fld = solver.StiffnessField(n, 3, PH, "voigt", np.full(105, 0.3), None)
+    c0 = solver.reference_medium(PH)
+    E = solver.strain_tensor([0.01, -0.002, 0.003, 0.001, 0.0, 0.004])
+    r = solver.solve(fld, E, c0, tol=0.0, max_iter=2)
+    assert max(r["errs"]) < 1e-14
+    assert np.max(np.abs(r["eps"] - E)) < 1e-16
+    c = rules.voigt(0.3, rules.iso_tensor(*PH[0]), rules.iso_tensor(*PH[1]))
+    assert np.max(np.abs(r["sig_mean"] - np.einsum("ijkl,kl->ij", c, E))) < 1e-15
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_grid_aligned_laminate_matches_two_layer_rule(axis):
+    # the discrete solution of a laminate is piecewise constant and its
+    # effective tensor is the 2-layer rule with the layer fraction
+    n = [5, 5, 5]
+    n[axis] = 9
+    nx, ny, nz = n
+    f = np.zeros((nz, ny, nx))
+    sl = [slice(None)] * 3
+    sl[2 - axis] = slice(2, 5)
+    f[tuple(sl)] = 1.0
+    fld = solver.StiffnessField(tuple(n), 3, PH, "none", f, None)
+    c0 = solver.reference_medium(PH)
+    C, reps = solver.effective_tensor(fld, c0, 1e-13, 5000, 3, keep_fields=True)
+    nh = np.zeros(3)
+    nh[axis] = 1.0
+    ref = rules.to_mandel(rules.two_layer(3.0 / 9.0, nh, rules.iso_tensor(*PH[0]), rules.iso_tensor(*PH[1])))
+    assert np.max(np.abs(C - ref)) < 1e-11 * np.max(np.abs(ref))
+    # strain is uniform within each layer
+    e = reps[0]["eps"].reshape(nz, ny, nx, 3, 3)
+    lay = np.moveaxis(e, 2 - axis, 0)
+    for k in range(n[axis]):
+        assert np.max(np.abs(lay[k] - lay[k].reshape(-1, 3, 3)[0])) < 1e-12
+
+
+def test_2d_laminate_plane_strain():
+    n = (9, 7, 1)
+    f = np.zeros((1, 7, 9))
+    f[:, :, 0:4] = 1.0
+    fld = solver.StiffnessField(n, 2, PH, "none", f, None)
+    c0 = solver.reference_medium(PH)
+    C, _ = solver.effective_tensor(fld, c0, 1e-13, 5000, 2)
+    ref = rules.to_mandel(rules.two_layer(4.0 / 9.0, np.array([1.0, 0, 0]),
+                                          rules.iso_tensor(*PH[0]), rules.iso_tensor(*PH[1])))
+    assert C.shape == (3, 3)
+    assert np.max(np.abs(C - ref[np.ix_([0, 1, 5], [0, 1, 5])])) < 1e-11 * np.max(np.abs(ref))
+
+
+def _dense_solution(fld, E, c0):
+    """Solve (I + Gamma0 * dc) eps = E directly, the operator built with the naive DFT."""
+    n = fld.n
+    nx, ny, nz = n
+    N = nx * ny * nz
+    xi = solver.frequency_grid(n)
+    lam0, mu0 = c0
+    dc = fld.voxel_tensors() - rules.iso_tensor(lam0, mu0)
+    sym = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+
+    def op(v):
+        e = np.zeros((N, 3, 3))
+        for a, (i, j) in enumerate(sym):
+            e[:, i, j] = v[a::6]
+            e[:, j, i] = v[a::6]
+        tau = np.einsum("nijkl,nkl->nij", dc, e).reshape(nz, ny, nx, 3, 3)
+        th = solver.naive_dft(tau)
+        eh = solver._apply_gamma(th, xi, lam0, mu0)      # -Gamma0^ : tau^
+        g = np.real(solver.naive_dft(eh, sign=+1) / N).reshape(N, 3, 3)
+        out = e - g
+        return np.stack([out[:, i, j] for (i, j) in sym], axis=1).reshape(-1)
+
+    A = np.stack([op(col) for col in np.eye(6 * N)], axis=1)
+    rhs = np.tile([E[i, j] for (i, j) in sym], N)
+    x = np.linalg.solve(A, rhs)
+    out = np.zeros((N, 3, 3))
+    for a, (i, j) in enumerate(sym):
+        out[:, i, j] = x[a::6]
+        out[:, j, i] = x[a::6]
+    return out.reshape(nz, ny, nx, 3, 3)
+
+
+@pytest.mark.parametrize("rule", ["voigt", "reuss"])
+def test_fixed_point_limit_equals_dense_solve(rule):
+    n = (3, 3, 3)
+    f = random_fraction_case(7, n)
+    fld = solver.StiffnessField(n, 3, PH, rule, f, None)
+    c0 = solver.reference_medium(PH)
+    E = solver.strain_tensor([0.3, -0.1, 0.2, 0.05, -0.07, 0.11])
+    r = solver.solve(fld, E, c0, tol=1e-14, max_iter=3000)
+    assert r["status"] == solver.STATUS_CONVERGED
+    ref = _dense_solution(fld, E, c0)
+    assert np.max(np.abs(r["eps"] - ref)) < 1e-11
+
+
+def _sphere_field(n=9, rule="laminate", contrast=10.0):
+    w = small_sphere_case(n=(n, n, n), fraction=0.2, contrast=contrast, rule=rule,
+                          radius_vox=1.0, subsamples=4)
+    return w, solver.build_field(w)
+
+
+def test_effective_tensor_symmetric_bounded_cubic():
+    w, fld = _sphere_field(9)
+    c0 = solver.reference_medium(w.phases)
+    C, reps = solver.effective_tensor(fld, c0, 1e-12, 5000, 3)
+    assert all(r["status"] == solver.STATUS_CONVERGED for r in reps)
+    assert np.max(np.abs(C - C.T)) < 1e-10 * np.max(np.abs(C))
+    # Voigt/Reuss bounds over the filtered field
+    cm = rules.to_mandel(fld.voxel_tensors())
+    V = np.mean(cm, axis=0)
+    Rr = np.linalg.inv(np.mean(np.linalg.inv(cm), axis=0))
+    assert np.min(np.linalg.eigvalsh(V - C)) > -1e-10
+    assert np.min(np.linalg.eigvalsh(C - Rr)) > -1e-10
+    # cubic symmetry of a centred sphere on an odd grid
+    tol = 1e-9 * np.max(np.abs(C))
+    assert abs(C[0, 0] - C[1, 1]) < tol and abs(C[0, 0] - C[2, 2]) < tol
+    assert abs(C[0, 1] - C[0, 2]) < tol and abs(C[0, 1] - C[1, 2]) < tol
+    assert abs(C[3, 3] - C[4, 4]) < tol and abs(C[3, 3] - C[5, 5]) < tol
+    off = C.copy()
+    off[:3, :3] = 0
+    np.fill_diagonal(off, 0)
+    assert np.max(np.abs(off)) < tol
+
+
+def test_traction_history_identity():
+    """xi . sigma^_i = xi . (tau^_i - tau^_{i-1}) for i >= 1; xi . tau^_0 for i = 0."""
+    w, fld = _sphere_field(7)
+    c0 = solver.reference_medium(w.phases)
+    C0 = rules.iso_tensor(*c0)
+    xi = solver.frequency_grid(w.n)
+    E = solver.strain_tensor([0.0, 0.0, 0.0, 0.0, 0.0, 0.01])
+    eps = np.broadcast_to(E, (7, 7, 7, 3, 3)).copy()
+    prev = None
+    for i in range(4):
+        r = solver.solve(fld, E, c0, tol=0.0, max_iter=i)
+        sig = fld.apply(eps)
+        tau = sig - np.einsum("ijkl,zyxkl->zyxij", C0, eps)
+        th = np.fft.fftn(tau, axes=(0, 1, 2))
+        d = th if prev is None else th - prev
+        num = math.sqrt(float(np.sum(np.abs(np.einsum("zyxj,zyxij->zyxi", xi, d)) ** 2)))
+        den = float(np.linalg.norm(np.fft.fftn(sig, axes=(0, 1, 2))[0, 0, 0]))
+        assert num / den == pytest.approx(r["err"], rel=1e-9)
+        prev = th
+        eps = r["eps"]
+
+
+def test_reference_medium_below_optimal_diverges():
+    # Figure 3: below the optimal reference medium the fixed point does not converge
+    w, fld = _sphere_field(7, contrast=10.0)
+    E = solver.strain_tensor([0.01, 0, 0, 0, 0, 0])
+    ok = solver.solve(fld, E, solver.reference_medium(w.phases, 1.0), 1e-6, 2000)
+    assert ok["status"] == solver.STATUS_CONVERGED
+    bad = solver.solve(fld, E, solver.reference_medium(w.phases, 0.5), 1e-6, 2000)
+    assert bad["status"] == solver.STATUS_DIVERGED
+    assert bad["errs"][-1] > 1e3 * bad["errs"][0]
+
+
+def test_max_iter_and_stall_statuses():
+    w, fld = _sphere_field(7, contrast=100.0)
+    c0 = solver.reference_medium(w.phases)
+    E = solver.strain_tensor([0.01, 0, 0, 0, 0, 0])
+    r = solver.solve(fld, E, c0, 1e-12, 5)
+    assert r["status"] == solver.STATUS_NOT_CONVERGED and r["iters"] == 5 and len(r["errs"]) == 6
+    # a 1-iteration stall window on an error that cannot keep dropping 1% per step
+    r2 = solver.solve(fld, E, c0, 1e-14, 400, stall_window=1)
+    assert r2["status"] in (solver.STATUS_STALLED, solver.STATUS_CONVERGED)
+
+
+def test_filter_does_not_change_iteration_count_much():
+    # Section 5 / Figure 3: filtering has no marked effect on the iteration count
+    its = []
+    for rule in ["none", "voigt", "laminate"]:
+        w, fld = _sphere_field(15, rule=rule, contrast=10.0)
+        r = solver.solve(fld, [0.01, 0, 0, 0, 0, 0], solver.reference_medium(w.phases), 1e-4, 2000)
+        its.append(r["iters"])
+    assert max(its) - min(its) <= 0.25 * max(its)
