@@ -1,0 +1,231 @@
+/*
+ * hm.h - C ABI of the MI355X (gfx950) filtered-property Lippmann-Schwinger
+ * solver.
+ *
+ * Method: L. Gelebart, F. Ouaki, "Filtering material properties to improve
+ * FFT-based methods for numerical homogenization" (arXiv:1412.3228).
+ * Section 2 defines the problem (a periodic cell of stiffness field c under
+ * a macroscopic strain E), the Lippmann-Schwinger equations (eqs. 1-a, 1-b),
+ * the Green operator in Fourier space (eq. 2), the odd truncated frequency
+ * set J, the filtered stiffness c~(x_a) = HR(c, omega(x_a)) with phase
+ * fractions from a refined grid, the Voigt, Reuss and 2-layer rules
+ * (eqs. 3, 4, 5) and the numerical setup (filter radius in pixel units,
+ * interface normal from the inclusion centre, stress-equilibrium criterion).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Grid      dim = 2 (plane strain) or 3.  n[0], n[1], n[2] are the voxel
+ *           counts along x, y, z; every n[d] must be odd and a product of
+ *           3, 5 and 7 no larger than 243 (n[2] == 1 when dim == 2).
+ *           Voxel (i, j, k) has its centre at (i + 0.5, j + 0.5, k + 0.5)
+ *           in voxel units; the cell is periodic.
+ * Fields    Real per-voxel fields are stored [z][y][x] (x fastest).
+ *           Strain fields are [load][component][z][y][x] with the tensor
+ *           components in the order 11, 22, 33, 23, 13, 12 (no sqrt(2)).
+ *           In 2D the six components are still stored (33, 23, 13 are 0).
+ * Tensors   Effective tensors are Mandel matrices (order 11, 22, 33, 23,
+ *           13, 12 with sqrt(2) on shear rows and columns), column-major
+ *           = row-major because they are symmetric up to solver tolerance;
+ *           in 2D the 3x3 in-plane block (11, 22, 12).
+ * Phases    phases[0] is the matrix, phases[1] the inclusion; the fraction
+ *           field holds the inclusion volume fraction f in each filter.
+ * Precision HM_FP64: every field and transform in double.  HM_MIXED:
+ *           fields, transforms and the polarization in float; the
+ *           equilibrium-error norm, the mean stress and the effective
+ *           tensor are accumulated in double.  Fraction fields are double
+ *           for HM_FP64 and float for HM_MIXED.
+ * Memory    Pointers named d_* are device pointers on the current HIP
+ *           device, owned by the caller; other pointers are host memory,
+ *           read or written synchronously before the call returns.  The
+ *           library owns its per-grid plans and workspace (released by
+ *           hm_release_plans).  Device work is ordered on `stream`
+ *           (a hipStream_t, NULL for the default stream); calls that
+ *           return host results synchronise that stream.
+ * Errors    Calls return HM_OK (0) on success, a positive warning when the
+ *           solve stopped without meeting the tolerance (outputs are still
+ *           written), or a negative error with nothing written;
+ *           hm_last_error() returns the calling thread's last message.
+ *           Calls on one stream must not overlap in time from several host
+ *           threads (the workspace of a plan is shared).
+ */
+#ifndef HM_H
+#define HM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define HM_OK 0
+#define HM_NOT_CONVERGED 1 /* max_iter reached before e < tol          */
+#define HM_STALLED 2       /* error stopped decreasing (stall window)  */
+#define HM_DIVERGED 3      /* error not finite or above 1e3 * e_0      */
+#define HM_E_ARG (-1)      /* invalid argument                          */
+#define HM_E_SIZE (-2)     /* unsupported grid size                     */
+#define HM_E_NOMEM (-3)    /* device allocation failed                  */
+#define HM_E_DEVICE (-4)   /* HIP runtime error                         */
+#define HM_E_DATA (-5)     /* device input inconsistent with the rule   */
+
+/* Homogenisation rule of the filter (Section 2, eqs. 3-5). */
+typedef enum {
+  HM_RULE_NONE = 0,     /* no filter: c~ = phase tensor at the grid point  */
+  HM_RULE_VOIGT = 1,    /* eq. 3: fraction-weighted mean of stiffnesses    */
+  HM_RULE_REUSS = 2,    /* eq. 4: inverse of the mean of compliances       */
+  HM_RULE_LAMINATE = 3  /* eq. 5: two-phase laminate ("2-layer") rule      */
+} hm_rule;
+
+typedef enum { HM_FP64 = 0, HM_MIXED = 1 } hm_prec;
+
+typedef struct {
+  int dim;  /* 2 or 3 */
+  int n[3]; /* voxels along x, y, z */
+} hm_grid;
+
+/* Isotropic elastic phase: Lame parameters. */
+typedef struct {
+  double lambda, mu;
+} hm_iso;
+
+/* Spherical (3D) or circular (2D, c[2] ignored) inclusion, voxel units,
+ * centre in [0, n[d]) per axis, radius > 0. */
+typedef struct {
+  double c[3];
+  double r;
+} hm_sphere;
+
+typedef struct {
+  hm_prec prec;     /* HM_FP64 or HM_MIXED                                   */
+  double tol;       /* stop when the equilibrium error e_i < tol (0: never)   */
+  int max_iter;     /* last iterate index evaluated (>= 0)                   */
+  double c0_alpha;  /* reference medium = alpha * mean of min/max Lame (> 0) */
+  int check_every;  /* host polls the stop flags every k iterations (>= 1)   */
+  int stall_window; /* > 0: stop when e has not dropped 1% for this many its */
+  int use_graph;    /* nonzero: replay the iteration through a HIP graph      */
+} hm_solve_opts;
+
+/* Per-load-case outcome. */
+typedef struct {
+  int iters;      /* index i of the reported iterate                      */
+  int status;     /* HM_OK, HM_NOT_CONVERGED, HM_STALLED or HM_DIVERGED   */
+  double err;     /* equilibrium error e_i of the reported iterate        */
+  double err0;    /* e_0                                                  */
+  double seconds; /* wall time of the whole call                          */
+} hm_report;
+
+/*
+ * hm_filter - per-voxel phase fractions of a sphere/disk microstructure.
+ *
+ * Section 2: c~(x_a) = HR(c, omega(x_a)) with omega a uniform filter
+ * centred on the grid point, the fractions being averages of the phase
+ * indicators on a refined grid; the numerical setup gives the filter
+ * radius in pixel units.  Refined grid: `subsamples` = S (even, 2..32)
+ * points per voxel and axis, on the global lattice of spacing 1/S voxel
+ * whose points are the centres of the S^dim sub-cells of every voxel.  A
+ * refined point belongs to the inclusion set when its periodic minimum-image
+ * distance to some sphere centre is <= that sphere's radius (centres are
+ * rounded to the nearest multiple of 1/(2S) voxel).  The filter keeps the
+ * refined points within `radius_vox` voxels of the voxel centre (closed
+ * ball); M is their number.  rule == HM_RULE_NONE ignores the radius and
+ * takes the single indicator value at the voxel centre (M = 1).
+ *
+ * Outputs (device, N = n[0]*n[1]*n[2] entries each, [z][y][x]):
+ *   d_count  uint32 number of filter points inside the inclusion set;
+ *   d_frac   count / M as one IEEE division, double (HM_FP64) or float
+ *            (HM_MIXED);
+ *   d_incl   nullable; for voxels with 0 < count < M the index of the
+ *            sphere whose surface is nearest to the voxel centre (lowest
+ *            index on ties), -1 elsewhere.
+ * Counts are exact integers; the call returns once the kernel is queued.
+ */
+int hm_filter(const hm_grid* grid, const hm_sphere* spheres, int n_spheres,
+              double radius_vox, int subsamples, hm_rule rule, hm_prec prec,
+              uint32_t* d_count, void* d_frac, int32_t* d_incl, void* stream);
+
+/*
+ * hm_solve - basic fixed-point Lippmann-Schwinger solve with the filtered
+ * stiffness, for n_load macroscopic strains at once.
+ *
+ * Section 2, eqs. 1-a, 1-b and 2: tau = (c~ - c0) : eps,
+ * eps^(xi) = -Gamma0^(xi) : tau^(xi) for xi != 0, eps^(0) = E, on the odd
+ * frequency set J with xi = 2 pi a.  c~ per voxel: the phase tensor where
+ * f is exactly 0 or 1, else `rule` applied to f (HM_RULE_LAMINATE uses the
+ * normal from the centre of sphere d_incl[v] to the voxel centre; e_1 when
+ * d_incl[v] < 0).  c0 is isotropic with Lame parameters c0_alpha times the
+ * mean of the phases' smallest and largest values (Figure 3 caption).
+ * Iterate i evaluates sigma_i = c~ : eps_i and its stress-equilibrium error
+ * e_i = sqrt(sum_xi |xi . sigma^_i(xi)|^2) / |sigma^_i(0)| (Section 2 setup;
+ * unnormalised DFT, Frobenius norms) and stops as hm_report describes.
+ *
+ * Inputs:  d_frac (N, precision of opts->prec), d_incl (N int32, required
+ *          for HM_RULE_LAMINATE, else nullable), spheres (host, used for the
+ *          laminate normals), E (host, 6 * n_load doubles, tensor
+ *          components 11, 22, 33, 23, 13, 12 of each load case).
+ * Outputs: sig_mean (host, 6 * n_load doubles, <sigma_i> of the reported
+ *          iterate), rep (host, n_load entries, nullable), d_eps (nullable,
+ *          device, 6 * N * n_load reals of the solve precision: the strain
+ *          field produced by the update from the reported iterate).
+ * Returns the largest status over load cases, or a negative error.
+ * HM_E_DATA: a fractional voxel with HM_RULE_NONE, or d_incl out of range.
+ */
+int hm_solve(const hm_grid* grid, const hm_iso phases[2], hm_rule rule,
+             const void* d_frac, const int32_t* d_incl,
+             const hm_sphere* spheres, int n_spheres,
+             const double* E, int n_load, const hm_solve_opts* opts,
+             void* d_eps, double* sig_mean, hm_report* rep, void* stream);
+
+/*
+ * hm_effective_tensor - effective stiffness from the mean stresses of the
+ * unit Mandel strains (6 in 3D, 11/22/12 in 2D), all solved in one batched
+ * launch (the paper's macroscopic output is the average stress, Section 3).
+ * Column J of C_mandel is Mandel(<sigma>) under the J-th unit Mandel strain.
+ * Inputs as hm_solve.  Outputs: C_mandel (host, 36 or 9 doubles, row-major),
+ * rep (host, 6 or 3 entries, nullable), d_eps (nullable, device strain
+ * fields of the 6 or 3 solves, as hm_solve).
+ */
+int hm_effective_tensor(const hm_grid* grid, const hm_iso phases[2], hm_rule rule,
+                        const void* d_frac, const int32_t* d_incl,
+                        const hm_sphere* spheres, int n_spheres,
+                        const hm_solve_opts* opts, double* C_mandel,
+                        void* d_eps, hm_report* rep, void* stream);
+
+/*
+ * hm_solve_adjoint - gradient of a loss L(C_eff) with respect to the phase
+ * Lame parameters and the per-voxel fraction field.
+ *
+ * The discrete problem is self-adjoint (Gamma0 and c~ are symmetric), so
+ * the adjoint fields of the unit-strain solves are those solves' own
+ * fields and dC_KL/dtheta = (1/N) sum_x eps^K : dc~/dtheta : eps^L (Hill
+ * energy identity at the discrete solution).  dc~/dtheta differentiates the
+ * rule of eqs. 3-5 at each voxel's fraction and normal; pure voxels use the
+ * phase tensor for the Lame derivatives; c0 is held fixed.
+ *
+ * Inputs:  dLdC (host, 36 or 9 doubles, row-major, = dL/dC_mandel),
+ *          d_eps (device, the n_load = 6 or 3 fields written by
+ *          hm_effective_tensor with the same inputs, solve precision),
+ *          d_frac, d_incl, spheres as hm_solve.
+ * Outputs: dLdphase (host, 4 doubles: dL/dlambda_0, dL/dmu_0, dL/dlambda_1,
+ *          dL/dmu_1, accumulated in double), d_dLdfrac (nullable, device,
+ *          N reals of the solve precision, zero for HM_RULE_NONE).
+ */
+int hm_solve_adjoint(const hm_grid* grid, const hm_iso phases[2], hm_rule rule,
+                     const void* d_frac, const int32_t* d_incl,
+                     const hm_sphere* spheres, int n_spheres, hm_prec prec,
+                     const double* dLdC, const void* d_eps, int n_load,
+                     double* dLdphase, void* d_dLdfrac, void* stream);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char* hm_last_error(void);
+
+/* Frees every cached plan, workspace and graph (device memory). */
+void hm_release_plans(void);
+
+/* 1 if the library can launch on the current device, else 0. */
+int hm_device_ok(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HM_H */

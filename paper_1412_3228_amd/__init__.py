@@ -1,0 +1,17 @@
+"""MI355X (gfx950) filtered-property Lippmann-Schwinger solver.
+
+Method: L. Gelebart, F. Ouaki, "Filtering material properties to improve
+FFT-based methods for numerical homogenization" (arXiv:1412.3228).  The
+compute path is the HIP library libhm.so (C ABI in include/hm.h); this
+package is its thin Python binding.
+"""
+from .api import (  # noqa: F401
+    EffectiveTensor,
+    device_ok,
+    hm_effective_tensor,
+    hm_filter,
+    hm_solve,
+    hm_solve_adjoint,
+    release_plans,
+)
+from ._lib import EXPORTS, HmError, LIB_PATH, load  # noqa: F401

@@ -1,0 +1,94 @@
+"""ctypes declarations of the C ABI in include/hm.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhm.so")
+
+HM_OK = 0
+HM_NOT_CONVERGED = 1
+HM_STALLED = 2
+HM_DIVERGED = 3
+HM_E_ARG = -1
+HM_E_SIZE = -2
+HM_E_NOMEM = -3
+HM_E_DEVICE = -4
+HM_E_DATA = -5
+
+RULES = {"none": 0, "voigt": 1, "reuss": 2, "laminate": 3}
+PRECS = {"fp64": 0, "mixed": 1}
+
+# Every symbol include/hm.h declares.
+EXPORTS = ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_solve_adjoint",
+           "hm_last_error", "hm_release_plans", "hm_device_ok")
+
+
+class HmGrid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3)]
+
+
+class HmIso(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_double), ("mu", ctypes.c_double)]
+
+
+class HmSphere(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double * 3), ("r", ctypes.c_double)]
+
+
+class HmSolveOpts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("c0_alpha", ctypes.c_double), ("check_every", ctypes.c_int),
+                ("stall_window", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
+class HmReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("err", ctypes.c_double),
+                ("err0", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+_dp = _P(ctypes.c_double)
+_lib = None
+
+
+class HmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("hm error %d: %s" % (code, msg))
+        self.code = code
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads libhm.so once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libhm.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    lib.hm_filter.argtypes = [_P(HmGrid), _P(HmSphere), ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                              ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]
+    lib.hm_solve.argtypes = [_P(HmGrid), _P(HmIso), ctypes.c_int, _vp, _vp, _P(HmSphere), ctypes.c_int,
+                             _dp, ctypes.c_int, _P(HmSolveOpts), _vp, _dp, _P(HmReport), _vp]
+    lib.hm_effective_tensor.argtypes = [_P(HmGrid), _P(HmIso), ctypes.c_int, _vp, _vp, _P(HmSphere),
+                                        ctypes.c_int, _P(HmSolveOpts), _dp, _vp, _P(HmReport), _vp]
+    lib.hm_solve_adjoint.argtypes = [_P(HmGrid), _P(HmIso), ctypes.c_int, _vp, _vp, _P(HmSphere),
+                                     ctypes.c_int, ctypes.c_int, _dp, _vp, ctypes.c_int, _dp, _vp, _vp]
+    for f in ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_solve_adjoint", "hm_device_ok"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.hm_last_error.argtypes = []
+    lib.hm_last_error.restype = ctypes.c_char_p
+    lib.hm_release_plans.argtypes = []
+    lib.hm_release_plans.restype = None
+    lib.hm_device_ok.argtypes = []
+    _lib = lib
+    return lib
+
+
+def check(rc: int, allow_warnings: bool = True) -> int:
+    """Raises HmError on a negative code; returns warnings (>0) unchanged."""
+    if rc < 0 or (rc > 0 and not allow_warnings):
+        msg = load().hm_last_error().decode()
+        raise HmError(rc, msg)
+    return rc

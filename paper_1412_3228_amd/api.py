@@ -1,0 +1,224 @@
+"""Python binding of the C ABI (include/hm.h) on torch device tensors.
+
+Only argument marshalling lives here: every step of the filter, the solve
+and the gradient runs in the HIP library.  PyTorch provides device memory
+and the current stream.  Importing works without a GPU; calling needs the
+built library and a gfx950 device, and fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_DT = {"fp64": torch.float64, "mixed": torch.float32}
+
+
+def _lib():
+    lib = L.load()
+    return lib
+
+
+def _device(device) -> torch.device:
+    d = torch.device(device)
+    if d.type != "cuda":
+        raise ValueError("the HIP library needs a cuda (HIP) device, got %s" % d)
+    return d
+
+
+def _grid(n: Sequence[int], dim: int) -> L.HmGrid:
+    g = L.HmGrid()
+    g.dim = int(dim)
+    for i in range(3):
+        g.n[i] = int(n[i])
+    return g
+
+
+def _spheres(spheres) -> tuple:
+    sph = np.asarray(spheres, dtype=np.float64).reshape(-1, 4)
+    arr = (L.HmSphere * max(1, sph.shape[0]))()
+    for k in range(sph.shape[0]):
+        arr[k].c[0], arr[k].c[1], arr[k].c[2] = (float(v) for v in sph[k, :3])
+        arr[k].r = float(sph[k, 3])
+    return arr, int(sph.shape[0])
+
+
+def _phases(phases) -> ctypes.Array:
+    arr = (L.HmIso * 2)()
+    for p in range(2):
+        arr[p].lam = float(phases[p][0])
+        arr[p].mu = float(phases[p][1])
+    return arr
+
+
+def _stream(dev: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph) -> L.HmSolveOpts:
+    o = L.HmSolveOpts()
+    o.prec = L.PRECS[prec]
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.c0_alpha = float(c0_alpha)
+    o.check_every = int(check_every)
+    o.stall_window = int(stall_window)
+    o.use_graph = 1 if use_graph else 0
+    return o
+
+
+def _reports(rep, k):
+    return [{"iters": rep[i].iters, "status": rep[i].status, "err": rep[i].err,
+             "err0": rep[i].err0, "seconds": rep[i].seconds} for i in range(k)]
+
+
+def _check_field(t: torch.Tensor, N: int, dtype, dev, name: str):
+    if t is None:
+        return
+    if t.device != dev or t.dtype != dtype or t.numel() != N or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s tensor of %d entries on %s" % (name, dtype, N, dev))
+
+
+def hm_filter(n, dim, spheres, radius_vox: float, subsamples: int, rule: str, prec: str = "fp64",
+              device="cuda:0"):
+    """Per-voxel counts, fractions and normal-sphere ids (see hm_filter in include/hm.h)."""
+    dev = _device(device)
+    N = int(n[0] * n[1] * n[2])
+    count = torch.empty(N, dtype=torch.int32, device=dev)
+    frac = torch.empty(N, dtype=_DT[prec], device=dev)
+    incl = torch.empty(N, dtype=torch.int32, device=dev)
+    g = _grid(n, dim)
+    sph, ns = _spheres(spheres)
+    rc = _lib().hm_filter(ctypes.byref(g), sph, ns, float(radius_vox), int(subsamples), L.RULES[rule],
+                          L.PRECS[prec], _ptr(count), _ptr(frac), _ptr(incl), _stream(dev))
+    L.check(rc)
+    return count, frac, incl
+
+
+def hm_solve(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres, E,
+             prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
+             check_every: int = 1, stall_window: int = 0, use_graph: bool = False, want_eps: bool = False):
+    """Fixed-point solve for the rows of E (n_load x 6 tensor components)."""
+    dev = frac.device
+    N = int(n[0] * n[1] * n[2])
+    _check_field(frac, N, _DT[prec], dev, "frac")
+    _check_field(incl, N, torch.int32, dev, "incl")
+    Ea = np.ascontiguousarray(np.asarray(E, dtype=np.float64).reshape(-1, 6))
+    nl = Ea.shape[0]
+    sig = np.zeros((nl, 6))
+    rep = (L.HmReport * nl)()
+    eps = torch.empty((nl, 6, N), dtype=_DT[prec], device=dev) if want_eps else None
+    g = _grid(n, dim)
+    sph, ns = _spheres(spheres)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph)
+    rc = _lib().hm_solve(ctypes.byref(g), _phases(phases), L.RULES[rule], _ptr(frac), _ptr(incl), sph, ns,
+                         Ea.ctypes.data_as(L._dp), nl, ctypes.byref(o), _ptr(eps),
+                         sig.ctypes.data_as(L._dp), rep, _stream(dev))
+    L.check(rc)
+    return {"status": rc, "sig_mean": sig, "reports": _reports(rep, nl), "eps": eps}
+
+
+def hm_effective_tensor(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres,
+                        prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
+                        check_every: int = 1, stall_window: int = 0, use_graph: bool = False,
+                        want_eps: bool = False):
+    """Effective Mandel tensor from the unit-strain solves (6 in 3D, 3 in 2D)."""
+    dev = frac.device
+    N = int(n[0] * n[1] * n[2])
+    _check_field(frac, N, _DT[prec], dev, "frac")
+    _check_field(incl, N, torch.int32, dev, "incl")
+    k = 3 if dim == 2 else 6
+    C = np.zeros((k, k))
+    rep = (L.HmReport * k)()
+    eps = torch.empty((k, 6, N), dtype=_DT[prec], device=dev) if want_eps else None
+    g = _grid(n, dim)
+    sph, ns = _spheres(spheres)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph)
+    rc = _lib().hm_effective_tensor(ctypes.byref(g), _phases(phases), L.RULES[rule], _ptr(frac), _ptr(incl),
+                                    sph, ns, ctypes.byref(o), C.ctypes.data_as(L._dp), _ptr(eps), rep,
+                                    _stream(dev))
+    L.check(rc)
+    return {"status": rc, "C": C, "reports": _reports(rep, k), "eps": eps}
+
+
+def hm_solve_adjoint(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres,
+                     dLdC, eps: torch.Tensor, prec: str = "fp64", want_dfrac: bool = True):
+    """dL/d(lambda_0, mu_0, lambda_1, mu_1) and dL/dfrac from the unit-strain fields."""
+    dev = frac.device
+    N = int(n[0] * n[1] * n[2])
+    k = 3 if dim == 2 else 6
+    _check_field(frac, N, _DT[prec], dev, "frac")
+    _check_field(incl, N, torch.int32, dev, "incl")
+    if eps.device != dev or eps.dtype != _DT[prec] or eps.numel() != k * 6 * N or not eps.is_contiguous():
+        raise ValueError("eps must hold the %d unit-strain fields (%d x 6 x %d)" % (k, k, N))
+    G = np.ascontiguousarray(np.asarray(dLdC, dtype=np.float64).reshape(k, k))
+    dph = np.zeros(4)
+    dfr = torch.empty(N, dtype=_DT[prec], device=dev) if want_dfrac else None
+    g = _grid(n, dim)
+    sph, ns = _spheres(spheres)
+    rc = _lib().hm_solve_adjoint(ctypes.byref(g), _phases(phases), L.RULES[rule], _ptr(frac), _ptr(incl), sph,
+                                 ns, L.PRECS[prec], G.ctypes.data_as(L._dp), _ptr(eps), k,
+                                 dph.ctypes.data_as(L._dp), _ptr(dfr), _stream(dev))
+    L.check(rc)
+    return dph, dfr
+
+
+def release_plans():
+    _lib().hm_release_plans()
+
+
+def device_ok() -> bool:
+    return bool(_lib().hm_device_ok())
+
+
+class EffectiveTensor(torch.autograd.Function):
+    """C_eff(lame, frac) with a backward pass through hm_solve_adjoint.
+
+    forward(lame, frac, cell) where lame = (lambda_0, mu_0, lambda_1, mu_1)
+    (CPU float64 tensor), frac the per-voxel fraction field (device tensor
+    of the solve precision) and cell a dict with keys n, dim, rule, incl,
+    spheres, prec, tol, max_iter and optionally checkpoint.  The unit-strain
+    fields are kept for the backward pass unless cell["checkpoint"] is
+    true, in which case they are recomputed there (less memory, one more
+    batched solve).
+    """
+
+    @staticmethod
+    def forward(ctx, lame, frac, cell):
+        ph = ((float(lame[0]), float(lame[1])), (float(lame[2]), float(lame[3])))
+        keep = not cell.get("checkpoint", False)
+        out = hm_effective_tensor(cell["n"], cell["dim"], ph, cell["rule"], frac.detach(), cell.get("incl"),
+                                  cell["spheres"], prec=cell.get("prec", "fp64"), tol=cell.get("tol", 1e-4),
+                                  max_iter=cell.get("max_iter", 10000), check_every=cell.get("check_every", 8),
+                                  want_eps=keep)
+        ctx.cell = cell
+        ctx.ph = ph
+        ctx.eps = out["eps"]
+        ctx.save_for_backward(frac)
+        ctx.reports = out["reports"]
+        return torch.from_numpy(out["C"].copy())
+
+    @staticmethod
+    def backward(ctx, gC):
+        (frac,) = ctx.saved_tensors
+        cell = ctx.cell
+        eps = ctx.eps
+        if eps is None:
+            eps = hm_effective_tensor(cell["n"], cell["dim"], ctx.ph, cell["rule"], frac.detach(),
+                                      cell.get("incl"), cell["spheres"], prec=cell.get("prec", "fp64"),
+                                      tol=cell.get("tol", 1e-4), max_iter=cell.get("max_iter", 10000),
+                                      check_every=cell.get("check_every", 8), want_eps=True)["eps"]
+        dph, dfr = hm_solve_adjoint(cell["n"], cell["dim"], ctx.ph, cell["rule"], frac.detach(), cell.get("incl"),
+                                    cell["spheres"], gC.detach().cpu().numpy(), eps,
+                                    prec=cell.get("prec", "fp64"))
+        ctx.eps = None
+        return torch.from_numpy(dph), dfr, None

@@ -1,0 +1,677 @@
+// C ABI of the library (declared in include/hm.h): argument checks, plans
+// (per precision, grid and load count: workspace, twiddles, launch
+// arguments, captured graphs) and the host side of the fixed-point loop.
+//
+// The loop launches xsweep, ysweep(forward), zsweep, ysweep(inverse) and
+// finalize per iteration; finalize decides on the device whether a load case
+// stops (Section 2 setup: stress-equilibrium criterion), and the sweeps of a
+// stopped load case return at once, so the host only polls the stop flags
+// every `check_every` iterations and the iteration counts are exact.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/hm.h"
+#include "hm_common.hpp"
+#include "hm_adjoint.hpp"
+#include "hm_filter.hpp"
+#include "hm_solve_kernels.hpp"
+
+namespace hm {
+
+const AxisKernels* axis_kernels_f64_g0(int n);
+const AxisKernels* axis_kernels_f64_g1(int n);
+const AxisKernels* axis_kernels_f64_g2(int n);
+const AxisKernels* axis_kernels_f64_g3(int n);
+const AxisKernels* axis_kernels_f32_g0(int n);
+const AxisKernels* axis_kernels_f32_g1(int n);
+const AxisKernels* axis_kernels_f32_g2(int n);
+const AxisKernels* axis_kernels_f32_g3(int n);
+
+const AxisKernels* axis_kernels(bool fp64, int n) {
+  const AxisKernels* k = nullptr;
+  if (fp64) {
+    if (!k) k = axis_kernels_f64_g0(n);
+    if (!k) k = axis_kernels_f64_g1(n);
+    if (!k) k = axis_kernels_f64_g2(n);
+    if (!k) k = axis_kernels_f64_g3(n);
+  } else {
+    if (!k) k = axis_kernels_f32_g0(n);
+    if (!k) k = axis_kernels_f32_g1(n);
+    if (!k) k = axis_kernels_f32_g2(n);
+    if (!k) k = axis_kernels_f32_g3(n);
+  }
+  return k;
+}
+
+
+}  // namespace hm
+
+using namespace hm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HM_HIP(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(HM_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kMaxLoads = 8;
+
+bool supported_length(int n) {
+  if (n < 1 || n > 243) return false;
+  int m = n;
+  while (m % 7 == 0) m /= 7;
+  while (m % 5 == 0) m /= 5;
+  while (m % 3 == 0) m /= 3;
+  return m == 1;
+}
+
+int check_grid(const hm_grid* g) {
+  if (!g) return fail(HM_E_ARG, "grid is NULL");
+  if (g->dim != 2 && g->dim != 3) return fail(HM_E_ARG, "dim must be 2 or 3 (got %d)", g->dim);
+  for (int d = 0; d < 3; ++d) {
+    if (g->n[d] < 1) return fail(HM_E_ARG, "n[%d] = %d must be positive", d, g->n[d]);
+    if (g->n[d] % 2 == 0) return fail(HM_E_SIZE, "n[%d] = %d must be odd", d, g->n[d]);
+    if (!supported_length(g->n[d]))
+      return fail(HM_E_SIZE, "n[%d] = %d must be a product of 3, 5, 7 and <= 243", d, g->n[d]);
+  }
+  if (g->dim == 2 && g->n[2] != 1) return fail(HM_E_ARG, "2D grids need n[2] == 1");
+  if (g->dim == 3 && (g->n[0] < 3 || g->n[1] < 3 || g->n[2] < 3))
+    return fail(HM_E_SIZE, "3D grids need at least 3 voxels per axis");
+  if (g->dim == 2 && (g->n[0] < 3 || g->n[1] < 3)) return fail(HM_E_SIZE, "2D grids need at least 3x3 voxels");
+  return HM_OK;
+}
+
+int check_spheres(const hm_grid* g, const hm_sphere* s, int ns) {
+  if (ns < 0) return fail(HM_E_ARG, "n_spheres < 0");
+  if (ns > 0 && !s) return fail(HM_E_ARG, "spheres is NULL");
+  const int axes = g->dim == 2 ? 2 : 3;
+  for (int k = 0; k < ns; ++k) {
+    if (!(s[k].r > 0.0) || !isfinite(s[k].r)) return fail(HM_E_ARG, "sphere %d: radius must be > 0", k);
+    for (int a = 0; a < axes; ++a)
+      if (!(s[k].c[a] >= 0.0 && s[k].c[a] < (double)g->n[a]))
+        return fail(HM_E_ARG, "sphere %d: centre coordinate %d outside [0, n)", k, a);
+  }
+  return HM_OK;
+}
+
+int check_phases(const hm_iso* ph) {
+  if (!ph) return fail(HM_E_ARG, "phases is NULL");
+  for (int p = 0; p < 2; ++p) {
+    if (!isfinite(ph[p].lambda) || !isfinite(ph[p].mu) || !(ph[p].mu > 0.0) ||
+        !(3.0 * ph[p].lambda + 2.0 * ph[p].mu > 0.0))
+      return fail(HM_E_ARG, "phase %d: needs mu > 0 and 3 lambda + 2 mu > 0", p);
+  }
+  return HM_OK;
+}
+
+int check_opts(const hm_solve_opts* o) {
+  if (!o) return fail(HM_E_ARG, "opts is NULL");
+  if (o->prec != HM_FP64 && o->prec != HM_MIXED) return fail(HM_E_ARG, "unknown precision");
+  if (!(o->tol >= 0.0)) return fail(HM_E_ARG, "tol must be >= 0");
+  if (o->max_iter < 0) return fail(HM_E_ARG, "max_iter must be >= 0");
+  if (!(o->c0_alpha > 0.0) || !isfinite(o->c0_alpha)) return fail(HM_E_ARG, "c0_alpha must be > 0");
+  if (o->check_every < 1) return fail(HM_E_ARG, "check_every must be >= 1");
+  if (o->stall_window < 0) return fail(HM_E_ARG, "stall_window must be >= 0");
+  return HM_OK;
+}
+
+// Twiddles exp(-2 pi i k / n) computed in long double, rounded once.
+std::vector<double> twiddles(int n) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  std::vector<double> t(2 * (size_t)n);
+  for (int k = 0; k < n; ++k) {
+    const long double ang = -2.0L * pi * (long double)k / (long double)n;
+    t[2 * k] = (double)cosl(ang);
+    t[2 * k + 1] = (double)sinl(ang);
+  }
+  return t;
+}
+
+struct Plan {
+  bool fp64 = true;
+  int n[3] = {0, 0, 0};
+  int n_load = 0;
+  int device = 0;
+  const AxisKernels* kx = nullptr;
+  const AxisKernels* ky = nullptr;
+  const AxisKernels* kz = nullptr;
+  void* spec = nullptr;
+  void* hist = nullptr;
+  double* taupart = nullptr;
+  double* errpart = nullptr;
+  SolverState* state = nullptr;
+  SolverState* state_host = nullptr;  // pinned
+  double* errhist = nullptr;
+  int hist_cap = 0;
+  SolveParams* prm = nullptr;
+  SolveParams* prm_host = nullptr;  // pinned staging
+  double* sph = nullptr;
+  int sph_cap = 0;
+  void* tw[3] = {nullptr, nullptr, nullptr};
+  SolveArgs args;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  int graph_k = 0;
+};
+
+std::mutex g_mutex;
+std::map<std::tuple<int, bool, int, int, int, int>, Plan*> g_plans;
+
+void free_plan(Plan* p) {
+  if (p->graph) (void)hipGraphExecDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  (void)hipFree(p->spec);
+  (void)hipFree(p->hist);
+  (void)hipFree(p->taupart);
+  (void)hipFree(p->errpart);
+  (void)hipFree(p->state);
+  (void)hipFree(p->errhist);
+  (void)hipFree(p->prm);
+  (void)hipFree(p->sph);
+  for (int a = 0; a < 3; ++a) (void)hipFree(p->tw[a]);
+  if (p->state_host) (void)hipHostFree(p->state_host);
+  if (p->prm_host) (void)hipHostFree(p->prm_host);
+  delete p;
+}
+
+int device_alloc(void** ptr, size_t bytes, const char* what) {
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(HM_E_NOMEM, "cannot allocate %zu bytes for %s: %s", bytes, what, hipGetErrorString(e));
+  }
+  return HM_OK;
+}
+
+int upload_twiddles(Plan* p, int axis, int n) {
+  std::vector<double> t = twiddles(n);
+  const size_t bytes = (size_t)n * (p->fp64 ? 16 : 8);
+  int rc = device_alloc(&p->tw[axis], bytes, "twiddles");
+  if (rc) return rc;
+  if (p->fp64) {
+    HM_HIP(hipMemcpy(p->tw[axis], t.data(), bytes, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(t.size());
+    for (size_t i = 0; i < t.size(); ++i) f[i] = (float)t[i];
+    HM_HIP(hipMemcpy(p->tw[axis], f.data(), bytes, hipMemcpyHostToDevice));
+  }
+  return HM_OK;
+}
+
+int get_plan(bool fp64, const int n[3], int dim, int n_load, Plan** out) {
+  int dev = 0;
+  HM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_mutex);
+  auto key = std::make_tuple(dev, fp64, n[0], n[1], n[2], n_load);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    *out = it->second;
+    return HM_OK;
+  }
+  Plan* p = new Plan();
+  p->fp64 = fp64;
+  p->device = dev;
+  for (int d = 0; d < 3; ++d) p->n[d] = n[d];
+  p->n_load = n_load;
+  p->kx = axis_kernels(fp64, n[0]);
+  p->ky = axis_kernels(fp64, n[1]);
+  p->kz = axis_kernels(fp64, n[2]);
+  if (!p->kx || !p->ky || !p->kz) {
+    delete p;
+    return fail(HM_E_SIZE, "no kernels compiled for grid %dx%dx%d", n[0], n[1], n[2]);
+  }
+  const int H = (n[0] + 1) / 2;
+  const size_t cplx = fp64 ? 16 : 8;
+  const size_t plane = (size_t)n[2] * n[1] * H;
+  const int g2 = (n[1] * n[2] + p->kx->x_lines - 1) / p->kx->x_lines;
+  const int ntx3 = (H + p->ky->y_width - 1) / p->ky->y_width;
+  const int ntx4 = (H + p->kz->z_width - 1) / p->kz->z_width;
+  int rc = HM_OK;
+  if (!rc) rc = device_alloc(&p->spec, (size_t)n_load * 6 * plane * cplx, "spectrum");
+  if (!rc) rc = device_alloc(&p->hist, (size_t)n_load * 3 * plane * cplx, "traction history");
+  if (!rc) rc = device_alloc((void**)&p->taupart, (size_t)n_load * g2 * 6 * sizeof(double), "tau partials");
+  if (!rc) rc = device_alloc((void**)&p->errpart, (size_t)n_load * n[1] * ntx4 * sizeof(double), "error partials");
+  if (!rc) rc = device_alloc((void**)&p->state, (size_t)n_load * sizeof(SolverState), "state");
+  if (!rc) rc = device_alloc((void**)&p->prm, sizeof(SolveParams), "params");
+  if (!rc) rc = upload_twiddles(p, 0, n[0]);
+  if (!rc) rc = upload_twiddles(p, 1, n[1]);
+  if (!rc) rc = upload_twiddles(p, 2, n[2]);
+  if (!rc && hipHostMalloc((void**)&p->state_host, (size_t)n_load * sizeof(SolverState), 0) != hipSuccess)
+    rc = fail(HM_E_NOMEM, "pinned state buffer");
+  if (!rc && hipHostMalloc((void**)&p->prm_host, sizeof(SolveParams), 0) != hipSuccess)
+    rc = fail(HM_E_NOMEM, "pinned params buffer");
+  if (rc) {
+    free_plan(p);
+    return rc;
+  }
+  SolveArgs& a = p->args;
+  memset(&a, 0, sizeof a);
+  a.spec = p->spec;
+  a.hist = p->hist;
+  a.taupart = p->taupart;
+  a.errpart = p->errpart;
+  a.state = p->state;
+  a.prm = p->prm;
+  a.twx = p->tw[0];
+  a.twy = p->tw[1];
+  a.twz = p->tw[2];
+  a.nx = n[0];
+  a.ny = n[1];
+  a.nz = n[2];
+  a.H = H;
+  a.dim = dim;
+  a.n_load = n_load;
+  a.g2 = g2;
+  a.ntx3 = ntx3;
+  a.ntx4 = ntx4;
+  g_plans[key] = p;
+  *out = p;
+  return HM_OK;
+}
+
+int ensure_hist(Plan* p, int cap) {
+  if (p->hist_cap >= cap) return HM_OK;
+  if (p->errhist) (void)hipFree(p->errhist);
+  p->errhist = nullptr;
+  p->hist_cap = 0;
+  int rc = device_alloc((void**)&p->errhist, (size_t)p->n_load * cap * sizeof(double), "error history");
+  if (rc) return rc;
+  p->hist_cap = cap;
+  p->args.errhist = p->errhist;
+  p->args.hist_cap = cap;
+  if (p->graph) {
+    (void)hipGraphExecDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  return HM_OK;
+}
+
+int ensure_spheres(Plan* p, int ns) {
+  if (p->sph_cap >= ns && p->sph) return HM_OK;
+  if (p->sph) (void)hipFree(p->sph);
+  p->sph = nullptr;
+  const int cap = ns > 16 ? ns : 16;
+  int rc = device_alloc((void**)&p->sph, (size_t)cap * 4 * sizeof(double), "sphere table");
+  if (rc) return rc;
+  p->sph_cap = cap;
+  return HM_OK;
+}
+
+hipError_t launch_iteration(Plan* p, const SolveArgs& a, bool first, hipStream_t s) {
+  hipError_t e;
+  if ((e = (first ? p->kx->x_first : p->kx->x_iter)(a, s)) != hipSuccess) return e;
+  if ((e = p->ky->y_fwd(a, s)) != hipSuccess) return e;
+  if ((e = p->kz->z_gamma(a, s)) != hipSuccess) return e;
+  if ((e = p->ky->y_inv(a, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_finalize<256>), dim3(a.n_load), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+int poll_done(Plan* p, hipStream_t s, bool* all_done) {
+  HM_HIP(hipMemcpyAsync(p->state_host, p->state, (size_t)p->n_load * sizeof(SolverState), hipMemcpyDeviceToHost, s));
+  HM_HIP(hipStreamSynchronize(s));
+  bool d = true;
+  for (int l = 0; l < p->n_load; ++l) d = d && p->state_host[l].done;
+  *all_done = d;
+  return HM_OK;
+}
+
+int build_graph(Plan* p, int k) {
+  if (p->graph && p->graph_k == k) return HM_OK;
+  if (p->graph) {
+    (void)hipGraphExecDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  if (!p->cap_stream) HM_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  SolveArgs a = p->args;
+  a.first = 0;
+  hipGraph_t g = nullptr;
+  HM_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  for (int i = 0; i < k && le == hipSuccess; ++i) le = launch_iteration(p, a, false, p->cap_stream);
+  hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
+  if (le != hipSuccess || ce != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(HM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(le != hipSuccess ? le : ce));
+  }
+  hipError_t ie = hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    p->graph = nullptr;
+    return fail(HM_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ie));
+  }
+  p->graph_k = k;
+  return HM_OK;
+}
+
+// The solve shared by hm_solve and hm_effective_tensor.
+int solve_impl(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,
+               const int32_t* d_incl, const hm_sphere* spheres, int n_spheres, const double* E, int n_load,
+               const hm_solve_opts* opts, void* d_eps, double* sig_mean, hm_report* rep, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  int rc;
+  if ((rc = check_grid(grid))) return rc;
+  if ((rc = check_phases(phases))) return rc;
+  if ((rc = check_opts(opts))) return rc;
+  if ((rc = check_spheres(grid, spheres, n_spheres))) return rc;
+  if (rule < HM_RULE_NONE || rule > HM_RULE_LAMINATE) return fail(HM_E_ARG, "unknown rule %d", (int)rule);
+  if (!d_frac) return fail(HM_E_ARG, "d_frac is NULL");
+  if (rule == HM_RULE_LAMINATE && !d_incl) return fail(HM_E_ARG, "the 2-layer rule needs d_incl");
+  if (n_load < 1 || n_load > kMaxLoads) return fail(HM_E_ARG, "n_load must be in 1..%d", kMaxLoads);
+  if (!E || !sig_mean) return fail(HM_E_ARG, "E and sig_mean must not be NULL");
+  for (int i = 0; i < 6 * n_load; ++i)
+    if (!isfinite(E[i])) return fail(HM_E_ARG, "E has a non-finite entry");
+  const bool fp64 = opts->prec == HM_FP64;
+  Plan* p = nullptr;
+  if ((rc = get_plan(fp64, grid->n, grid->dim, n_load, &p))) return rc;
+  if ((rc = ensure_hist(p, opts->max_iter + 1))) return rc;
+  if ((rc = ensure_spheres(p, n_spheres))) return rc;
+
+  SolveParams& P = *p->prm_host;
+  memset(&P, 0, sizeof P);
+  P.pl[0] = phases[0].lambda;
+  P.pl[1] = phases[1].lambda;
+  P.pm[0] = phases[0].mu;
+  P.pm[1] = phases[1].mu;
+  const double lmin = fmin(phases[0].lambda, phases[1].lambda), lmax = fmax(phases[0].lambda, phases[1].lambda);
+  const double mmin = fmin(phases[0].mu, phases[1].mu), mmax = fmax(phases[0].mu, phases[1].mu);
+  P.rl = opts->c0_alpha * 0.5 * (lmin + lmax);
+  P.rm = opts->c0_alpha * 0.5 * (mmin + mmax);
+  if (!(P.rm > 0.0) || !(P.rl + 2.0 * P.rm > 0.0)) return fail(HM_E_ARG, "reference medium is not positive");
+  P.tol = opts->tol;
+  P.max_iter = opts->max_iter;
+  P.stall_window = opts->stall_window;
+  P.rule = (int)rule;
+  P.nsph = n_spheres;
+  P.frac = d_frac;
+  P.incl = d_incl;
+  P.sph = p->sph;
+  for (int i = 0; i < 6 * n_load; ++i) P.E[i] = E[i];
+
+  std::vector<double> sph(4 * (size_t)(n_spheres > 0 ? n_spheres : 1), 0.0);
+  for (int k = 0; k < n_spheres; ++k) {
+    for (int a = 0; a < 3; ++a) sph[4 * k + a] = spheres[k].c[a];
+    sph[4 * k + 3] = spheres[k].r;
+  }
+  if (n_spheres > 0)
+    HM_HIP(hipMemcpyAsync(p->sph, sph.data(), (size_t)n_spheres * 4 * sizeof(double), hipMemcpyHostToDevice, s));
+  HM_HIP(hipMemcpyAsync(p->prm, p->prm_host, sizeof(SolveParams), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL((k_reset_state<64>), dim3(1), dim3(64), 0, s, p->state, n_load);
+  HM_HIP(hipGetLastError());
+
+  SolveArgs a = p->args;
+  const int k = opts->check_every;
+  bool done = false;
+  a.first = 1;
+  HM_HIP(launch_iteration(p, a, true, s));
+  a.first = 0;
+  int it = 1;
+  if (opts->max_iter == 0 || k == 1) {
+    if ((rc = poll_done(p, s, &done))) return rc;
+  }
+  if (opts->use_graph && !done && opts->max_iter > 0) {
+    if ((rc = build_graph(p, k))) return rc;
+    while (!done && it <= opts->max_iter) {
+      HM_HIP(hipGraphLaunch(p->graph, s));
+      it += k;
+      if ((rc = poll_done(p, s, &done))) return rc;
+    }
+  } else {
+    while (!done && it <= opts->max_iter) {
+      HM_HIP(launch_iteration(p, a, false, s));
+      ++it;
+      if (it % k == 0 || it > opts->max_iter)
+        if ((rc = poll_done(p, s, &done))) return rc;
+    }
+  }
+  if (!done && (rc = poll_done(p, s, &done))) return rc;
+  if (d_eps) {
+    a.eps_out = d_eps;
+    HM_HIP(p->kx->x_export(a, s));
+  }
+  if ((rc = poll_done(p, s, &done))) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = HM_OK;
+  int flags = 0;
+  for (int l = 0; l < n_load; ++l) {
+    const SolverState& st = p->state_host[l];
+    for (int c = 0; c < 6; ++c) sig_mean[6 * l + c] = st.sig[c];
+    const int status = st.done ? st.status : HM_NOT_CONVERGED;
+    if (rep) {
+      rep[l].iters = st.iters;
+      rep[l].status = status;
+      rep[l].err = st.err;
+      rep[l].err0 = st.err0;
+      rep[l].seconds = secs;
+    }
+    if (status > worst) worst = status;
+    flags |= st.flags;
+  }
+  if (flags & FLAG_NONE_FRACTIONAL) return fail(HM_E_DATA, "fractional voxel with HM_RULE_NONE");
+  if (flags & FLAG_BAD_INCL) return fail(HM_E_DATA, "d_incl holds a sphere index >= n_spheres");
+  return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hm_last_error(void) { return g_last_error.c_str(); }
+
+int hm_device_ok(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  return strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+}
+
+void hm_release_plans(void) {
+  std::lock_guard<std::mutex> lock(g_mutex);
+  for (auto& kv : g_plans) free_plan(kv.second);
+  g_plans.clear();
+}
+
+int hm_filter(const hm_grid* grid, const hm_sphere* spheres, int n_spheres, double radius_vox, int subsamples,
+              hm_rule rule, hm_prec prec, uint32_t* d_count, void* d_frac, int32_t* d_incl, void* stream) {
+  int rc;
+  if ((rc = check_grid(grid))) return rc;
+  if ((rc = check_spheres(grid, spheres, n_spheres))) return rc;
+  if (rule < HM_RULE_NONE || rule > HM_RULE_LAMINATE) return fail(HM_E_ARG, "unknown rule %d", (int)rule);
+  if (prec != HM_FP64 && prec != HM_MIXED) return fail(HM_E_ARG, "unknown precision");
+  if (subsamples < 2 || subsamples > 32 || subsamples % 2) return fail(HM_E_ARG, "subsamples must be even, 2..32");
+  const bool point = rule == HM_RULE_NONE;
+  if (!point && !(radius_vox > 0.0 && radius_vox * subsamples <= 64.0))
+    return fail(HM_E_ARG, "radius_vox must be > 0 with radius_vox * subsamples <= 64");
+  if (!d_count || !d_frac) return fail(HM_E_ARG, "d_count and d_frac must not be NULL");
+  FilterArgs a;
+  memset(&a, 0, sizeof a);
+  a.nsph = n_spheres;
+  a.dim = grid->dim;
+  a.S = subsamples;
+  const double s2 = 2.0 * subsamples;
+  for (int d = 0; d < 3; ++d) {
+    a.n[d] = grid->n[d];
+    a.P[d] = 2LL * grid->n[d] * subsamples;
+  }
+  std::vector<LatSphere> tab((size_t)(n_spheres > 0 ? n_spheres : 1));
+  for (int k = 0; k < n_spheres; ++k) {
+    for (int d = 0; d < 3; ++d) {
+      const double c = spheres[k].c[d] * s2;
+      tab[k].c[d] = (long long)(c >= 0.0 ? floor(c + 0.5) : -floor(-c + 0.5));
+    }
+    tab[k].t = spheres[k].r * s2;
+    tab[k].R2 = tab[k].t * tab[k].t;
+  }
+  a.point = point ? 1 : 0;
+  if (point) {
+    a.M = 1;
+  } else {
+    a.rho = radius_vox * s2;
+    a.rho2 = a.rho * a.rho;
+    a.m = (int)floor(a.rho);
+    const int axes = grid->dim == 2 ? 2 : 3;
+    int M = 0;
+    for (int oz = (axes == 3 ? -a.m : 0); oz <= (axes == 3 ? a.m : 0); ++oz) {
+      if (axes == 3 && (oz & 1) == 0) continue;
+      for (int oy = -a.m; oy <= a.m; ++oy) {
+        if ((oy & 1) == 0) continue;
+        for (int ox = -a.m; ox <= a.m; ++ox) {
+          if ((ox & 1) == 0) continue;
+          const long long o2 = (long long)ox * ox + (long long)oy * oy + (long long)oz * oz;
+          if ((double)o2 <= a.rho2) ++M;
+        }
+      }
+    }
+    if (M < 1) return fail(HM_E_ARG, "filter radius keeps no refined point");
+    a.M = M;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  LatSphere* dtab = nullptr;
+  const size_t tb = tab.size() * sizeof(LatSphere);
+  if ((rc = device_alloc((void**)&dtab, tb, "sphere table"))) return rc;
+  hipError_t e = hipMemcpyAsync(dtab, tab.data(), tb, hipMemcpyHostToDevice, s);
+  a.sph = dtab;
+  a.count = d_count;
+  a.frac = d_frac;
+  a.incl = d_incl;
+  if (e == hipSuccess) e = launch_filter(a, prec == HM_FP64, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(dtab);
+  if (e != hipSuccess) return fail(HM_E_DEVICE, "filter: %s", hipGetErrorString(e));
+  return HM_OK;
+}
+
+int hm_solve(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac, const int32_t* d_incl,
+             const hm_sphere* spheres, int n_spheres, const double* E, int n_load, const hm_solve_opts* opts,
+             void* d_eps, double* sig_mean, hm_report* rep, void* stream) {
+  return solve_impl(grid, phases, rule, d_frac, d_incl, spheres, n_spheres, E, n_load, opts, d_eps, sig_mean, rep,
+                    (hipStream_t)stream);
+}
+
+int hm_effective_tensor(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,
+                        const int32_t* d_incl, const hm_sphere* spheres, int n_spheres, const hm_solve_opts* opts,
+                        double* C_mandel, void* d_eps, hm_report* rep, void* stream) {
+  int rc;
+  if ((rc = check_grid(grid))) return rc;
+  if (!C_mandel) return fail(HM_E_ARG, "C_mandel is NULL");
+  const double r2 = 1.0 / sqrt(2.0);
+  // unit Mandel strains as tensor components (11, 22, 33, 23, 13, 12)
+  static const int idx3[6] = {0, 1, 2, 3, 4, 5};
+  static const int idx2[3] = {0, 1, 5};
+  const int k = grid->dim == 2 ? 3 : 6;
+  const int* idx = grid->dim == 2 ? idx2 : idx3;
+  double E[36] = {0};
+  for (int J = 0; J < k; ++J) E[6 * J + idx[J]] = idx[J] < 3 ? 1.0 : r2;
+  double sig[36];
+  rc = solve_impl(grid, phases, rule, d_frac, d_incl, spheres, n_spheres, E, k, opts, d_eps, sig, rep,
+                  (hipStream_t)stream);
+  if (rc < 0) return rc;
+  const double w[6] = {1.0, 1.0, 1.0, sqrt(2.0), sqrt(2.0), sqrt(2.0)};
+  for (int I = 0; I < k; ++I)
+    for (int J = 0; J < k; ++J) C_mandel[I * k + J] = w[idx[I]] * sig[6 * J + idx[I]];
+  return rc;
+}
+
+int hm_solve_adjoint(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,
+                     const int32_t* d_incl, const hm_sphere* spheres, int n_spheres, hm_prec prec,
+                     const double* dLdC, const void* d_eps, int n_load, double* dLdphase, void* d_dLdfrac,
+                     void* stream) {
+  int rc;
+  if ((rc = check_grid(grid))) return rc;
+  if ((rc = check_phases(phases))) return rc;
+  if ((rc = check_spheres(grid, spheres, n_spheres))) return rc;
+  if (rule < HM_RULE_NONE || rule > HM_RULE_LAMINATE) return fail(HM_E_ARG, "unknown rule %d", (int)rule);
+  if (prec != HM_FP64 && prec != HM_MIXED) return fail(HM_E_ARG, "unknown precision");
+  const int k = grid->dim == 2 ? 3 : 6;
+  if (n_load != k) return fail(HM_E_ARG, "n_load must be %d (the unit Mandel strains)", k);
+  if (!d_frac || !d_eps || !dLdC || !dLdphase) return fail(HM_E_ARG, "NULL input or output");
+  if (rule == HM_RULE_LAMINATE && !d_incl) return fail(HM_E_ARG, "the 2-layer rule needs d_incl");
+  for (int i = 0; i < k * k; ++i)
+    if (!isfinite(dLdC[i])) return fail(HM_E_ARG, "dLdC has a non-finite entry");
+  hipStream_t s = (hipStream_t)stream;
+  const long long N = (long long)grid->n[0] * grid->n[1] * grid->n[2];
+  const int blocks = (int)((N + 255) / 256);
+  HillArgs a;
+  memset(&a, 0, sizeof a);
+  a.eps = d_eps;
+  a.frac = d_frac;
+  a.incl = d_incl;
+  a.nsph = n_spheres;
+  a.dim = grid->dim;
+  a.n_load = n_load;
+  a.rule = (int)rule;
+  for (int d = 0; d < 3; ++d) a.n[d] = grid->n[d];
+  for (int p = 0; p < 2; ++p) {
+    a.pl[p] = phases[p].lambda;
+    a.pm[p] = phases[p].mu;
+  }
+  for (int i = 0; i < k * k; ++i) a.G[i] = dLdC[i];
+  a.dfrac = d_dLdfrac;
+  double* dsph = nullptr;
+  double* dpart = nullptr;
+  std::vector<double> sph(4 * (size_t)(n_spheres > 0 ? n_spheres : 1), 0.0);
+  for (int q = 0; q < n_spheres; ++q) {
+    for (int c = 0; c < 3; ++c) sph[4 * q + c] = spheres[q].c[c];
+    sph[4 * q + 3] = spheres[q].r;
+  }
+  if ((rc = device_alloc((void**)&dsph, sph.size() * sizeof(double), "sphere table"))) return rc;
+  if ((rc = device_alloc((void**)&dpart, (size_t)blocks * 4 * sizeof(double), "gradient partials"))) {
+    (void)hipFree(dsph);
+    return rc;
+  }
+  std::vector<double> part((size_t)blocks * 4);
+  hipError_t e = hipMemcpyAsync(dsph, sph.data(), sph.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  a.sph = dsph;
+  a.part = dpart;
+  if (e == hipSuccess) e = launch_hill(a, prec == HM_FP64, blocks, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(part.data(), dpart, part.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(dsph);
+  (void)hipFree(dpart);
+  if (e != hipSuccess) return fail(HM_E_DEVICE, "adjoint: %s", hipGetErrorString(e));
+  for (int q = 0; q < 4; ++q) {
+    double sum = 0.0, comp = 0.0;
+    for (int b = 0; b < blocks; ++b) {
+      const double x = part[(size_t)b * 4 + q];
+      const double t = sum + x;
+      comp += fabs(sum) >= fabs(x) ? (sum - t) + x : (x - t) + sum;
+      sum = t;
+    }
+    dLdphase[q] = (sum + comp) / (double)N;
+  }
+  return HM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Shared types of the HIP library: complex vectors, solver state and the
+// argument blocks passed to the kernels.  Included by device and host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hm {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+template <typename T> using cx = typename Vec2<T>::type;
+
+template <typename C> __device__ __forceinline__ C c_add(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C c_sub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C c_conj(C a) { return C{a.x, -a.y}; }
+template <typename C> __device__ __forceinline__ C c_mul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename C, typename T> __device__ __forceinline__ C c_scale(C a, T s) { return C{a.x * s, a.y * s}; }
+
+// Stop codes written by the finalize kernel (mirror the public HM_* codes).
+enum : int { ST_RUNNING = -1, ST_CONVERGED = 0, ST_NOT_CONVERGED = 1, ST_STALLED = 2, ST_DIVERGED = 3 };
+// Bits of SolverState::flags.
+enum : int { FLAG_NONE_FRACTIONAL = 1, FLAG_BAD_INCL = 2 };
+
+constexpr double kDivergenceFactor = 1.0e3;
+constexpr double kStallDecrease = 0.99;
+
+// One per load case, in device memory.
+struct SolverState {
+  int iter;    // index of the next iterate to evaluate
+  int done;    // nonzero once the load case has stopped
+  int status;  // ST_*
+  int iters;   // reported iterate index
+  int flags;   // data problems seen by the kernels
+  int iref;    // iteration of the last 1% improvement
+  int pad0, pad1;
+  double err;   // error of the last evaluated (or reported) iterate
+  double err0;  // error of iterate 0
+  double ref;   // error at iref
+  double sig[6];  // <sigma> of the last evaluated (or reported) iterate
+};
+
+// Per-solve values read by the kernels through a device pointer, so that a
+// captured graph stays valid from one solve to the next.
+struct SolveParams {
+  double pl[2], pm[2];  // phase Lame parameters (0: matrix, 1: inclusion)
+  double rl, rm;        // reference medium
+  double tol;
+  int max_iter;
+  int stall_window;
+  int rule;
+  int nsph;
+  const void* frac;   // T[N]
+  const int* incl;    // int32[N] or null
+  const double* sph;  // [nsph][4]: centre x, y, z, radius (voxel units)
+  double E[6 * 8];    // macroscopic strains, tensor components, per load case
+};
+
+// Plan-stable launch arguments.
+struct SolveArgs {
+  void* spec;       // cx<T>[n_load][6][nz][ny][H]  x-spectrum / full spectrum
+  void* hist;       // cx<T>[n_load][3][nz][ny][H]  previous projected traction
+  double* taupart;  // [n_load][g2][6]  per-block sums of tau
+  double* errpart;  // [n_load][ny * ntx4]  per-block equilibrium sums
+  SolverState* state;   // [n_load]
+  double* errhist;      // [n_load][hist_cap]
+  const SolveParams* prm;
+  void* eps_out;        // export target T[n_load][6][N]
+  const void* twx;      // twiddles exp(-2 pi i k / n), per axis, cx<T>[n]
+  const void* twy;
+  const void* twz;
+  int nx, ny, nz, H, dim, n_load;
+  int g2, ntx3, ntx4;
+  int hist_cap;
+  int first;  // 1 on iterate 0 (uniform strain, empty traction history)
+};
+
+}  // namespace hm

@@ -1,0 +1,143 @@
+// Filter of material properties: sub-voxel phase fractions.
+//
+// Section 2: the filtered behaviour at a grid point uses the phase volume
+// fractions inside a uniform filter centred on it, which may be estimated by
+// averaging the phase indicators over a refined grid; the numerical setup
+// gives the filter radius in pixel units and the interface normal as the
+// direction from the inclusion centre to the grid point.
+//
+// Integer lattice: u = (voxel size) / (2 S).  Voxel a has its centre at
+// (2a + 1) S; refined points sit at odd coordinates (spacing 2u); the filter
+// keeps offsets o (odd per axis) with |o|^2 <= (2 r S)^2.  A refined point is
+// inside the inclusion set when, for some sphere, its periodic minimum-image
+// squared distance to the rounded centre is <= R^2, so every count is an
+// exact integer.  One thread per voxel: spheres that cannot reach the filter
+// ball are skipped and a sphere that contains the whole ball gives the full
+// count without enumeration (both decisions are conservative by one lattice
+// unit); remaining voxels enumerate the stencil against the candidates.
+#include <math.h>
+#include <stdint.h>
+
+#include "hm_common.hpp"
+#include "hm_filter.hpp"
+
+namespace hm {
+
+__device__ __forceinline__ long long min_image(long long d, long long P) {
+  const long long h = P / 2;
+  while (d >= h) d -= P;
+  while (d < -h) d += P;
+  return d;
+}
+
+constexpr int kMaxCand = 8;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_filter(FilterArgs a) {
+  const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const int x = (int)(v % a.n[0]);
+  const int y = (int)((v / a.n[0]) % a.n[1]);
+  const int z = (int)(v / ((long long)a.n[0] * a.n[1]));
+  const int axes = a.dim == 2 ? 2 : 3;
+  const long long X[3] = {(2LL * x + 1) * a.S, (2LL * y + 1) * a.S, (2LL * z + 1) * a.S};
+
+  uint32_t cnt = 0;
+  if (a.point) {
+    for (int k = 0; k < a.nsph; ++k) {
+      long long d2 = 0;
+      for (int ax = 0; ax < axes; ++ax) {
+        const long long d = min_image(X[ax] - a.sph[k].c[ax], a.P[ax]);
+        d2 += d * d;
+      }
+      if ((double)d2 <= a.sph[k].R2) {
+        cnt = 1;
+        break;
+      }
+    }
+  } else {
+    int cand[kMaxCand];
+    int nc = 0;
+    bool overflow = false, full = false;
+    for (int k = 0; k < a.nsph && !full; ++k) {
+      long long d2 = 0;
+      for (int ax = 0; ax < axes; ++ax) {
+        const long long d = min_image(X[ax] - a.sph[k].c[ax], a.P[ax]);
+        d2 += d * d;
+      }
+      const double D = sqrt((double)d2);
+      if (D + a.rho <= a.sph[k].t - 1.0) {
+        full = true;
+      } else if (D - a.rho <= a.sph[k].t + 1.0) {
+        if (nc < kMaxCand)
+          cand[nc++] = k;
+        else
+          overflow = true;
+      }
+    }
+    if (full) {
+      cnt = (uint32_t)a.M;
+    } else if (nc > 0) {
+      const int zlo = axes == 3 ? -a.m : 0;
+      const int zhi = axes == 3 ? a.m : 0;
+      for (int oz = zlo; oz <= zhi; ++oz) {
+        if (axes == 3 && (oz & 1) == 0) continue;
+        for (int oy = -a.m; oy <= a.m; ++oy) {
+          if ((oy & 1) == 0) continue;
+          for (int ox = -a.m; ox <= a.m; ++ox) {
+            if ((ox & 1) == 0) continue;
+            const long long o2 = (long long)ox * ox + (long long)oy * oy + (long long)oz * oz;
+            if ((double)o2 > a.rho2) continue;
+            const long long p[3] = {X[0] + ox, X[1] + oy, X[2] + oz};
+            bool in = false;
+            const int nk = overflow ? a.nsph : nc;
+            for (int q = 0; q < nk && !in; ++q) {
+              const int k = overflow ? q : cand[q];
+              long long d2 = 0;
+              for (int ax = 0; ax < axes; ++ax) {
+                const long long d = min_image(p[ax] - a.sph[k].c[ax], a.P[ax]);
+                d2 += d * d;
+              }
+              in = (double)d2 <= a.sph[k].R2;
+            }
+            cnt += in ? 1u : 0u;
+          }
+        }
+      }
+    }
+  }
+  a.count[v] = cnt;
+  static_cast<T*>(a.frac)[v] = (T)cnt / (T)a.M;
+  if (a.incl) {
+    int best = -1;
+    if (cnt > 0 && cnt < (uint32_t)a.M) {
+      double bd = INFINITY;
+      for (int k = 0; k < a.nsph; ++k) {
+        long long d2 = 0;
+        for (int ax = 0; ax < axes; ++ax) {
+          const long long d = min_image(X[ax] - a.sph[k].c[ax], a.P[ax]);
+          d2 += d * d;
+        }
+        const double dist = fabs(sqrt((double)d2) - a.sph[k].t);
+        if (dist < bd) {
+          bd = dist;
+          best = k;
+        }
+      }
+    }
+    a.incl[v] = best;
+  }
+}
+
+hipError_t launch_filter(const FilterArgs& a, bool fp64, hipStream_t s) {
+  const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
+  const dim3 grid((unsigned)((N + 255) / 256));
+  if (fp64)
+    hipLaunchKernelGGL((k_filter<double>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_filter<float>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace hm

@@ -1,0 +1,511 @@
+// Kernels of one fixed-point iteration of the Lippmann-Schwinger solve
+// (Section 2, eqs. 1-a, 1-b, 2) on an odd grid.
+//
+// Storage between iterations: the x-spectrum of the strain, i.e. for every
+// (load, component, z, y) the half line kx = 0..(nx-1)/2 of the DFT along x
+// (the other half follows by Hermitian symmetry of real data).  One
+// iteration is four sweeps over that array plus a tiny finalize kernel:
+//   xsweep  inverse x-DFT -> strain at the grid points -> polarization
+//           tau = (c~ - c0) : eps -> forward x-DFT; per-block sums of tau
+//   ysweep  forward y-DFT of every (component, z, kx) line
+//   zsweep  forward z-DFT, eps^ = -Gamma0^ : tau^ (eps^(0) = E), the
+//           equilibrium-error partial sums, inverse z-DFT
+//   ysweep  inverse y-DFT
+//   finalize  error, mean stress, stop decision (one block per load case)
+// The six real strain components are transformed as three complex lines
+// (11 + i 22, 33 + i 23, 13 + i 12), which is exact for real data of any
+// (odd) length.  The 1/N of the inverse transform is applied in zsweep.
+//
+// Equilibrium error: for xi != 0 and i >= 1, xi . sigma^_i =
+// xi . (tau^_i - tau^_(i-1)) because xi . (c0 : Gamma0^ : t) = xi . t, and
+// xi . sigma^_0 = xi . tau^_0 for the uniform first iterate.  zsweep keeps
+// a_i = tau^_i . n (n = xi / |xi|) from the previous iteration and
+// accumulates sum_xi w |xi|^2 |a_i - a_(i-1)|^2 over the half spectrum
+// (w = 1 at kx = 0, 2 elsewhere).
+#pragma once
+
+#include "hm_common.hpp"
+#include "hm_fft.hpp"
+#include "hm_material.hpp"
+
+namespace hm {
+
+enum : int { MODE_FIRST = 0, MODE_ITER = 1, MODE_EXPORT = 2 };
+
+// Deterministic block sum (fixed shuffle tree, then waves in order); the
+// result is valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+// Polarization at one voxel: tau = (c~ - c0) : e.
+template <typename T>
+__device__ __forceinline__ void voxel_tau(const SolveArgs& a, const SolveParams& P, SolverState* st, size_t v,
+                                          int x, int y, int z, const T e[6], T tau[6]) {
+  const T f = static_cast<const T*>(P.frac)[v];
+  Coef<T> c;
+  c.aniso = false;
+  c.a3 = c.a4 = c.a5 = T(0);
+  if (f == T(0)) {
+    c.a1 = T(P.pl[0]);
+    c.a2 = T(2.0 * P.pm[0]);
+  } else if (f == T(1)) {
+    c.a1 = T(P.pl[1]);
+    c.a2 = T(2.0 * P.pm[1]);
+  } else {
+    const T pl[2] = {T(P.pl[0]), T(P.pl[1])};
+    const T pm[2] = {T(P.pm[0]), T(P.pm[1])};
+    int rule = P.rule;
+    if (rule == RULE_NONE) {
+      atomicOr(&st->flags, FLAG_NONE_FRACTIONAL);
+      rule = RULE_VOIGT;
+    }
+    rule_coefficients<T>(rule, f, pl, pm, c);
+    if (c.aniso) {
+      const int k = P.incl ? P.incl[v] : -1;
+      if (k >= P.nsph) atomicOr(&st->flags, FLAG_BAD_INCL);
+      if (k >= 0 && k < P.nsph) {
+        interface_normal<T>(P.sph, k, x, y, z, a.nx, a.ny, a.nz, a.dim, c.n);
+      } else {
+        c.n[0] = T(1);
+        c.n[1] = T(0);
+        c.n[2] = T(0);
+      }
+    }
+  }
+  c.a1 -= T(P.rl);
+  c.a2 -= T(2.0 * P.rm);
+  apply_form<T>(c, e, tau);
+}
+
+// ---------------------------------------------------------------- xsweep --
+template <typename T, int NX, int L, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
+  constexpr int LL = 3 * L;
+  constexpr int H = (NX + 1) / 2;
+  __shared__ cx<T> buf[NX * LL];
+  __shared__ cx<T> s_tw[NX];
+  __shared__ double red[NT / 64];
+  const int tid = threadIdx.x;
+  const int load = blockIdx.y;
+  SolverState* st = a.state + load;
+  if (MODE != MODE_EXPORT && st->done) return;
+  const SolveParams& P = *a.prm;
+  const int nlines = a.ny * a.nz;
+  const int line0 = blockIdx.x * L;
+  const size_t cs = (size_t)nlines * H;
+  cx<T>* spec = static_cast<cx<T>*>(a.spec) + (size_t)load * 6 * cs;
+  load_twiddles<T, NX, NT>(s_tw, static_cast<const cx<T>*>(a.twx), tid);
+
+  if (MODE != MODE_FIRST) {
+    for (int idx = tid; idx < 3 * L * H; idx += NT) {
+      const int p = idx / (L * H);
+      const int rem = idx - p * (L * H);
+      const int l = rem / H;
+      const int k = rem - l * H;
+      const int line = line0 + l;
+      cx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
+      if (line < nlines) {
+        A = spec[(size_t)(2 * p) * cs + (size_t)line * H + k];
+        B = spec[(size_t)(2 * p + 1) * cs + (size_t)line * H + k];
+      }
+      buf[k * LL + p * L + l] = cx<T>{A.x - B.y, A.y + B.x};
+      if (k > 0) buf[(NX - k) * LL + p * L + l] = cx<T>{A.x + B.y, B.x - A.y};
+    }
+    __syncthreads();
+    fft_lines<T, NX, LL, NT, +1>(buf, s_tw, tid);
+  }
+
+  if (MODE == MODE_EXPORT) {
+    const size_t N = (size_t)nlines * NX;
+    T* out = static_cast<T*>(a.eps_out) + (size_t)load * 6 * N;
+    for (int idx = tid; idx < L * NX; idx += NT) {
+      const int l = idx / NX, x = idx - l * NX, line = line0 + l;
+      if (line < nlines) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          const cx<T> Z = buf[x * LL + p * L + l];
+          out[(size_t)(2 * p) * N + (size_t)line * NX + x] = Z.x;
+          out[(size_t)(2 * p + 1) * N + (size_t)line * NX + x] = Z.y;
+        }
+      }
+    }
+    return;
+  }
+
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int idx = tid; idx < L * NX; idx += NT) {
+    const int l = idx / NX, x = idx - l * NX, line = line0 + l;
+    T e[6];
+    if (MODE == MODE_FIRST) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) e[c] = T(P.E[load * 6 + c]);
+    } else {
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const cx<T> Z = buf[x * LL + p * L + l];
+        e[2 * p] = Z.x;
+        e[2 * p + 1] = Z.y;
+      }
+    }
+    T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    if (line < nlines) {
+      const int y = line % a.ny, z = line / a.ny;
+      voxel_tau<T>(a, P, st, (size_t)line * NX + x, x, y, z, e, tau);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[c] += (double)tau[c];
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p) buf[x * LL + p * L + l] = cx<T>{tau[2 * p], tau[2 * p + 1]};
+  }
+  __syncthreads();
+  fft_lines<T, NX, LL, NT, -1>(buf, s_tw, tid);
+
+  for (int idx = tid; idx < 3 * L * H; idx += NT) {
+    const int p = idx / (L * H);
+    const int rem = idx - p * (L * H);
+    const int l = rem / H;
+    const int k = rem - l * H;
+    const int line = line0 + l;
+    if (line < nlines) {
+      const cx<T> Z = buf[k * LL + p * L + l];
+      const cx<T> Zc = c_conj(buf[((NX - k) % NX) * LL + p * L + l]);
+      const cx<T> A = {T(0.5) * (Z.x + Zc.x), T(0.5) * (Z.y + Zc.y)};
+      const cx<T> B = {T(0.5) * (Z.y - Zc.y), T(-0.5) * (Z.x - Zc.x)};
+      spec[(size_t)(2 * p) * cs + (size_t)line * H + k] = A;
+      spec[(size_t)(2 * p + 1) * cs + (size_t)line * H + k] = B;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const double s = block_sum<NT>(acc[c], red);
+    if (tid == 0) a.taupart[((size_t)load * a.g2 + blockIdx.x) * 6 + c] = s;
+  }
+}
+
+// ---------------------------------------------------------------- ysweep --
+template <typename T, int NY, int W, int NT, int SIGN>
+__global__ __launch_bounds__(NT) void k_ysweep(SolveArgs a) {
+  __shared__ cx<T> buf[NY * W];
+  __shared__ cx<T> s_tw[NY];
+  const int tid = threadIdx.x;
+  const int z = blockIdx.y;
+  const int load = blockIdx.z / 6, comp = blockIdx.z - 6 * (blockIdx.z / 6);
+  if (a.state[load].done) return;
+  const int H = a.H;
+  const int kx0 = blockIdx.x * W;
+  cx<T>* base = static_cast<cx<T>*>(a.spec) + ((size_t)(load * 6 + comp) * a.nz + z) * (size_t)NY * H + kx0;
+  load_twiddles<T, NY, NT>(s_tw, static_cast<const cx<T>*>(a.twy), tid);
+  for (int idx = tid; idx < NY * W; idx += NT) {
+    const int j = idx / W, w = idx - j * W;
+    buf[idx] = (kx0 + w < H) ? base[(size_t)j * H + w] : cx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  fft_lines<T, NY, W, NT, SIGN>(buf, s_tw, tid);
+  for (int idx = tid; idx < NY * W; idx += NT) {
+    const int j = idx / W, w = idx - j * W;
+    if (kx0 + w < H) base[(size_t)j * H + w] = buf[idx];
+  }
+}
+
+// ---------------------------------------------------------------- zsweep --
+template <typename T, int NZ, int W, int NT>
+__global__ __launch_bounds__(NT) void k_zsweep(SolveArgs a) {
+  constexpr int SL = W * NZ;
+  constexpr int Q = (SL + NT - 1) / NT;
+  __shared__ cx<T> buf[SL];
+  __shared__ cx<T> s_tw[NZ];
+  __shared__ double red[NT / 64];
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x, ky = blockIdx.y, load = blockIdx.z;
+  if (a.state[load].done) return;
+  const SolveParams& P = *a.prm;
+  const int H = a.H, ny = a.ny;
+  const int kx0 = tile * W;
+  const size_t zs = (size_t)ny * H;
+  const size_t plane = (size_t)NZ * zs;
+  cx<T>* sp = static_cast<cx<T>*>(a.spec) + (size_t)load * 6 * plane + (size_t)ky * H + kx0;
+  cx<T>* hp = static_cast<cx<T>*>(a.hist) + (size_t)load * 3 * plane + (size_t)ky * H + kx0;
+  load_twiddles<T, NZ, NT>(s_tw, static_cast<const cx<T>*>(a.twz), tid);
+
+  cx<T> r[6][Q];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    for (int idx = tid; idx < SL; idx += NT) {
+      const int kz = idx / W, w = idx - kz * W;
+      buf[idx] = (kx0 + w < H) ? sp[(size_t)c * plane + (size_t)kz * zs + w] : cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    fft_lines<T, NZ, W, NT, -1>(buf, s_tw, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int s = tid + q * NT;
+      if (s < SL) r[c][q] = buf[s];
+    }
+    __syncthreads();
+  }
+
+  const double rl = P.rl, rm = P.rm;
+  const T inv2mu = T(1.0 / (2.0 * rm));
+  const T cc = T((rl + rm) / (rm * (rl + 2.0 * rm)));
+  const T invN = T(1.0 / ((double)a.nx * (double)ny * (double)NZ));
+  const int ay = ky <= (ny - 1) / 2 ? ky : ky - ny;
+  const double twopi = 6.283185307179586476925286766559;
+  double S = 0.0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int s = tid + q * NT;
+    if (s >= SL) continue;
+    const int kz = s / W, w = s - kz * W;
+    const int kx = kx0 + w;
+    if (kx >= H) continue;
+    const int az = kz <= (NZ - 1) / 2 ? kz : kz - NZ;
+    const size_t ho = (size_t)kz * zs + w;
+    if (kx == 0 && ay == 0 && az == 0) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) r[c][q] = cx<T>{T(P.E[load * 6 + c]), T(0)};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) hp[(size_t)c * plane + ho] = cx<T>{T(0), T(0)};
+      continue;
+    }
+    const double x0 = twopi * kx, x1 = twopi * ay, x2 = twopi * az;
+    const double q2 = x0 * x0 + x1 * x1 + x2 * x2;
+    const double rinv = 1.0 / sqrt(q2);
+    const T n0 = T(x0 * rinv), n1 = T(x1 * rinv), n2 = T(x2 * rinv);
+    const cx<T> t11 = r[0][q], t22 = r[1][q], t33 = r[2][q], t23 = r[3][q], t13 = r[4][q], t12 = r[5][q];
+    // a = tau^ . n
+    const cx<T> a0 = {t11.x * n0 + t12.x * n1 + t13.x * n2, t11.y * n0 + t12.y * n1 + t13.y * n2};
+    const cx<T> a1 = {t12.x * n0 + t22.x * n1 + t23.x * n2, t12.y * n0 + t22.y * n1 + t23.y * n2};
+    const cx<T> a2 = {t13.x * n0 + t23.x * n1 + t33.x * n2, t13.y * n0 + t23.y * n1 + t33.y * n2};
+    const cx<T> na = {a0.x * n0 + a1.x * n1 + a2.x * n2, a0.y * n0 + a1.y * n1 + a2.y * n2};
+    // equilibrium error partial
+    {
+      cx<T> p0 = {T(0), T(0)}, p1 = {T(0), T(0)}, p2 = {T(0), T(0)};
+      if (!a.first) {
+        p0 = hp[ho];
+        p1 = hp[plane + ho];
+        p2 = hp[2 * plane + ho];
+      }
+      const double d0x = (double)a0.x - (double)p0.x, d0y = (double)a0.y - (double)p0.y;
+      const double d1x = (double)a1.x - (double)p1.x, d1y = (double)a1.y - (double)p1.y;
+      const double d2x = (double)a2.x - (double)p2.x, d2y = (double)a2.y - (double)p2.y;
+      const double wk = kx == 0 ? 1.0 : 2.0;
+      S += wk * q2 * (d0x * d0x + d0y * d0y + d1x * d1x + d1y * d1y + d2x * d2x + d2y * d2y);
+      hp[ho] = a0;
+      hp[plane + ho] = a1;
+      hp[2 * plane + ho] = a2;
+    }
+    // eps^_kh = -[(n_k a_h + n_h a_k) / (2 mu0) - cc (n.a) n_k n_h] / N
+    const T m = -invN;
+    auto comp = [&](T nk, T nh, cx<T> ak, cx<T> ah) -> cx<T> {
+      const T g = cc * nk * nh;
+      return cx<T>{m * ((nk * ah.x + nh * ak.x) * inv2mu - g * na.x),
+                   m * ((nk * ah.y + nh * ak.y) * inv2mu - g * na.y)};
+    };
+    r[0][q] = comp(n0, n0, a0, a0);
+    r[1][q] = comp(n1, n1, a1, a1);
+    r[2][q] = comp(n2, n2, a2, a2);
+    r[3][q] = comp(n1, n2, a1, a2);
+    r[4][q] = comp(n0, n2, a0, a2);
+    r[5][q] = comp(n0, n1, a0, a1);
+  }
+
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int s = tid + q * NT;
+      if (s < SL) buf[s] = r[c][q];
+    }
+    __syncthreads();
+    fft_lines<T, NZ, W, NT, +1>(buf, s_tw, tid);
+    for (int idx = tid; idx < SL; idx += NT) {
+      const int kz = idx / W, w = idx - kz * W;
+      if (kx0 + w < H) sp[(size_t)c * plane + (size_t)kz * zs + w] = buf[idx];
+    }
+    __syncthreads();
+  }
+  const double tot = block_sum<NT>(S, red);
+  if (tid == 0) a.errpart[(size_t)load * ((size_t)ny * a.ntx4) + (size_t)ky * a.ntx4 + tile] = tot;
+}
+
+// -------------------------------------------------------------- finalize --
+__device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
+  const double t = s + x;
+  if (fabs(s) >= fabs(x))
+    c += (s - t) + x;
+  else
+    c += (x - t) + s;
+  s = t;
+}
+
+// Compensated, deterministic sum of v[i * stride] for i < n over the block.
+template <int NT>
+__device__ double block_compensated_sum(const double* v, size_t n, size_t stride, double* ss, double* sc) {
+  const int tid = threadIdx.x;
+  double s = 0.0, c = 0.0;
+  for (size_t i = tid; i < n; i += NT) neumaier_add(s, c, v[i * stride]);
+  ss[tid] = s;
+  sc[tid] = c;
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      double s1 = ss[tid], c1 = sc[tid];
+      neumaier_add(s1, c1, ss[tid + h]);
+      ss[tid] = s1;
+      sc[tid] = c1 + sc[tid + h];
+    }
+    __syncthreads();
+  }
+  const double out = ss[0] + sc[0];
+  __syncthreads();
+  return out;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_finalize(SolveArgs a) {
+  __shared__ double ss[NT], sc[NT];
+  const int load = blockIdx.x;
+  SolverState* st = a.state + load;
+  if (st->done) return;
+  const SolveParams& P = *a.prm;
+  double tsum[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+    tsum[c] = block_compensated_sum<NT>(a.taupart + (size_t)load * a.g2 * 6 + c, (size_t)a.g2, 6, ss, sc);
+  const size_t ne = (size_t)a.ny * a.ntx4;
+  const double S = block_compensated_sum<NT>(a.errpart + (size_t)load * ne, ne, 1, ss, sc);
+  if (threadIdx.x != 0) return;
+  const double N = (double)a.nx * (double)a.ny * (double)a.nz;
+  const double* E = P.E + 6 * load;
+  const double trE = E[0] + E[1] + E[2];
+  double sig[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) sig[c] = tsum[c] / N + (c < 3 ? P.rl * trE : 0.0) + 2.0 * P.rm * E[c];
+  const double fro = sqrt(sig[0] * sig[0] + sig[1] * sig[1] + sig[2] * sig[2] +
+                          2.0 * (sig[3] * sig[3] + sig[4] * sig[4] + sig[5] * sig[5]));
+  const double den = N * fro;
+  const double e = den > 0.0 ? sqrt(S) / den : (S == 0.0 ? 0.0 : INFINITY);
+  const int i = st->iter;
+  if (i < a.hist_cap) a.errhist[(size_t)load * a.hist_cap + i] = e;
+  if (i == 0) st->err0 = e;
+  int status = ST_RUNNING;
+  if (e < P.tol) {
+    status = ST_CONVERGED;
+  } else if (!isfinite(e) || (st->err0 > 0.0 && e > kDivergenceFactor * st->err0)) {
+    status = ST_DIVERGED;
+  } else {
+    if (i == 0 || e < kStallDecrease * st->ref) {
+      st->ref = e;
+      st->iref = i;
+    }
+    if (P.stall_window > 0 && i - st->iref >= P.stall_window)
+      status = ST_STALLED;
+    else if (i >= P.max_iter)
+      status = ST_NOT_CONVERGED;
+  }
+  st->err = e;
+  st->iters = i;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) st->sig[c] = sig[c];
+  if (status != ST_RUNNING) {
+    st->status = status;
+    st->done = 1;
+  }
+  st->iter = i + 1;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_reset_state(SolverState* st, int n_load) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n_load) return;
+  SolverState z;
+  z.iter = 0;
+  z.done = 0;
+  z.status = ST_RUNNING;
+  z.iters = 0;
+  z.flags = 0;
+  z.iref = 0;
+  z.pad0 = z.pad1 = 0;
+  z.err = z.err0 = z.ref = 0.0;
+  for (int c = 0; c < 6; ++c) z.sig[c] = 0.0;
+  st[l] = z;
+}
+
+// ------------------------------------------------------------ registry --
+using solve_launch_fn = hipError_t (*)(const SolveArgs&, hipStream_t);
+
+struct AxisKernels {
+  int n;
+  solve_launch_fn x_first, x_iter, x_export;
+  solve_launch_fn y_fwd, y_inv;
+  solve_launch_fn z_gamma;
+  int x_lines;  // lines per xsweep block
+  int y_width;  // kx tile of ysweep
+  int z_width;  // kx tile of zsweep
+};
+
+// Tile choices (per precision and line length).
+template <typename T, int N> struct Tiles {
+  static constexpr int xl0 = 1000 / (N > 0 ? N : 1);
+  static constexpr int XL = xl0 < 1 ? 1 : (xl0 > 8 ? 8 : xl0);
+  static constexpr int XNT = 256;
+  static constexpr int YW = sizeof(T) == 8 ? 8 : 16;
+  static constexpr int YNT = 256;
+  static constexpr int ZW = sizeof(T) == 8 ? 8 : 16;
+  static constexpr int ZNT = (ZW * N > 1024) ? 512 : 256;
+};
+
+template <typename T, int NX, int MODE>
+hipError_t launch_x(const SolveArgs& a, hipStream_t s) {
+  using TL = Tiles<T, NX>;
+  hipLaunchKernelGGL((k_xsweep<T, NX, TL::XL, TL::XNT, MODE>), dim3(a.g2, a.n_load), dim3(TL::XNT), 0, s, a);
+  return hipGetLastError();
+}
+template <typename T, int NY, int SIGN>
+hipError_t launch_y(const SolveArgs& a, hipStream_t s) {
+  using TL = Tiles<T, NY>;
+  hipLaunchKernelGGL((k_ysweep<T, NY, TL::YW, TL::YNT, SIGN>), dim3(a.ntx3, a.nz, 6 * a.n_load), dim3(TL::YNT), 0,
+                     s, a);
+  return hipGetLastError();
+}
+template <typename T, int NZ>
+hipError_t launch_z(const SolveArgs& a, hipStream_t s) {
+  using TL = Tiles<T, NZ>;
+  hipLaunchKernelGGL((k_zsweep<T, NZ, TL::ZW, TL::ZNT>), dim3(a.ntx4, a.ny, a.n_load), dim3(TL::ZNT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+AxisKernels make_axis_kernels() {
+  using TL = Tiles<T, N>;
+  AxisKernels k;
+  k.n = N;
+  k.x_first = &launch_x<T, N, MODE_FIRST>;
+  k.x_iter = &launch_x<T, N, MODE_ITER>;
+  k.x_export = &launch_x<T, N, MODE_EXPORT>;
+  k.y_fwd = &launch_y<T, N, -1>;
+  k.y_inv = &launch_y<T, N, +1>;
+  k.z_gamma = &launch_z<T, N>;
+  k.x_lines = TL::XL;
+  k.y_width = TL::YW;
+  k.z_width = TL::ZW;
+  return k;
+}
+
+// Lookup across the size groups compiled in separate translation units.
+const AxisKernels* axis_kernels(bool fp64, int n);
+
+}  // namespace hm
