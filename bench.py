@@ -1,0 +1,254 @@
+"""Benchmark of the filtered-property Lippmann-Schwinger solve on one MI355X.
+
+Workload: 125^3 periodic cell, one centred sphere of volume fraction 0.25,
+isotropic phases (nu = 0.3) at contrasts E_incl/E_mat = 100 and 0.01,
+2-layer filter of radius 1 voxel with 8^3 sub-samples per voxel, the six
+unit Mandel strains solved together, stress-equilibrium tolerance 1e-4.
+
+One step = for each path (FP64, mixed) and each contrast: filter -> batched
+six-load fixed-point solve to tolerance -> effective tensor -> gradient of
+||C_eff - C_target||^2 by the adjoint identity.  The reported value is the
+mixed path's voxel-iterations per second over the timed steps (one
+voxel-iteration = one grid point x one evaluated iterate x one load case);
+the FP64 path's figure and the ratio are reported beside it, with each
+path's effective-tensor error against a tightly converged FP64 solve.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+       python bench.py --kernel-pass   (a few profiled iterations, for rocprofv3)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "voxel-iterations/s of LS fixed point, mixed vs FP64 at equal C_eff error; %HBM peak"
+CONTRASTS = (100.0, 0.01)
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def kernel_bytes(n, prec, kernel):
+    """Algorithmic HBM bytes of one launch of `kernel` for ONE load case.
+
+    The stored state is the x-half-spectrum: 6 components x nz x ny x H
+    complex values (H = (nx + 1) / 2).  xsweep reads and writes it and reads
+    the material (fraction + normal-sphere id); each ysweep reads and writes
+    it; zsweep also reads and writes the 3-component traction history.
+    """
+    nx, ny, nz = n
+    H = (nx + 1) // 2
+    cb = 16 if prec == "fp64" else 8
+    plane = nz * ny * H
+    spec = 2 * 6 * plane * cb
+    if kernel == "xsweep":
+        return spec + nx * ny * nz * ((8 if prec == "fp64" else 4) + 4)
+    if kernel in ("ysweep_fwd", "ysweep_inv"):
+        return spec
+    if kernel == "zsweep":
+        return spec + 2 * 3 * plane * cb
+    return 0
+
+
+def run_path(hm, w, prec, contrast, dev, profile=True, C_target=None, max_iter=5000):
+    """filter -> six-load solve -> C_eff -> adjoint gradient.  Returns a dict."""
+    import torch
+    t0 = time.perf_counter()
+    cnt, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, prec, dev)
+    out = hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, prec=prec, tol=w.tol,
+                                 max_iter=max_iter, check_every=16, stall_window=(20 if prec == "mixed" else 0),
+                                 want_eps=True, profile=profile)
+    timing = hm.last_timing() if profile else None
+    C = out["C"]
+    Ct = C if C_target is None else C_target
+    G = 2.0 * (C - Ct)
+    dph, dfr = hm.hm_solve_adjoint(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, G, out["eps"], prec=prec)
+    _sync()
+    dt = time.perf_counter() - t0
+    N = w.nvox
+    vit = sum((r["iters"] + 1) for r in out["reports"]) * N
+    del out["eps"], frac, incl, cnt, dfr
+    return {"seconds": dt, "voxel_iterations": vit, "C": C, "reports": out["reports"], "timing": timing,
+            "dLdphase": dph}
+
+
+def roofline(timings, n, prec, reports):
+    """Dominant kernel of the profiled solves, its algorithmic bandwidth vs peak."""
+    tot = {}
+    for t in timings:
+        for k, ms in t["ms"].items():
+            tot[k] = tot.get(k, 0.0) + ms * t["iterations"]
+    dom = max(tot, key=tot.get)
+    # average number of active load cases per launch over the profiled iterations
+    its = sum(t["iterations"] for t in timings)
+    active = sum(sum(r["iters"] + 1 for r in rep) for rep in reports) / max(1, its)
+    ms = tot[dom] / its
+    bytes_launch = kernel_bytes(n, prec, dom) * active
+    achieved = bytes_launch / (ms * 1e-3) / 1e9
+    return {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "ms_per_launch": ms,
+            "algorithmic_bytes_per_launch": bytes_launch, "active_loads_per_launch": active,
+            "ms_per_kernel": {k: v / its for k, v in tot.items()}}
+
+
+def cpu_baseline(iters=1):
+    """The oracle timed on this host's cores on a bounded sample of the workload."""
+    from oracle import filter as ofilter, solver as osolver
+    from workloads import workload_c2
+    w = workload_c2(CONTRASTS[0])
+    vox = ofilter.all_voxels(w.n)
+    d = np.linalg.norm(vox + 0.5 - w.spheres[0, :3], axis=1)
+    R = w.spheres[0, 3]
+    # the oracle's counts on the interface band; voxels farther than the
+    # filter radius plus a margin from the surface are pure
+    band = np.abs(d - R) <= w.radius_vox + 2.0
+    frac = (d < R).astype(np.float64)
+    cnt, M = ofilter.counts_at(w.n, 3, w.spheres, w.radius_vox, w.subsamples, vox[band])
+    frac[band] = cnt / M
+    incl = np.where((frac > 0) & (frac < 1), 0, -1)
+    fld = osolver.build_field(w, frac, incl)
+    c0 = osolver.reference_medium(w.phases)
+    w0, c0t = time.perf_counter(), time.process_time()
+    r = osolver.solve(fld, w.loads[0], c0, 0.0, iters)
+    wall = time.perf_counter() - w0
+    cpu = time.process_time() - c0t
+    evals = r["iters"] + 1
+    return {"value": evals * w.nvox / wall, "unit": "voxel-iterations/s", "cores": max(1, int(round(cpu / wall))),
+            "kind": "oracle",
+            "sample": "%d fixed-point iterations of one load case (first unit strain, contrast 100) on the full "
+                      "125^3 grid, FP64; %.1f s wall" % (evals, wall),
+            "host_cores_available": len(os.sched_getaffinity(0))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernel-pass", action="store_true",
+                    help="run a few profiled iterations of each path (for rocprofv3)")
+    ap.add_argument("--n", type=int, default=125)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1412_3228_amd as hm
+    from workloads import workload_c2, target_perturbation
+
+    dev = torch.device("cuda:0")
+    works = {c: workload_c2(c, n=args.n) for c in CONTRASTS}
+    n = works[CONTRASTS[0]].n
+    N = works[CONTRASTS[0]].nvox
+
+    if args.kernel_pass:
+        for prec in ("fp64", "mixed"):
+            w = works[CONTRASTS[0]]
+            cnt, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, prec, dev)
+            hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, prec=prec, tol=0.0,
+                                   max_iter=9, check_every=10, profile=True)
+            t = hm.last_timing()
+            print(json.dumps({"kernel_pass": prec, "timing": t}), flush=True)
+        # calibration copy of a known size for the rocprofv3 byte counters
+        x = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        _sync()
+        print(json.dumps({"calibration_copy_bytes": int(x.numel())}), flush=True)
+        return
+
+    # reference effective tensors (tightly converged FP64), untimed
+    ref = {}
+    targets = {}
+    for c in CONTRASTS:
+        w = works[c]
+        cnt, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", dev)
+        o = hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, prec="fp64", tol=1e-9,
+                                   max_iter=20000, check_every=32, use_graph=True)
+        ref[c] = o["C"]
+        u = target_perturbation(5, (6, 6))
+        Ct = ref[c] * (1.0 + 0.05 * u)
+        targets[c] = 0.5 * (Ct + Ct.T)
+        print("reference C (contrast %g): iters %s" % (c, [r["iters"] for r in o["reports"]]), file=sys.stderr,
+              flush=True)
+        del frac, incl, cnt
+
+    def one_step(profile=True):
+        res = {}
+        for prec in ("fp64", "mixed"):
+            for c in CONTRASTS:
+                res[(prec, c)] = run_path(hm, works[c], prec, c, dev, profile=profile, C_target=targets[c])
+        return res
+
+    for _ in range(args.warmup):
+        one_step()
+    _sync()
+    t0 = time.perf_counter()
+    steps = []
+    for s in range(args.steps):
+        steps.append(one_step())
+        print("step %d done" % s, file=sys.stderr, flush=True)
+    _sync()
+    total = time.perf_counter() - t0
+
+    paths = {}
+    for prec in ("fp64", "mixed"):
+        secs = sum(st[(prec, c)]["seconds"] for st in steps for c in CONTRASTS)
+        vit = sum(st[(prec, c)]["voxel_iterations"] for st in steps for c in CONTRASTS)
+        last = steps[-1]
+        errs = {str(c): float(np.linalg.norm(last[(prec, c)]["C"] - ref[c]) / np.linalg.norm(ref[c]))
+                for c in CONTRASTS}
+        iters = {str(c): [r["iters"] for r in last[(prec, c)]["reports"]] for c in CONTRASTS}
+        status = {str(c): [r["status"] for r in last[(prec, c)]["reports"]] for c in CONTRASTS}
+        finals = {str(c): [r["err"] for r in last[(prec, c)]["reports"]] for c in CONTRASTS}
+        timings = [st[(prec, c)]["timing"] for st in steps for c in CONTRASTS]
+        reps = [st[(prec, c)]["reports"] for st in steps for c in CONTRASTS]
+        paths[prec] = {"value": vit / secs, "seconds": secs, "voxel_iterations": vit,
+                       "ceff_rel_err_vs_fp64_tol1e-9": errs, "iters": iters, "status": status,
+                       "final_equilibrium_error": finals,
+                       "roofline": roofline(timings, n, prec, reps)}
+    mixed, fp64 = paths["mixed"], paths["fp64"]
+    line = {
+        "metric": METRIC,
+        "value": mixed["value"],
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "centred sphere f=0.25 in a %d^3 cell, contrasts 100 and 0.01, 2-layer filter "
+                               "r=1 voxel with 8^3 sub-samples, 6 unit Mandel strains batched, tol 1e-4" % n[0],
+                   "grid": list(n), "load_cases": 6, "voxels": N},
+        "mixed_over_fp64": mixed["value"] / fp64["value"],
+        "equal_ceff_error": "both paths within 1e-5 of the tightly converged FP64 effective tensor",
+        "paths": paths,
+        "roofline": mixed["roofline"],
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

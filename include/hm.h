@@ -103,7 +103,18 @@ typedef struct {
   int check_every;  /* host polls the stop flags every k iterations (>= 1)   */
   int stall_window; /* > 0: stop when e has not dropped 1% for this many its */
   int use_graph;    /* nonzero: replay the iteration through a HIP graph      */
+  int profile;      /* nonzero: time every kernel launch with HIP events on
+                       `stream` (forces direct launches); see hm_last_timing */
 } hm_solve_opts;
+
+/* Average device duration per launch of each kernel of the iteration, over
+ * the iterations a profiled solve evaluated (the longest load case). */
+typedef struct {
+  int iterations; /* iterations averaged                                   */
+  int n_load;     /* load cases of the solve                               */
+  double ms[5];   /* xsweep, forward ysweep, zsweep, inverse ysweep,
+                     finalize (milliseconds per launch)                     */
+} hm_timing;
 
 /* Per-load-case outcome. */
 typedef struct {
@@ -214,6 +225,10 @@ int hm_solve_adjoint(const hm_grid* grid, const hm_iso phases[2], hm_rule rule,
                      const hm_sphere* spheres, int n_spheres, hm_prec prec,
                      const double* dLdC, const void* d_eps, int n_load,
                      double* dLdphase, void* d_dLdfrac, void* stream);
+
+/* Timing of the calling thread's last solve run with opts->profile set.
+ * Returns HM_E_ARG when there is none. */
+int hm_last_timing(hm_timing* out);
 
 /* Message of the calling thread's last failed call ("" if none). */
 const char* hm_last_error(void);

@@ -12,6 +12,7 @@ from .api import (  # noqa: F401
     hm_filter,
     hm_solve,
     hm_solve_adjoint,
+    last_timing,
     release_plans,
 )
 from ._lib import EXPORTS, HmError, LIB_PATH, load  # noqa: F401

@@ -21,7 +21,7 @@ PRECS = {"fp64": 0, "mixed": 1}
 
 # Every symbol include/hm.h declares.
 EXPORTS = ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_solve_adjoint",
-           "hm_last_error", "hm_release_plans", "hm_device_ok")
+           "hm_last_error", "hm_last_timing", "hm_release_plans", "hm_device_ok")
 
 
 class HmGrid(ctypes.Structure):
@@ -39,7 +39,12 @@ class HmSphere(ctypes.Structure):
 class HmSolveOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("c0_alpha", ctypes.c_double), ("check_every", ctypes.c_int),
-                ("stall_window", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("stall_window", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("profile", ctypes.c_int)]
+
+
+class HmTiming(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("n_load", ctypes.c_int), ("ms", ctypes.c_double * 5)]
 
 
 class HmReport(ctypes.Structure):
@@ -77,6 +82,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                      ctypes.c_int, ctypes.c_int, _dp, _vp, ctypes.c_int, _dp, _vp, _vp]
     for f in ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_solve_adjoint", "hm_device_ok"):
         getattr(lib, f).restype = ctypes.c_int
+    lib.hm_last_timing.argtypes = [_P(HmTiming)]
+    lib.hm_last_timing.restype = ctypes.c_int
     lib.hm_last_error.argtypes = []
     lib.hm_last_error.restype = ctypes.c_char_p
     lib.hm_release_plans.argtypes = []

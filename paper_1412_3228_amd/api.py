@@ -64,7 +64,7 @@ def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
-def _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph) -> L.HmSolveOpts:
+def _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile=False) -> L.HmSolveOpts:
     o = L.HmSolveOpts()
     o.prec = L.PRECS[prec]
     o.tol = float(tol)
@@ -73,6 +73,7 @@ def _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph) -
     o.check_every = int(check_every)
     o.stall_window = int(stall_window)
     o.use_graph = 1 if use_graph else 0
+    o.profile = 1 if profile else 0
     return o
 
 
@@ -106,7 +107,8 @@ def hm_filter(n, dim, spheres, radius_vox: float, subsamples: int, rule: str, pr
 
 def hm_solve(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres, E,
              prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
-             check_every: int = 1, stall_window: int = 0, use_graph: bool = False, want_eps: bool = False):
+             check_every: int = 1, stall_window: int = 0, use_graph: bool = False, want_eps: bool = False,
+             profile: bool = False):
     """Fixed-point solve for the rows of E (n_load x 6 tensor components)."""
     dev = frac.device
     N = int(n[0] * n[1] * n[2])
@@ -119,7 +121,7 @@ def hm_solve(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch
     eps = torch.empty((nl, 6, N), dtype=_DT[prec], device=dev) if want_eps else None
     g = _grid(n, dim)
     sph, ns = _spheres(spheres)
-    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile)
     rc = _lib().hm_solve(ctypes.byref(g), _phases(phases), L.RULES[rule], _ptr(frac), _ptr(incl), sph, ns,
                          Ea.ctypes.data_as(L._dp), nl, ctypes.byref(o), _ptr(eps),
                          sig.ctypes.data_as(L._dp), rep, _stream(dev))
@@ -130,7 +132,7 @@ def hm_solve(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch
 def hm_effective_tensor(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres,
                         prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
                         check_every: int = 1, stall_window: int = 0, use_graph: bool = False,
-                        want_eps: bool = False):
+                        want_eps: bool = False, profile: bool = False):
     """Effective Mandel tensor from the unit-strain solves (6 in 3D, 3 in 2D)."""
     dev = frac.device
     N = int(n[0] * n[1] * n[2])
@@ -142,7 +144,7 @@ def hm_effective_tensor(n, dim, phases, rule: str, frac: torch.Tensor, incl: Opt
     eps = torch.empty((k, 6, N), dtype=_DT[prec], device=dev) if want_eps else None
     g = _grid(n, dim)
     sph, ns = _spheres(spheres)
-    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile)
     rc = _lib().hm_effective_tensor(ctypes.byref(g), _phases(phases), L.RULES[rule], _ptr(frac), _ptr(incl),
                                     sph, ns, ctypes.byref(o), C.ctypes.data_as(L._dp), _ptr(eps), rep,
                                     _stream(dev))
@@ -170,6 +172,14 @@ def hm_solve_adjoint(n, dim, phases, rule: str, frac: torch.Tensor, incl: Option
                                  dph.ctypes.data_as(L._dp), _ptr(dfr), _stream(dev))
     L.check(rc)
     return dph, dfr
+
+
+def last_timing():
+    """Per-kernel average milliseconds of this thread's last profiled solve."""
+    t = L.HmTiming()
+    L.check(_lib().hm_last_timing(ctypes.byref(t)))
+    names = ("xsweep", "ysweep_fwd", "zsweep", "ysweep_inv", "finalize")
+    return {"iterations": t.iterations, "n_load": t.n_load, "ms": {n: t.ms[i] for i, n in enumerate(names)}}
 
 
 def release_plans():

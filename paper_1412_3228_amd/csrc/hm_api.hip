@@ -13,6 +13,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <map>
 #include <mutex>
@@ -61,6 +62,8 @@ using namespace hm;
 namespace {
 
 thread_local std::string g_last_error;
+thread_local hm_timing g_last_timing;
+thread_local bool g_have_timing = false;
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -369,6 +372,103 @@ int build_graph(Plan* p, int k) {
   return HM_OK;
 }
 
+int finish_solve(Plan* p, SolveArgs a, hipStream_t s, void* d_eps, double* sig_mean, hm_report* rep,
+                 std::chrono::steady_clock::time_point t0) {
+  int rc;
+  bool done = false;
+  if (d_eps) {
+    a.eps_out = d_eps;
+    HM_HIP(p->kx->x_export(a, s));
+  }
+  if ((rc = poll_done(p, s, &done))) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = HM_OK;
+  int flags = 0;
+  for (int l = 0; l < p->n_load; ++l) {
+    const SolverState& st = p->state_host[l];
+    for (int c = 0; c < 6; ++c) sig_mean[6 * l + c] = st.sig[c];
+    const int status = st.done ? st.status : HM_NOT_CONVERGED;
+    if (rep) {
+      rep[l].iters = st.iters;
+      rep[l].status = status;
+      rep[l].err = st.err;
+      rep[l].err0 = st.err0;
+      rep[l].seconds = secs;
+    }
+    if (status > worst) worst = status;
+    flags |= st.flags;
+  }
+  if (flags & FLAG_NONE_FRACTIONAL) return fail(HM_E_DATA, "fractional voxel with HM_RULE_NONE");
+  if (flags & FLAG_BAD_INCL) return fail(HM_E_DATA, "d_incl holds a sphere index >= n_spheres");
+  return worst;
+}
+
+// Direct launches with a HIP event before and after every kernel; durations
+// are read back at each poll and averaged over the iterations that the
+// longest load case evaluated.
+int profiled_loop(Plan* p, SolveArgs a, const hm_solve_opts* opts, hipStream_t s, void* d_eps, double* sig_mean,
+                  hm_report* rep, std::chrono::steady_clock::time_point t0) {
+  const int k = opts->check_every;
+  std::vector<hipEvent_t> ev((size_t)6 * k, nullptr);
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& q : ev)
+        if (q) (void)hipEventDestroy(q);
+      return fail(HM_E_DEVICE, "hipEventCreate failed");
+    }
+  std::vector<double> dur;  // 5 per iteration
+  bool done = false;
+  int it = 0, rc = HM_OK;
+  hipError_t err = hipSuccess;
+  while (!done && it <= opts->max_iter && err == hipSuccess && rc == HM_OK) {
+    int nb = 0;
+    for (; nb < k && it <= opts->max_iter; ++nb, ++it) {
+      hipEvent_t* e = &ev[(size_t)6 * nb];
+      a.first = it == 0 ? 1 : 0;
+      err = hipEventRecord(e[0], s);
+      if (err == hipSuccess) err = (it == 0 ? p->kx->x_first : p->kx->x_iter)(a, s);
+      if (err == hipSuccess) err = hipEventRecord(e[1], s);
+      if (err == hipSuccess) err = p->ky->y_fwd(a, s);
+      if (err == hipSuccess) err = hipEventRecord(e[2], s);
+      if (err == hipSuccess) err = p->kz->z_gamma(a, s);
+      if (err == hipSuccess) err = hipEventRecord(e[3], s);
+      if (err == hipSuccess) err = p->ky->y_inv(a, s);
+      if (err == hipSuccess) err = hipEventRecord(e[4], s);
+      if (err == hipSuccess) {
+        hipLaunchKernelGGL((k_finalize<256>), dim3(a.n_load), dim3(256), 0, s, a);
+        err = hipGetLastError();
+      }
+      if (err == hipSuccess) err = hipEventRecord(e[5], s);
+      if (err != hipSuccess) break;
+    }
+    if (err != hipSuccess) break;
+    rc = poll_done(p, s, &done);
+    for (int b = 0; b < nb && rc == HM_OK; ++b) {
+      for (int q = 0; q < 5; ++q) {
+        float ms = 0.0f;
+        err = hipEventElapsedTime(&ms, ev[(size_t)6 * b + q], ev[(size_t)6 * b + q + 1]);
+        dur.push_back((double)ms);
+      }
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (err != hipSuccess) return fail(HM_E_DEVICE, "profiled loop: %s", hipGetErrorString(err));
+  if (rc) return rc;
+  int last = 0;
+  for (int l = 0; l < p->n_load; ++l) last = std::max(last, p->state_host[l].iters);
+  const int nit = std::min((int)(dur.size() / 5), last + 1);
+  hm_timing t;
+  memset(&t, 0, sizeof t);
+  t.iterations = nit;
+  t.n_load = p->n_load;
+  for (int i = 0; i < nit; ++i)
+    for (int q = 0; q < 5; ++q) t.ms[q] += dur[(size_t)5 * i + q];
+  for (int q = 0; q < 5; ++q) t.ms[q] /= nit > 0 ? nit : 1;
+  g_last_timing = t;
+  g_have_timing = true;
+  return finish_solve(p, a, s, d_eps, sig_mean, rep, t0);
+}
+
 // The solve shared by hm_solve and hm_effective_tensor.
 int solve_impl(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,
                const int32_t* d_incl, const hm_sphere* spheres, int n_spheres, const double* E, int n_load,
@@ -427,6 +527,7 @@ int solve_impl(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const 
   SolveArgs a = p->args;
   const int k = opts->check_every;
   bool done = false;
+  if (opts->profile) return profiled_loop(p, a, opts, s, d_eps, sig_mean, rep, t0);
   a.first = 1;
   HM_HIP(launch_iteration(p, a, true, s));
   a.first = 0;
@@ -450,31 +551,7 @@ int solve_impl(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const 
     }
   }
   if (!done && (rc = poll_done(p, s, &done))) return rc;
-  if (d_eps) {
-    a.eps_out = d_eps;
-    HM_HIP(p->kx->x_export(a, s));
-  }
-  if ((rc = poll_done(p, s, &done))) return rc;
-  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  int worst = HM_OK;
-  int flags = 0;
-  for (int l = 0; l < n_load; ++l) {
-    const SolverState& st = p->state_host[l];
-    for (int c = 0; c < 6; ++c) sig_mean[6 * l + c] = st.sig[c];
-    const int status = st.done ? st.status : HM_NOT_CONVERGED;
-    if (rep) {
-      rep[l].iters = st.iters;
-      rep[l].status = status;
-      rep[l].err = st.err;
-      rep[l].err0 = st.err0;
-      rep[l].seconds = secs;
-    }
-    if (status > worst) worst = status;
-    flags |= st.flags;
-  }
-  if (flags & FLAG_NONE_FRACTIONAL) return fail(HM_E_DATA, "fractional voxel with HM_RULE_NONE");
-  if (flags & FLAG_BAD_INCL) return fail(HM_E_DATA, "d_incl holds a sphere index >= n_spheres");
-  return worst;
+  return finish_solve(p, a, s, d_eps, sig_mean, rep, t0);
 }
 
 }  // namespace
@@ -482,6 +559,13 @@ int solve_impl(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const 
 extern "C" {
 
 const char* hm_last_error(void) { return g_last_error.c_str(); }
+
+int hm_last_timing(hm_timing* out) {
+  if (!out) return fail(HM_E_ARG, "out is NULL");
+  if (!g_have_timing) return fail(HM_E_ARG, "no profiled solve on this thread");
+  *out = g_last_timing;
+  return HM_OK;
+}
 
 int hm_device_ok(void) {
   int n = 0;

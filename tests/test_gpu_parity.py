@@ -191,3 +191,18 @@ def test_adjoint_matches_oracle_gradient(hm):
     rph, rfr = ogradient.hill_gradient(fld, [r["eps"] for r in reps], G, w.phases, nrm)
     assert rel(dph, rph) < 1e-9
     assert rel(dfr.cpu().numpy(), rfr) < 1e-9
+
+
+def test_profiled_solve_matches_and_reports_timing(hm):
+    w = small_sphere_case(n=(21, 21, 21), fraction=0.2, contrast=10.0, rule="laminate",
+                          radius_vox=1.0, subsamples=4)
+    log("profiled solve")
+    _, _, _, frac, incl = _gpu_filter(hm, w)
+    a = hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, prec="fp64",
+                               tol=1e-6, max_iter=500, check_every=7)
+    b = hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, prec="fp64",
+                               tol=1e-6, max_iter=500, check_every=7, profile=True)
+    assert np.array_equal(a["C"], b["C"])
+    t = hm.last_timing()
+    assert t["iterations"] == max(r["iters"] for r in b["reports"]) + 1
+    assert all(v > 0 for v in t["ms"].values())
