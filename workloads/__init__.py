@@ -17,5 +17,6 @@ from .microstructures import (  # noqa: F401
     workload_c4,
     workload_c5,
     small_sphere_case,
+    target_perturbation,
     random_fraction_case,
 )
