@@ -250,7 +250,9 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, Plan** out) {
   }
   const int H = (n[0] + 1) / 2;
   const size_t cplx = fp64 ? 16 : 8;
-  const size_t plane = (size_t)n[2] * n[1] * H;
+  const int row = (int)(128 / cplx);  // complex values per 128-byte line
+  const int Hp = (H + row - 1) / row * row;
+  const size_t plane = (size_t)n[2] * n[1] * Hp;
   const int g2 = (n[1] * n[2] + p->kx->x_lines - 1) / p->kx->x_lines;
   const int ntx3 = (H + p->ky->y_width - 1) / p->ky->y_width;
   const int ntx4 = (H + p->kz->z_width - 1) / p->kz->z_width;
@@ -287,6 +289,7 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, Plan** out) {
   a.ny = n[1];
   a.nz = n[2];
   a.H = H;
+  a.Hp = Hp;
   a.dim = dim;
   a.n_load = n_load;
   a.g2 = g2;

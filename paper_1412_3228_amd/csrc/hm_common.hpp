@@ -61,8 +61,8 @@ struct SolveParams {
 
 // Plan-stable launch arguments.
 struct SolveArgs {
-  void* spec;       // cx<T>[n_load][6][nz][ny][H]  x-spectrum / full spectrum
-  void* hist;       // cx<T>[n_load][3][nz][ny][H]  previous projected traction
+  void* spec;       // cx<T>[n_load][6][nz][ny][Hp]  x-spectrum / full spectrum
+  void* hist;       // cx<T>[n_load][3][nz][ny][Hp]  previous projected traction
   double* taupart;  // [n_load][g2][6]  per-block sums of tau
   double* errpart;  // [n_load][ny * ntx4]  per-block equilibrium sums
   SolverState* state;   // [n_load]
@@ -73,6 +73,7 @@ struct SolveArgs {
   const void* twy;
   const void* twz;
   int nx, ny, nz, H, dim, n_load;
+  int Hp;  // row stride of spectrum and history (H rounded up to 128-byte rows)
   int g2, ntx3, ntx4;
   int hist_cap;
   int first;  // 1 on iterate 0 (uniform strain, empty traction history)

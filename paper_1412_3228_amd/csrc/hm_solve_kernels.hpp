@@ -50,11 +50,11 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-// Polarization at one voxel: tau = (c~ - c0) : e.
+// Polarization at one voxel: tau = (c~ - c0) : e, from the voxel's
+// fraction f and normal-sphere id k.
 template <typename T>
-__device__ __forceinline__ void voxel_tau(const SolveArgs& a, const SolveParams& P, SolverState* st, size_t v,
+__device__ __forceinline__ void voxel_tau(const SolveArgs& a, const SolveParams& P, SolverState* st, T f, int k,
                                           int x, int y, int z, const T e[6], T tau[6]) {
-  const T f = static_cast<const T*>(P.frac)[v];
   Coef<T> c;
   c.aniso = false;
   c.a3 = c.a4 = c.a5 = T(0);
@@ -74,7 +74,6 @@ __device__ __forceinline__ void voxel_tau(const SolveArgs& a, const SolveParams&
     }
     rule_coefficients<T>(rule, f, pl, pm, c);
     if (c.aniso) {
-      const int k = P.incl ? P.incl[v] : -1;
       if (k >= P.nsph) atomicOr(&st->flags, FLAG_BAD_INCL);
       if (k >= 0 && k < P.nsph) {
         interface_normal<T>(P.sph, k, x, y, z, a.nx, a.ny, a.nz, a.dim, c.n);
@@ -91,13 +90,21 @@ __device__ __forceinline__ void voxel_tau(const SolveArgs& a, const SolveParams&
 }
 
 // ---------------------------------------------------------------- xsweep --
+// A block owns L consecutive (y, z) lines.  All of its global reads (the
+// six half-lines of each line and the material of its voxels) are issued
+// into registers before any LDS work, so each block keeps its whole input
+// in flight at once.
 template <typename T, int NX, int L, int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
   constexpr int LL = 3 * L;
   constexpr int H = (NX + 1) / 2;
+  constexpr int NLD = 3 * L * H;  // (pair, line, kx) items
+  constexpr int QL = (NLD + NT - 1) / NT;
+  constexpr int NV = L * NX;  // voxels of the block
+  constexpr int QV = (NV + NT - 1) / NT;
   __shared__ cx<T> buf[NX * LL];
   __shared__ cx<T> s_tw[NX];
-  __shared__ double red[NT / 64];
+  __shared__ double red[6][NT / 64];
   const int tid = threadIdx.x;
   const int load = blockIdx.y;
   SolverState* st = a.state + load;
@@ -105,24 +112,62 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
   const SolveParams& P = *a.prm;
   const int nlines = a.ny * a.nz;
   const int line0 = blockIdx.x * L;
-  const size_t cs = (size_t)nlines * H;
+  const int Hp = a.Hp;
+  const size_t cs = (size_t)nlines * Hp;
   cx<T>* spec = static_cast<cx<T>*>(a.spec) + (size_t)load * 6 * cs;
+
+  cx<T> pa[QL], pb[QL];
+  if (MODE != MODE_FIRST) {
+#pragma unroll
+    for (int q = 0; q < QL; ++q) {
+      const int idx = tid + q * NT;
+      pa[q] = cx<T>{T(0), T(0)};
+      pb[q] = cx<T>{T(0), T(0)};
+      if (idx < NLD) {
+        const int p = idx / (L * H);
+        const int rem = idx - p * (L * H);
+        const int l = rem / H;
+        const int k = rem - l * H;
+        const int line = line0 + l;
+        if (line < nlines) {
+          pa[q] = spec[(size_t)(2 * p) * cs + (size_t)line * Hp + k];
+          pb[q] = spec[(size_t)(2 * p + 1) * cs + (size_t)line * Hp + k];
+        }
+      }
+    }
+  }
+  T fv[QV];
+  int iv[QV];
+  if (MODE != MODE_EXPORT) {
+    const T* frac = static_cast<const T*>(P.frac);
+#pragma unroll
+    for (int q = 0; q < QV; ++q) {
+      const int idx = tid + q * NT;
+      const int l = idx / NX, x = idx - l * NX, line = line0 + l;
+      fv[q] = T(0);
+      iv[q] = -1;
+      if (idx < NV && line < nlines) {
+        const size_t v = (size_t)line * NX + x;
+        fv[q] = frac[v];
+        if (P.incl) iv[q] = P.incl[v];
+      }
+    }
+  }
   load_twiddles<T, NX, NT>(s_tw, static_cast<const cx<T>*>(a.twx), tid);
 
   if (MODE != MODE_FIRST) {
-    for (int idx = tid; idx < 3 * L * H; idx += NT) {
-      const int p = idx / (L * H);
-      const int rem = idx - p * (L * H);
-      const int l = rem / H;
-      const int k = rem - l * H;
-      const int line = line0 + l;
-      cx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
-      if (line < nlines) {
-        A = spec[(size_t)(2 * p) * cs + (size_t)line * H + k];
-        B = spec[(size_t)(2 * p + 1) * cs + (size_t)line * H + k];
+#pragma unroll
+    for (int q = 0; q < QL; ++q) {
+      const int idx = tid + q * NT;
+      if (idx < NLD) {
+        const int p = idx / (L * H);
+        const int rem = idx - p * (L * H);
+        const int l = rem / H;
+        const int k = rem - l * H;
+        const cx<T> A = pa[q], B = pb[q];
+        buf[k * LL + p * L + l] = cx<T>{A.x - B.y, A.y + B.x};
+        if (k > 0) buf[(NX - k) * LL + p * L + l] = cx<T>{A.x + B.y, B.x - A.y};
       }
-      buf[k * LL + p * L + l] = cx<T>{A.x - B.y, A.y + B.x};
-      if (k > 0) buf[(NX - k) * LL + p * L + l] = cx<T>{A.x + B.y, B.x - A.y};
     }
     __syncthreads();
     fft_lines<T, NX, LL, NT, +1>(buf, s_tw, tid);
@@ -131,7 +176,7 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
   if (MODE == MODE_EXPORT) {
     const size_t N = (size_t)nlines * NX;
     T* out = static_cast<T*>(a.eps_out) + (size_t)load * 6 * N;
-    for (int idx = tid; idx < L * NX; idx += NT) {
+    for (int idx = tid; idx < NV; idx += NT) {
       const int l = idx / NX, x = idx - l * NX, line = line0 + l;
       if (line < nlines) {
 #pragma unroll
@@ -146,7 +191,10 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
   }
 
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int idx = tid; idx < L * NX; idx += NT) {
+#pragma unroll
+  for (int q = 0; q < QV; ++q) {
+    const int idx = tid + q * NT;
+    if (idx >= NV) continue;
     const int l = idx / NX, x = idx - l * NX, line = line0 + l;
     T e[6];
     if (MODE == MODE_FIRST) {
@@ -163,7 +211,7 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
     T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     if (line < nlines) {
       const int y = line % a.ny, z = line / a.ny;
-      voxel_tau<T>(a, P, st, (size_t)line * NX + x, x, y, z, e, tau);
+      voxel_tau<T>(a, P, st, fv[q], iv[q], x, y, z, e, tau);
 #pragma unroll
       for (int c = 0; c < 6; ++c) acc[c] += (double)tau[c];
     }
@@ -173,7 +221,7 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
   __syncthreads();
   fft_lines<T, NX, LL, NT, -1>(buf, s_tw, tid);
 
-  for (int idx = tid; idx < 3 * L * H; idx += NT) {
+  for (int idx = tid; idx < NLD; idx += NT) {
     const int p = idx / (L * H);
     const int rem = idx - p * (L * H);
     const int l = rem / H;
@@ -184,43 +232,120 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
       const cx<T> Zc = c_conj(buf[((NX - k) % NX) * LL + p * L + l]);
       const cx<T> A = {T(0.5) * (Z.x + Zc.x), T(0.5) * (Z.y + Zc.y)};
       const cx<T> B = {T(0.5) * (Z.y - Zc.y), T(-0.5) * (Z.x - Zc.x)};
-      spec[(size_t)(2 * p) * cs + (size_t)line * H + k] = A;
-      spec[(size_t)(2 * p + 1) * cs + (size_t)line * H + k] = B;
+      spec[(size_t)(2 * p) * cs + (size_t)line * Hp + k] = A;
+      spec[(size_t)(2 * p + 1) * cs + (size_t)line * Hp + k] = B;
     }
   }
+  // deterministic block sums of the six tau components
+  const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    const double s = block_sum<NT>(acc[c], red);
-    if (tid == 0) a.taupart[((size_t)load * a.g2 + blockIdx.x) * 6 + c] = s;
+    double v = acc[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[c][wv] = v;
+  }
+  __syncthreads();
+  if (tid < 6) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) s += red[tid][i];
+    a.taupart[((size_t)load * a.g2 + blockIdx.x) * 6 + tid] = s;
   }
 }
 
 // ---------------------------------------------------------------- ysweep --
+// A block owns W adjacent kx columns of one (load, component, z) plane.
 template <typename T, int NY, int W, int NT, int SIGN>
 __global__ __launch_bounds__(NT) void k_ysweep(SolveArgs a) {
-  __shared__ cx<T> buf[NY * W];
+  constexpr int SL = NY * W;
+  constexpr int Q = (SL + NT - 1) / NT;
+  __shared__ cx<T> buf[SL];
   __shared__ cx<T> s_tw[NY];
   const int tid = threadIdx.x;
   const int z = blockIdx.y;
   const int load = blockIdx.z / 6, comp = blockIdx.z - 6 * (blockIdx.z / 6);
   if (a.state[load].done) return;
-  const int H = a.H;
+  const int H = a.H, Hp = a.Hp;
   const int kx0 = blockIdx.x * W;
-  cx<T>* base = static_cast<cx<T>*>(a.spec) + ((size_t)(load * 6 + comp) * a.nz + z) * (size_t)NY * H + kx0;
+  cx<T>* base = static_cast<cx<T>*>(a.spec) + ((size_t)(load * 6 + comp) * a.nz + z) * (size_t)NY * Hp + kx0;
+  cx<T> r[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int s = tid + q * NT;
+    r[q] = cx<T>{T(0), T(0)};
+    if (s < SL) {
+      const int j = s / W, w = s - j * W;
+      if (kx0 + w < H) r[q] = base[(size_t)j * Hp + w];
+    }
+  }
   load_twiddles<T, NY, NT>(s_tw, static_cast<const cx<T>*>(a.twy), tid);
-  for (int idx = tid; idx < NY * W; idx += NT) {
-    const int j = idx / W, w = idx - j * W;
-    buf[idx] = (kx0 + w < H) ? base[(size_t)j * H + w] : cx<T>{T(0), T(0)};
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int s = tid + q * NT;
+    if (s < SL) buf[s] = r[q];
   }
   __syncthreads();
   fft_lines<T, NY, W, NT, SIGN>(buf, s_tw, tid);
-  for (int idx = tid; idx < NY * W; idx += NT) {
-    const int j = idx / W, w = idx - j * W;
-    if (kx0 + w < H) base[(size_t)j * H + w] = buf[idx];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int s = tid + q * NT;
+    if (s < SL) {
+      const int j = s / W, w = s - j * W;
+      if (kx0 + w < H) base[(size_t)j * Hp + w] = buf[s];
+    }
   }
 }
 
 // ---------------------------------------------------------------- zsweep --
+// A block owns W adjacent kx columns of one (load, ky) slab, i.e. W z-lines
+// of every component; thread slot s = kz * W + w is one frequency.
+// Gamma0^ : tau^ depends on tau^ only through a = tau^ . n, so the six
+// components are transformed one at a time (the next one's global read in
+// flight meanwhile) and folded into a; the inverse phase rebuilds each
+// strain component from a before its inverse transform.
+
+// Per-frequency registers of the z-sweep: unit normal and a = tau^ . n.
+template <typename T> struct Slot {
+  T n0, n1, n2;
+  cx<T> a0, a1, a2;
+};
+
+// Tensor indices (i, j) of component c in the order 11, 22, 33, 23, 13, 12.
+__device__ __forceinline__ int comp_i(int c) { return c < 3 ? c : (c == 3 ? 1 : 0); }
+__device__ __forceinline__ int comp_j(int c) { return c < 3 ? c : (c == 5 ? 1 : 2); }
+
+template <typename T> __device__ __forceinline__ T pick(int k, T v0, T v1, T v2) {
+  return k == 0 ? v0 : (k == 1 ? v1 : v2);
+}
+
+// a_k += tau_c (d_ki n_j + d_kj n_i) for i != j, a_i += tau_c n_i for i == j.
+template <typename T>
+__device__ __forceinline__ void fold_component(int c, cx<T> v, Slot<T>& z) {
+  const int i = comp_i(c), j = comp_j(c);
+  const T ni = pick(i, z.n0, z.n1, z.n2), nj = pick(j, z.n0, z.n1, z.n2);
+  const T w0 = (i == 0 ? nj : T(0)) + (j == 0 && i != j ? ni : T(0));
+  const T w1 = (i == 1 ? nj : T(0)) + (j == 1 && i != j ? ni : T(0));
+  const T w2 = (i == 2 ? nj : T(0)) + (j == 2 && i != j ? ni : T(0));
+  z.a0.x += v.x * w0;
+  z.a0.y += v.y * w0;
+  z.a1.x += v.x * w1;
+  z.a1.y += v.y * w1;
+  z.a2.x += v.x * w2;
+  z.a2.y += v.y * w2;
+}
+
+// Component c of m * [(n (x) a + a (x) n) / (2 mu0) - cc (n.a) n (x) n].
+template <typename T>
+__device__ __forceinline__ cx<T> strain_component(int c, const Slot<T>& z, cx<T> na, T inv2mu, T cc, T m) {
+  const int i = comp_i(c), j = comp_j(c);
+  const T ni = pick(i, z.n0, z.n1, z.n2), nj = pick(j, z.n0, z.n1, z.n2);
+  const T aix = pick(i, z.a0.x, z.a1.x, z.a2.x), aiy = pick(i, z.a0.y, z.a1.y, z.a2.y);
+  const T ajx = pick(j, z.a0.x, z.a1.x, z.a2.x), ajy = pick(j, z.a0.y, z.a1.y, z.a2.y);
+  const T g = cc * ni * nj;
+  return cx<T>{m * ((ni * ajx + nj * aix) * inv2mu - g * na.x), m * ((ni * ajy + nj * aiy) * inv2mu - g * na.y)};
+}
+
 template <typename T, int NZ, int W, int NT>
 __global__ __launch_bounds__(NT) void k_zsweep(SolveArgs a) {
   constexpr int SL = W * NZ;
@@ -232,108 +357,118 @@ __global__ __launch_bounds__(NT) void k_zsweep(SolveArgs a) {
   const int tile = blockIdx.x, ky = blockIdx.y, load = blockIdx.z;
   if (a.state[load].done) return;
   const SolveParams& P = *a.prm;
-  const int H = a.H, ny = a.ny;
+  const int H = a.H, Hp = a.Hp, ny = a.ny;
   const int kx0 = tile * W;
-  const size_t zs = (size_t)ny * H;
+  const size_t zs = (size_t)ny * Hp;
   const size_t plane = (size_t)NZ * zs;
-  cx<T>* sp = static_cast<cx<T>*>(a.spec) + (size_t)load * 6 * plane + (size_t)ky * H + kx0;
-  cx<T>* hp = static_cast<cx<T>*>(a.hist) + (size_t)load * 3 * plane + (size_t)ky * H + kx0;
+  cx<T>* sp = static_cast<cx<T>*>(a.spec) + (size_t)load * 6 * plane + (size_t)ky * Hp + kx0;
+  cx<T>* hp = static_cast<cx<T>*>(a.hist) + (size_t)load * 3 * plane + (size_t)ky * Hp + kx0;
+  const int ay = ky <= (ny - 1) / 2 ? ky : ky - ny;
+  const double twopi = 6.283185307179586476925286766559;
+
+  bool ok[Q];
+  unsigned off[Q];
+  Slot<T> z[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int s = tid + q * NT;
+    const int kz = s / W, w = s - (s / W) * W;
+    const int kx = kx0 + w;
+    ok[q] = s < SL && kx < H;
+    off[q] = (unsigned)(kz * zs + w);
+    const int az = kz <= (NZ - 1) / 2 ? kz : kz - NZ;
+    const double x0 = twopi * kx, x1 = twopi * ay, x2 = twopi * az;
+    const double q2 = x0 * x0 + x1 * x1 + x2 * x2;
+    const double rinv = q2 > 0.0 ? 1.0 / sqrt(q2) : 0.0;
+    z[q].n0 = T(x0 * rinv);
+    z[q].n1 = T(x1 * rinv);
+    z[q].n2 = T(x2 * rinv);
+    z[q].a0 = z[q].a1 = z[q].a2 = cx<T>{T(0), T(0)};
+  }
+  cx<T> nxt[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) nxt[q] = ok[q] ? sp[off[q]] : cx<T>{T(0), T(0)};
   load_twiddles<T, NZ, NT>(s_tw, static_cast<const cx<T>*>(a.twz), tid);
 
-  cx<T> r[6][Q];
-#pragma unroll
+#pragma unroll 1
   for (int c = 0; c < 6; ++c) {
-    for (int idx = tid; idx < SL; idx += NT) {
-      const int kz = idx / W, w = idx - kz * W;
-      buf[idx] = (kx0 + w < H) ? sp[(size_t)c * plane + (size_t)kz * zs + w] : cx<T>{T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int s = tid + q * NT;
+      if (s < SL) buf[s] = nxt[q];
+    }
+    if (c < 5) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) nxt[q] = ok[q] ? sp[(size_t)(c + 1) * plane + off[q]] : cx<T>{T(0), T(0)};
     }
     __syncthreads();
     fft_lines<T, NZ, W, NT, -1>(buf, s_tw, tid);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int s = tid + q * NT;
-      if (s < SL) r[c][q] = buf[s];
+      if (s < SL) fold_component<T>(c, buf[s], z[q]);
     }
     __syncthreads();
   }
 
-  const double rl = P.rl, rm = P.rm;
-  const T inv2mu = T(1.0 / (2.0 * rm));
-  const T cc = T((rl + rm) / (rm * (rl + 2.0 * rm)));
-  const T invN = T(1.0 / ((double)a.nx * (double)ny * (double)NZ));
-  const int ay = ky <= (ny - 1) / 2 ? ky : ky - ny;
-  const double twopi = 6.283185307179586476925286766559;
+  // equilibrium error partial and traction history
   double S = 0.0;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
+    if (!ok[q]) continue;
     const int s = tid + q * NT;
-    if (s >= SL) continue;
     const int kz = s / W, w = s - kz * W;
-    const int kx = kx0 + w;
-    if (kx >= H) continue;
     const int az = kz <= (NZ - 1) / 2 ? kz : kz - NZ;
-    const size_t ho = (size_t)kz * zs + w;
+    const int kx = kx0 + w;
+    cx<T>* h0 = hp + off[q];
     if (kx == 0 && ay == 0 && az == 0) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) r[c][q] = cx<T>{T(P.E[load * 6 + c]), T(0)};
-#pragma unroll
-      for (int c = 0; c < 3; ++c) hp[(size_t)c * plane + ho] = cx<T>{T(0), T(0)};
+      h0[0] = h0[plane] = h0[2 * plane] = cx<T>{T(0), T(0)};
       continue;
     }
-    const double x0 = twopi * kx, x1 = twopi * ay, x2 = twopi * az;
-    const double q2 = x0 * x0 + x1 * x1 + x2 * x2;
-    const double rinv = 1.0 / sqrt(q2);
-    const T n0 = T(x0 * rinv), n1 = T(x1 * rinv), n2 = T(x2 * rinv);
-    const cx<T> t11 = r[0][q], t22 = r[1][q], t33 = r[2][q], t23 = r[3][q], t13 = r[4][q], t12 = r[5][q];
-    // a = tau^ . n
-    const cx<T> a0 = {t11.x * n0 + t12.x * n1 + t13.x * n2, t11.y * n0 + t12.y * n1 + t13.y * n2};
-    const cx<T> a1 = {t12.x * n0 + t22.x * n1 + t23.x * n2, t12.y * n0 + t22.y * n1 + t23.y * n2};
-    const cx<T> a2 = {t13.x * n0 + t23.x * n1 + t33.x * n2, t13.y * n0 + t23.y * n1 + t33.y * n2};
-    const cx<T> na = {a0.x * n0 + a1.x * n1 + a2.x * n2, a0.y * n0 + a1.y * n1 + a2.y * n2};
-    // equilibrium error partial
-    {
-      cx<T> p0 = {T(0), T(0)}, p1 = {T(0), T(0)}, p2 = {T(0), T(0)};
-      if (!a.first) {
-        p0 = hp[ho];
-        p1 = hp[plane + ho];
-        p2 = hp[2 * plane + ho];
-      }
-      const double d0x = (double)a0.x - (double)p0.x, d0y = (double)a0.y - (double)p0.y;
-      const double d1x = (double)a1.x - (double)p1.x, d1y = (double)a1.y - (double)p1.y;
-      const double d2x = (double)a2.x - (double)p2.x, d2y = (double)a2.y - (double)p2.y;
-      const double wk = kx == 0 ? 1.0 : 2.0;
-      S += wk * q2 * (d0x * d0x + d0y * d0y + d1x * d1x + d1y * d1y + d2x * d2x + d2y * d2y);
-      hp[ho] = a0;
-      hp[plane + ho] = a1;
-      hp[2 * plane + ho] = a2;
+    cx<T> p0 = {T(0), T(0)}, p1 = {T(0), T(0)}, p2 = {T(0), T(0)};
+    if (!a.first) {
+      p0 = h0[0];
+      p1 = h0[plane];
+      p2 = h0[2 * plane];
     }
-    // eps^_kh = -[(n_k a_h + n_h a_k) / (2 mu0) - cc (n.a) n_k n_h] / N
-    const T m = -invN;
-    auto comp = [&](T nk, T nh, cx<T> ak, cx<T> ah) -> cx<T> {
-      const T g = cc * nk * nh;
-      return cx<T>{m * ((nk * ah.x + nh * ak.x) * inv2mu - g * na.x),
-                   m * ((nk * ah.y + nh * ak.y) * inv2mu - g * na.y)};
-    };
-    r[0][q] = comp(n0, n0, a0, a0);
-    r[1][q] = comp(n1, n1, a1, a1);
-    r[2][q] = comp(n2, n2, a2, a2);
-    r[3][q] = comp(n1, n2, a1, a2);
-    r[4][q] = comp(n0, n2, a0, a2);
-    r[5][q] = comp(n0, n1, a0, a1);
+    const double d0x = (double)z[q].a0.x - (double)p0.x, d0y = (double)z[q].a0.y - (double)p0.y;
+    const double d1x = (double)z[q].a1.x - (double)p1.x, d1y = (double)z[q].a1.y - (double)p1.y;
+    const double d2x = (double)z[q].a2.x - (double)p2.x, d2y = (double)z[q].a2.y - (double)p2.y;
+    h0[0] = z[q].a0;
+    h0[plane] = z[q].a1;
+    h0[2 * plane] = z[q].a2;
+    const double x0 = twopi * kx, x1 = twopi * ay, x2 = twopi * az;
+    S += (kx == 0 ? 1.0 : 2.0) * (x0 * x0 + x1 * x1 + x2 * x2) *
+         (d0x * d0x + d0y * d0y + d1x * d1x + d1y * d1y + d2x * d2x + d2y * d2y);
   }
 
+  // eps^_kh = -[(n_k a_h + n_h a_k) / (2 mu0) - cc (n.a) n_k n_h] / N, eps^(0) = E
+  const double rl = P.rl, rm = P.rm;
+  const T inv2mu = T(1.0 / (2.0 * rm));
+  const T cc = T((rl + rm) / (rm * (rl + 2.0 * rm)));
+  const T m = T(-1.0 / ((double)a.nx * (double)ny * (double)NZ));
+  cx<T> na[Q];
 #pragma unroll
+  for (int q = 0; q < Q; ++q)
+    na[q] = cx<T>{z[q].a0.x * z[q].n0 + z[q].a1.x * z[q].n1 + z[q].a2.x * z[q].n2,
+                  z[q].a0.y * z[q].n0 + z[q].a1.y * z[q].n1 + z[q].a2.y * z[q].n2};
+#pragma unroll 1
   for (int c = 0; c < 6; ++c) {
+    const T Ec = T(P.E[load * 6 + c]);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int s = tid + q * NT;
-      if (s < SL) buf[s] = r[c][q];
+      if (s < SL) {
+        const bool zero = z[q].n0 == T(0) && z[q].n1 == T(0) && z[q].n2 == T(0);
+        buf[s] = zero ? cx<T>{Ec, T(0)} : strain_component<T>(c, z[q], na[q], inv2mu, cc, m);
+      }
     }
     __syncthreads();
     fft_lines<T, NZ, W, NT, +1>(buf, s_tw, tid);
-    for (int idx = tid; idx < SL; idx += NT) {
-      const int kz = idx / W, w = idx - kz * W;
-      if (kx0 + w < H) sp[(size_t)c * plane + (size_t)kz * zs + w] = buf[idx];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int s = tid + q * NT;
+      if (s < SL && ok[q]) sp[(size_t)c * plane + off[q]] = buf[s];
     }
     __syncthreads();
   }
@@ -465,7 +600,8 @@ template <typename T, int N> struct Tiles {
   static constexpr int YW = sizeof(T) == 8 ? 8 : 16;
   static constexpr int YNT = 256;
   static constexpr int ZW = sizeof(T) == 8 ? 8 : 16;
-  static constexpr int ZNT = (ZW * N > 1024) ? 512 : 256;
+  static constexpr int zt0 = ((ZW * N + 63) / 64) * 64;
+  static constexpr int ZNT = zt0 > 1024 ? 1024 : (zt0 < 64 ? 64 : zt0);
 };
 
 template <typename T, int NX, int MODE>
