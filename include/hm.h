@@ -105,6 +105,8 @@ typedef struct {
   int use_graph;    /* nonzero: replay the iteration through a HIP graph      */
   int profile;      /* nonzero: time every kernel launch with HIP events on
                        `stream` (forces direct launches); see hm_last_timing */
+  int autotune;     /* nonzero: on a plan's first solve, time every compiled
+                       tile schedule of the sweeps and keep the fastest     */
 } hm_solve_opts;
 
 /* Average device duration per launch of each kernel of the iteration, over
@@ -114,6 +116,10 @@ typedef struct {
   int n_load;     /* load cases of the solve                               */
   double ms[5];   /* xsweep, forward ysweep, zsweep, inverse ysweep,
                      finalize (milliseconds per launch)                     */
+  int x_lines;    /* schedule in use: grid lines per xsweep block,         */
+  int y_width;    /*   kx columns per ysweep block,                        */
+  int z_width;    /*   kx columns per zsweep block                         */
+  int z_threads;  /*   and zsweep block size                               */
 } hm_timing;
 
 /* Per-load-case outcome. */

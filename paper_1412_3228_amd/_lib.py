@@ -40,11 +40,13 @@ class HmSolveOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("c0_alpha", ctypes.c_double), ("check_every", ctypes.c_int),
                 ("stall_window", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("profile", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("autotune", ctypes.c_int)]
 
 
 class HmTiming(ctypes.Structure):
-    _fields_ = [("iterations", ctypes.c_int), ("n_load", ctypes.c_int), ("ms", ctypes.c_double * 5)]
+    _fields_ = [("iterations", ctypes.c_int), ("n_load", ctypes.c_int), ("ms", ctypes.c_double * 5),
+                ("x_lines", ctypes.c_int), ("y_width", ctypes.c_int), ("z_width", ctypes.c_int),
+                ("z_threads", ctypes.c_int)]
 
 
 class HmReport(ctypes.Structure):

@@ -64,7 +64,8 @@ def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
-def _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile=False) -> L.HmSolveOpts:
+def _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile=False,
+          autotune=True) -> L.HmSolveOpts:
     o = L.HmSolveOpts()
     o.prec = L.PRECS[prec]
     o.tol = float(tol)
@@ -74,6 +75,7 @@ def _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, p
     o.stall_window = int(stall_window)
     o.use_graph = 1 if use_graph else 0
     o.profile = 1 if profile else 0
+    o.autotune = 1 if autotune else 0
     return o
 
 
@@ -179,7 +181,9 @@ def last_timing():
     t = L.HmTiming()
     L.check(_lib().hm_last_timing(ctypes.byref(t)))
     names = ("xsweep", "ysweep_fwd", "zsweep", "ysweep_inv", "finalize")
-    return {"iterations": t.iterations, "n_load": t.n_load, "ms": {n: t.ms[i] for i, n in enumerate(names)}}
+    return {"iterations": t.iterations, "n_load": t.n_load, "ms": {n: t.ms[i] for i, n in enumerate(names)},
+            "schedule": {"x_lines": t.x_lines, "y_width": t.y_width, "z_width": t.z_width,
+                         "z_threads": t.z_threads}}
 
 
 def release_plans():

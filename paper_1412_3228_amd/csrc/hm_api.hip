@@ -154,6 +154,9 @@ std::vector<double> twiddles(int n) {
   return t;
 }
 
+struct Plan;
+void set_schedule(Plan* p, const XKern* X, const YKern* Y, const ZKern* Z);
+
 struct Plan {
   bool fp64 = true;
   int n[3] = {0, 0, 0};
@@ -162,6 +165,10 @@ struct Plan {
   const AxisKernels* kx = nullptr;
   const AxisKernels* ky = nullptr;
   const AxisKernels* kz = nullptr;
+  const XKern* X = nullptr;  // chosen schedules
+  const YKern* Y = nullptr;
+  const ZKern* Z = nullptr;
+  bool tuned = false;
   void* spec = nullptr;
   void* hist = nullptr;
   double* taupart = nullptr;
@@ -253,9 +260,12 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, Plan** out) {
   const int row = (int)(128 / cplx);  // complex values per 128-byte line
   const int Hp = (H + row - 1) / row * row;
   const size_t plane = (size_t)n[2] * n[1] * Hp;
-  const int g2 = (n[1] * n[2] + p->kx->x_lines - 1) / p->kx->x_lines;
-  const int ntx3 = (H + p->ky->y_width - 1) / p->ky->y_width;
-  const int ntx4 = (H + p->kz->z_width - 1) / p->kz->z_width;
+  // partial-sum buffers sized for the finest schedule of each kernel
+  int min_lines = 1 << 30, min_zw = 1 << 30;
+  for (int v = 0; v < p->kx->nxv; ++v) min_lines = std::min(min_lines, p->kx->x[v].lines);
+  for (int v = 0; v < p->kz->nzv; ++v) min_zw = std::min(min_zw, p->kz->z[v].width);
+  const int g2 = (n[1] * n[2] + min_lines - 1) / min_lines;
+  const int ntx4 = (H + min_zw - 1) / min_zw;
   int rc = HM_OK;
   if (!rc) rc = device_alloc(&p->spec, (size_t)n_load * 6 * plane * cplx, "spectrum");
   if (!rc) rc = device_alloc(&p->hist, (size_t)n_load * 3 * plane * cplx, "traction history");
@@ -292,12 +302,24 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, Plan** out) {
   a.Hp = Hp;
   a.dim = dim;
   a.n_load = n_load;
-  a.g2 = g2;
-  a.ntx3 = ntx3;
-  a.ntx4 = ntx4;
+  set_schedule(p, &p->kx->x[0], &p->ky->y[0], &p->kz->z[0]);
   g_plans[key] = p;
   *out = p;
   return HM_OK;
+}
+
+void set_schedule(Plan* p, const XKern* X, const YKern* Y, const ZKern* Z) {
+  p->X = X;
+  p->Y = Y;
+  p->Z = Z;
+  SolveArgs& a = p->args;
+  a.g2 = (a.ny * a.nz + X->lines - 1) / X->lines;
+  a.ntx3 = (a.H + Y->width - 1) / Y->width;
+  a.ntx4 = (a.H + Z->width - 1) / Z->width;
+  if (p->graph) {
+    (void)hipGraphExecDestroy(p->graph);
+    p->graph = nullptr;
+  }
 }
 
 int ensure_hist(Plan* p, int cap) {
@@ -330,10 +352,10 @@ int ensure_spheres(Plan* p, int ns) {
 
 hipError_t launch_iteration(Plan* p, const SolveArgs& a, bool first, hipStream_t s) {
   hipError_t e;
-  if ((e = (first ? p->kx->x_first : p->kx->x_iter)(a, s)) != hipSuccess) return e;
-  if ((e = p->ky->y_fwd(a, s)) != hipSuccess) return e;
-  if ((e = p->kz->z_gamma(a, s)) != hipSuccess) return e;
-  if ((e = p->ky->y_inv(a, s)) != hipSuccess) return e;
+  if ((e = (first ? p->X->first : p->X->iter)(a, s)) != hipSuccess) return e;
+  if ((e = p->Y->fwd(a, s)) != hipSuccess) return e;
+  if ((e = p->Z->run(a, s)) != hipSuccess) return e;
+  if ((e = p->Y->inv(a, s)) != hipSuccess) return e;
   hipLaunchKernelGGL((k_finalize<256>), dim3(a.n_load), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -381,7 +403,7 @@ int finish_solve(Plan* p, SolveArgs a, hipStream_t s, void* d_eps, double* sig_m
   bool done = false;
   if (d_eps) {
     a.eps_out = d_eps;
-    HM_HIP(p->kx->x_export(a, s));
+    HM_HIP(p->X->exp(a, s));
   }
   if ((rc = poll_done(p, s, &done))) return rc;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -429,13 +451,13 @@ int profiled_loop(Plan* p, SolveArgs a, const hm_solve_opts* opts, hipStream_t s
       hipEvent_t* e = &ev[(size_t)6 * nb];
       a.first = it == 0 ? 1 : 0;
       err = hipEventRecord(e[0], s);
-      if (err == hipSuccess) err = (it == 0 ? p->kx->x_first : p->kx->x_iter)(a, s);
+      if (err == hipSuccess) err = (it == 0 ? p->X->first : p->X->iter)(a, s);
       if (err == hipSuccess) err = hipEventRecord(e[1], s);
-      if (err == hipSuccess) err = p->ky->y_fwd(a, s);
+      if (err == hipSuccess) err = p->Y->fwd(a, s);
       if (err == hipSuccess) err = hipEventRecord(e[2], s);
-      if (err == hipSuccess) err = p->kz->z_gamma(a, s);
+      if (err == hipSuccess) err = p->Z->run(a, s);
       if (err == hipSuccess) err = hipEventRecord(e[3], s);
-      if (err == hipSuccess) err = p->ky->y_inv(a, s);
+      if (err == hipSuccess) err = p->Y->inv(a, s);
       if (err == hipSuccess) err = hipEventRecord(e[4], s);
       if (err == hipSuccess) {
         hipLaunchKernelGGL((k_finalize<256>), dim3(a.n_load), dim3(256), 0, s, a);
@@ -464,12 +486,84 @@ int profiled_loop(Plan* p, SolveArgs a, const hm_solve_opts* opts, hipStream_t s
   memset(&t, 0, sizeof t);
   t.iterations = nit;
   t.n_load = p->n_load;
+  t.x_lines = p->X->lines;
+  t.y_width = p->Y->width;
+  t.z_width = p->Z->width;
+  t.z_threads = p->Z->threads;
   for (int i = 0; i < nit; ++i)
     for (int q = 0; q < 5; ++q) t.ms[q] += dur[(size_t)5 * i + q];
   for (int q = 0; q < 5; ++q) t.ms[q] /= nit > 0 ? nit : 1;
   g_last_timing = t;
   g_have_timing = true;
   return finish_solve(p, a, s, d_eps, sig_mean, rep, t0);
+}
+
+// Times every compiled schedule of the three sweeps on this plan's own
+// workspace (iteration mode, all load cases active) and keeps the fastest.
+// Runs once per plan, before the first solve; the workspace is zeroed first
+// and the solver state is reset by the caller afterwards.
+int tune_plan(Plan* p, hipStream_t s) {
+  hipEvent_t e0, e1;
+  HM_HIP(hipEventCreate(&e0));
+  HM_HIP(hipEventCreate(&e1));
+  const size_t cplx = p->fp64 ? 16 : 8;
+  const size_t plane = (size_t)p->n[2] * p->n[1] * p->args.Hp;
+  hipError_t err = hipMemsetAsync(p->spec, 0, (size_t)p->n_load * 6 * plane * cplx, s);
+  if (err == hipSuccess) err = hipMemsetAsync(p->hist, 0, (size_t)p->n_load * 3 * plane * cplx, s);
+  hipLaunchKernelGGL((k_reset_state<64>), dim3(1), dim3(64), 0, s, p->state, p->n_load);
+  if (err == hipSuccess) err = hipGetLastError();
+  auto time_it = [&](solve_launch_fn f, const SolveArgs& a, float* best) -> hipError_t {
+    hipError_t e = f(a, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = f(a, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    *best = ms;
+    return e;
+  };
+  const XKern* bx = &p->kx->x[0];
+  const YKern* by = &p->ky->y[0];
+  const ZKern* bz = &p->kz->z[0];
+  float tbest = 1e30f, t = 0.0f;
+  for (int v = 0; v < p->kx->nxv && err == hipSuccess; ++v) {
+    set_schedule(p, &p->kx->x[v], by, bz);
+    SolveArgs a = p->args;
+    a.first = 0;
+    err = time_it(p->kx->x[v].iter, a, &t);
+    if (t < tbest) {
+      tbest = t;
+      bx = &p->kx->x[v];
+    }
+  }
+  tbest = 1e30f;
+  for (int v = 0; v < p->ky->nyv && err == hipSuccess; ++v) {
+    set_schedule(p, bx, &p->ky->y[v], bz);
+    SolveArgs a = p->args;
+    err = time_it(p->ky->y[v].fwd, a, &t);
+    if (t < tbest) {
+      tbest = t;
+      by = &p->ky->y[v];
+    }
+  }
+  tbest = 1e30f;
+  for (int v = 0; v < p->kz->nzv && err == hipSuccess; ++v) {
+    set_schedule(p, bx, by, &p->kz->z[v]);
+    SolveArgs a = p->args;
+    a.first = 0;
+    err = time_it(p->kz->z[v].run, a, &t);
+    if (t < tbest) {
+      tbest = t;
+      bz = &p->kz->z[v];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(HM_E_DEVICE, "autotune: %s", hipGetErrorString(err));
+  set_schedule(p, bx, by, bz);
+  p->tuned = true;
+  return HM_OK;
 }
 
 // The solve shared by hm_solve and hm_effective_tensor.
@@ -524,6 +618,8 @@ int solve_impl(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const 
   if (n_spheres > 0)
     HM_HIP(hipMemcpyAsync(p->sph, sph.data(), (size_t)n_spheres * 4 * sizeof(double), hipMemcpyHostToDevice, s));
   HM_HIP(hipMemcpyAsync(p->prm, p->prm_host, sizeof(SolveParams), hipMemcpyHostToDevice, s));
+  if (opts->autotune && !p->tuned)
+    if ((rc = tune_plan(p, s))) return rc;
   hipLaunchKernelGGL((k_reset_state<64>), dim3(1), dim3(64), 0, s, p->state, n_load);
   HM_HIP(hipGetLastError());
 

@@ -347,7 +347,7 @@ __device__ __forceinline__ cx<T> strain_component(int c, const Slot<T>& z, cx<T>
 }
 
 template <typename T, int NZ, int W, int NT>
-__global__ __launch_bounds__(NT) void k_zsweep(SolveArgs a) {
+__global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
   constexpr int SL = W * NZ;
   constexpr int Q = (SL + NT - 1) / NT;
   __shared__ cx<T> buf[SL];
@@ -582,62 +582,101 @@ __global__ __launch_bounds__(NT) void k_reset_state(SolverState* st, int n_load)
 // ------------------------------------------------------------ registry --
 using solve_launch_fn = hipError_t (*)(const SolveArgs&, hipStream_t);
 
+// Candidate schedules of one axis length, timed by the plan's autotuner.
+struct XKern {
+  solve_launch_fn first, iter, exp;
+  int lines;  // (y, z) lines per block
+};
+struct YKern {
+  solve_launch_fn fwd, inv;
+  int width;  // kx columns per block
+};
+struct ZKern {
+  solve_launch_fn run;
+  int width;    // kx columns per block
+  int threads;  // block size
+};
+constexpr int kMaxVariants = 3;
 struct AxisKernels {
   int n;
-  solve_launch_fn x_first, x_iter, x_export;
-  solve_launch_fn y_fwd, y_inv;
-  solve_launch_fn z_gamma;
-  int x_lines;  // lines per xsweep block
-  int y_width;  // kx tile of ysweep
-  int z_width;  // kx tile of zsweep
+  int nxv, nyv, nzv;
+  XKern x[kMaxVariants];
+  YKern y[kMaxVariants];
+  ZKern z[kMaxVariants];
 };
 
-// Tile choices (per precision and line length).
-template <typename T, int N> struct Tiles {
-  static constexpr int xl0 = 1000 / (N > 0 ? N : 1);
-  static constexpr int XL = xl0 < 1 ? 1 : (xl0 > 8 ? 8 : xl0);
-  static constexpr int XNT = 256;
-  static constexpr int YW = sizeof(T) == 8 ? 8 : 16;
-  static constexpr int YNT = 256;
-  static constexpr int ZW = sizeof(T) == 8 ? 8 : 16;
-  static constexpr int zt0 = ((ZW * N + 63) / 64) * 64;
-  static constexpr int ZNT = zt0 > 1024 ? 1024 : (zt0 < 64 ? 64 : zt0);
+constexpr int clamp_int(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+constexpr int round64(int v) { return (v + 63) / 64 * 64; }
+
+// xsweep variant v: lines per block from {8, 4, 2}, limited to 56 KB of LDS.
+template <typename T, int N, int V> struct XTile {
+  static constexpr int want = V == 0 ? 8 : (V == 1 ? 4 : 2);
+  static constexpr int cap = (56 * 1024) / (3 * N * (int)sizeof(cx<T>));
+  static constexpr int L = clamp_int(want < cap ? want : cap, 1, 8);
+  static constexpr int NT = 256;
+};
+// ysweep variant v: width 128 B or 256 B of kx per row.
+template <typename T, int N, int V> struct YTile {
+  static constexpr int W = (V == 0 ? 128 : 256) / (int)sizeof(cx<T>);
+  static constexpr int NT = 256;
+};
+// zsweep variant v: width 128 B (v = 0) or 256 B (v = 1, 64 B when that
+// would need more than 1024 threads); threads so that each holds at most QT
+// frequency slots (2 in FP64, 4 in FP32; half that when radix-7 butterflies
+// are in play) under a 128-register cap.
+template <typename T, int N, int V> struct ZTile {
+  static constexpr int QT = (sizeof(T) == 8 ? 2 : 4) / (N % 7 == 0 ? 2 : 1);
+  static constexpr int W0 = 128 / (int)sizeof(cx<T>);
+  static constexpr int W1 = 256 / (int)sizeof(cx<T>);
+  static constexpr int W = V == 0 ? W0 : ((W1 * N + QT - 1) / QT <= 1024 ? W1 : W0 / 2);
+  static constexpr int NT = clamp_int(round64((W * N + QT - 1) / QT), 64, 1024);
 };
 
-template <typename T, int NX, int MODE>
+template <typename T, int NX, int MODE, int V>
 hipError_t launch_x(const SolveArgs& a, hipStream_t s) {
-  using TL = Tiles<T, NX>;
-  hipLaunchKernelGGL((k_xsweep<T, NX, TL::XL, TL::XNT, MODE>), dim3(a.g2, a.n_load), dim3(TL::XNT), 0, s, a);
+  using TL = XTile<T, NX, V>;
+  hipLaunchKernelGGL((k_xsweep<T, NX, TL::L, TL::NT, MODE>), dim3(a.g2, a.n_load), dim3(TL::NT), 0, s, a);
   return hipGetLastError();
 }
-template <typename T, int NY, int SIGN>
+template <typename T, int NY, int SIGN, int V>
 hipError_t launch_y(const SolveArgs& a, hipStream_t s) {
-  using TL = Tiles<T, NY>;
-  hipLaunchKernelGGL((k_ysweep<T, NY, TL::YW, TL::YNT, SIGN>), dim3(a.ntx3, a.nz, 6 * a.n_load), dim3(TL::YNT), 0,
+  using TL = YTile<T, NY, V>;
+  hipLaunchKernelGGL((k_ysweep<T, NY, TL::W, TL::NT, SIGN>), dim3(a.ntx3, a.nz, 6 * a.n_load), dim3(TL::NT), 0,
                      s, a);
   return hipGetLastError();
 }
-template <typename T, int NZ>
+template <typename T, int NZ, int V>
 hipError_t launch_z(const SolveArgs& a, hipStream_t s) {
-  using TL = Tiles<T, NZ>;
-  hipLaunchKernelGGL((k_zsweep<T, NZ, TL::ZW, TL::ZNT>), dim3(a.ntx4, a.ny, a.n_load), dim3(TL::ZNT), 0, s, a);
+  using TL = ZTile<T, NZ, V>;
+  hipLaunchKernelGGL((k_zsweep<T, NZ, TL::W, TL::NT>), dim3(a.ntx4, a.ny, a.n_load), dim3(TL::NT), 0, s, a);
   return hipGetLastError();
+}
+
+template <typename T, int N, int V> XKern make_x() {
+  return XKern{&launch_x<T, N, MODE_FIRST, V>, &launch_x<T, N, MODE_ITER, V>, &launch_x<T, N, MODE_EXPORT, V>,
+               XTile<T, N, V>::L};
+}
+template <typename T, int N, int V> YKern make_y() {
+  return YKern{&launch_y<T, N, -1, V>, &launch_y<T, N, +1, V>, YTile<T, N, V>::W};
+}
+template <typename T, int N, int V> ZKern make_z() {
+  return ZKern{&launch_z<T, N, V>, ZTile<T, N, V>::W, ZTile<T, N, V>::NT};
 }
 
 template <typename T, int N>
 AxisKernels make_axis_kernels() {
-  using TL = Tiles<T, N>;
   AxisKernels k;
   k.n = N;
-  k.x_first = &launch_x<T, N, MODE_FIRST>;
-  k.x_iter = &launch_x<T, N, MODE_ITER>;
-  k.x_export = &launch_x<T, N, MODE_EXPORT>;
-  k.y_fwd = &launch_y<T, N, -1>;
-  k.y_inv = &launch_y<T, N, +1>;
-  k.z_gamma = &launch_z<T, N>;
-  k.x_lines = TL::XL;
-  k.y_width = TL::YW;
-  k.z_width = TL::ZW;
+  k.x[0] = make_x<T, N, 0>();
+  k.nxv = 1;
+  if (XTile<T, N, 1>::L != k.x[0].lines) k.x[k.nxv++] = make_x<T, N, 1>();
+  if (XTile<T, N, 2>::L != k.x[k.nxv - 1].lines) k.x[k.nxv++] = make_x<T, N, 2>();
+  k.y[0] = make_y<T, N, 0>();
+  k.y[1] = make_y<T, N, 1>();
+  k.nyv = 2;
+  k.z[0] = make_z<T, N, 0>();
+  k.z[1] = make_z<T, N, 1>();
+  k.nzv = 2;
   return k;
 }
 
