@@ -119,7 +119,8 @@ typedef struct {
   int x_lines;    /* schedule in use: grid lines per xsweep block,         */
   int y_width;    /*   kx columns per ysweep block,                        */
   int z_width;    /*   kx columns per zsweep block                         */
-  int z_threads;  /*   and zsweep block size                               */
+  int z_threads;  /*   zsweep block size                                   */
+  int z_groups;   /*   and components per zsweep LDS transform             */
 } hm_timing;
 
 /* Per-load-case outcome. */

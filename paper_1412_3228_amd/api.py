@@ -183,7 +183,7 @@ def last_timing():
     names = ("xsweep", "ysweep_fwd", "zsweep", "ysweep_inv", "finalize")
     return {"iterations": t.iterations, "n_load": t.n_load, "ms": {n: t.ms[i] for i, n in enumerate(names)},
             "schedule": {"x_lines": t.x_lines, "y_width": t.y_width, "z_width": t.z_width,
-                         "z_threads": t.z_threads}}
+                         "z_threads": t.z_threads, "z_groups": t.z_groups}}
 
 
 def release_plans():

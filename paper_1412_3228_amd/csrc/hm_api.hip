@@ -356,7 +356,7 @@ hipError_t launch_iteration(Plan* p, const SolveArgs& a, bool first, hipStream_t
   if ((e = p->Y->fwd(a, s)) != hipSuccess) return e;
   if ((e = p->Z->run(a, s)) != hipSuccess) return e;
   if ((e = p->Y->inv(a, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_finalize<256>), dim3(a.n_load), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_finalize<kFinalizeThreads>), dim3(a.n_load), dim3(kFinalizeThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -460,7 +460,7 @@ int profiled_loop(Plan* p, SolveArgs a, const hm_solve_opts* opts, hipStream_t s
       if (err == hipSuccess) err = p->Y->inv(a, s);
       if (err == hipSuccess) err = hipEventRecord(e[4], s);
       if (err == hipSuccess) {
-        hipLaunchKernelGGL((k_finalize<256>), dim3(a.n_load), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_finalize<kFinalizeThreads>), dim3(a.n_load), dim3(kFinalizeThreads), 0, s, a);
         err = hipGetLastError();
       }
       if (err == hipSuccess) err = hipEventRecord(e[5], s);
@@ -490,6 +490,7 @@ int profiled_loop(Plan* p, SolveArgs a, const hm_solve_opts* opts, hipStream_t s
   t.y_width = p->Y->width;
   t.z_width = p->Z->width;
   t.z_threads = p->Z->threads;
+  t.z_groups = p->Z->groups;
   for (int i = 0; i < nit; ++i)
     for (int q = 0; q < 5; ++q) t.ms[q] += dur[(size_t)5 * i + q];
   for (int q = 0; q < 5; ++q) t.ms[q] /= nit > 0 ? nit : 1;

@@ -3,7 +3,8 @@
 // every line length is a product of odd radices; no power-of-two tricks.
 //
 // Layout: a workgroup transforms L lines of length N held in LDS as
-// buf[j * L + l] (element j of line l), so that consecutive threads touch
+// buf[j * LD + l] (element j of line l, row stride LD >= L; an odd LD spreads
+// strided accesses over all banks), so that consecutive threads touch
 // consecutive addresses.  Each radix-R pass reads R inputs per butterfly into
 // registers, synchronises, then writes the autosorted outputs back in place
 // (read-all / barrier / write-all, so one buffer suffices).  Twiddles come
@@ -108,7 +109,7 @@ template <int N> struct FftPlan {
   static_assert(passes() >= 0, "line length must be a product of 3, 5 and 7");
 };
 
-template <typename T, int N, int L, int NT, int R, int NS, int SIGN>
+template <typename T, int N, int L, int NT, int R, int NS, int SIGN, int LD>
 __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid) {
   constexpr int NB = N / R;
   constexpr int TOT = L * NB;
@@ -121,7 +122,7 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid) {
     if (EXACT || b < TOT) {
       const int l = b % L, j = b / L;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = buf[(j + r * NB) * L + l];
+      for (int r = 0; r < R; ++r) v[q][r] = buf[(j + r * NB) * LD + l];
     }
   }
   __syncthreads();
@@ -143,7 +144,7 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid) {
       dft_small<T, R, SIGN>(v[q]);
       const int base = (j / NS) * NS * R + jm;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(base + r * NS) * L + l] = v[q][r];
+      for (int r = 0; r < R; ++r) buf[(base + r * NS) * LD + l] = v[q][r];
     }
   }
   __syncthreads();
@@ -151,11 +152,11 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid) {
 
 // Transforms the L lines in buf.  The caller synchronises before the call
 // (data staged); the buffer is complete and synchronised on return.
-template <typename T, int N, int L, int NT, int SIGN, int P = 0>
+template <typename T, int N, int L, int NT, int SIGN, int LD = L, int P = 0>
 __device__ __forceinline__ void fft_lines(cx<T>* buf, const cx<T>* tw, int tid) {
   if constexpr (P < FftPlan<N>::passes()) {
-    fft_pass<T, N, L, NT, FftPlan<N>::radix(P), FftPlan<N>::stride(P), SIGN>(buf, tw, tid);
-    fft_lines<T, N, L, NT, SIGN, P + 1>(buf, tw, tid);
+    fft_pass<T, N, L, NT, FftPlan<N>::radix(P), FftPlan<N>::stride(P), SIGN, LD>(buf, tw, tid);
+    fft_lines<T, N, L, NT, SIGN, LD, P + 1>(buf, tw, tid);
   }
 }
 

@@ -32,6 +32,9 @@ namespace hm {
 
 enum : int { MODE_FIRST = 0, MODE_ITER = 1, MODE_EXPORT = 2 };
 
+// Block size of the finalize kernel (one block per load case).
+constexpr int kFinalizeThreads = 1024;
+
 // Deterministic block sum (fixed shuffle tree, then waves in order); the
 // result is valid in thread 0.
 template <int NT>
@@ -97,12 +100,13 @@ __device__ __forceinline__ void voxel_tau(const SolveArgs& a, const SolveParams&
 template <typename T, int NX, int L, int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
   constexpr int LL = 3 * L;
+  constexpr int LD = LL | 1;  // odd row stride: element rows spread over the banks
   constexpr int H = (NX + 1) / 2;
   constexpr int NLD = 3 * L * H;  // (pair, line, kx) items
   constexpr int QL = (NLD + NT - 1) / NT;
   constexpr int NV = L * NX;  // voxels of the block
   constexpr int QV = (NV + NT - 1) / NT;
-  __shared__ cx<T> buf[NX * LL];
+  __shared__ cx<T> buf[NX * LD];
   __shared__ cx<T> s_tw[NX];
   __shared__ double red[6][NT / 64];
   const int tid = threadIdx.x;
@@ -165,12 +169,12 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
         const int l = rem / H;
         const int k = rem - l * H;
         const cx<T> A = pa[q], B = pb[q];
-        buf[k * LL + p * L + l] = cx<T>{A.x - B.y, A.y + B.x};
-        if (k > 0) buf[(NX - k) * LL + p * L + l] = cx<T>{A.x + B.y, B.x - A.y};
+        buf[k * LD + p * L + l] = cx<T>{A.x - B.y, A.y + B.x};
+        if (k > 0) buf[(NX - k) * LD + p * L + l] = cx<T>{A.x + B.y, B.x - A.y};
       }
     }
     __syncthreads();
-    fft_lines<T, NX, LL, NT, +1>(buf, s_tw, tid);
+    fft_lines<T, NX, LL, NT, +1, LD>(buf, s_tw, tid);
   }
 
   if (MODE == MODE_EXPORT) {
@@ -181,7 +185,7 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
       if (line < nlines) {
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
-          const cx<T> Z = buf[x * LL + p * L + l];
+          const cx<T> Z = buf[x * LD + p * L + l];
           out[(size_t)(2 * p) * N + (size_t)line * NX + x] = Z.x;
           out[(size_t)(2 * p + 1) * N + (size_t)line * NX + x] = Z.y;
         }
@@ -203,7 +207,7 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
     } else {
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
-        const cx<T> Z = buf[x * LL + p * L + l];
+        const cx<T> Z = buf[x * LD + p * L + l];
         e[2 * p] = Z.x;
         e[2 * p + 1] = Z.y;
       }
@@ -216,10 +220,10 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
       for (int c = 0; c < 6; ++c) acc[c] += (double)tau[c];
     }
 #pragma unroll
-    for (int p = 0; p < 3; ++p) buf[x * LL + p * L + l] = cx<T>{tau[2 * p], tau[2 * p + 1]};
+    for (int p = 0; p < 3; ++p) buf[x * LD + p * L + l] = cx<T>{tau[2 * p], tau[2 * p + 1]};
   }
   __syncthreads();
-  fft_lines<T, NX, LL, NT, -1>(buf, s_tw, tid);
+  fft_lines<T, NX, LL, NT, -1, LD>(buf, s_tw, tid);
 
   for (int idx = tid; idx < NLD; idx += NT) {
     const int p = idx / (L * H);
@@ -228,8 +232,8 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
     const int k = rem - l * H;
     const int line = line0 + l;
     if (line < nlines) {
-      const cx<T> Z = buf[k * LL + p * L + l];
-      const cx<T> Zc = c_conj(buf[((NX - k) % NX) * LL + p * L + l]);
+      const cx<T> Z = buf[k * LD + p * L + l];
+      const cx<T> Zc = c_conj(buf[((NX - k) % NX) * LD + p * L + l]);
       const cx<T> A = {T(0.5) * (Z.x + Zc.x), T(0.5) * (Z.y + Zc.y)};
       const cx<T> B = {T(0.5) * (Z.y - Zc.y), T(-0.5) * (Z.x - Zc.x)};
       spec[(size_t)(2 * p) * cs + (size_t)line * Hp + k] = A;
@@ -346,11 +350,14 @@ __device__ __forceinline__ cx<T> strain_component(int c, const Slot<T>& z, cx<T>
   return cx<T>{m * ((ni * ajx + nj * aix) * inv2mu - g * na.x), m * ((ni * ajy + nj * aiy) * inv2mu - g * na.y)};
 }
 
-template <typename T, int NZ, int W, int NT>
+template <typename T, int NZ, int W, int NT, int CG>
 __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
+  static_assert(6 % CG == 0, "component groups must divide 6");
   constexpr int SL = W * NZ;
   constexpr int Q = (SL + NT - 1) / NT;
-  __shared__ cx<T> buf[SL];
+  constexpr int LW = CG * W;      // lines per transform: CG components x W columns
+  constexpr int LD = LW | 1;      // odd row stride
+  __shared__ cx<T> buf[NZ * LD];
   __shared__ cx<T> s_tw[NZ];
   __shared__ double red[NT / 64];
   const int tid = threadIdx.x;
@@ -368,6 +375,7 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
 
   bool ok[Q];
   unsigned off[Q];
+  unsigned lds[Q];  // LDS index of the slot's first component
   Slot<T> z[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -376,6 +384,7 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
     const int kx = kx0 + w;
     ok[q] = s < SL && kx < H;
     off[q] = (unsigned)(kz * zs + w);
+    lds[q] = (unsigned)(kz * LD + w);
     const int az = kz <= (NZ - 1) / 2 ? kz : kz - NZ;
     const double x0 = twopi * kx, x1 = twopi * ay, x2 = twopi * az;
     const double q2 = x0 * x0 + x1 * x1 + x2 * x2;
@@ -385,29 +394,34 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
     z[q].n2 = T(x2 * rinv);
     z[q].a0 = z[q].a1 = z[q].a2 = cx<T>{T(0), T(0)};
   }
-  cx<T> nxt[Q];
+  cx<T> nxt[CG][Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) nxt[q] = ok[q] ? sp[off[q]] : cx<T>{T(0), T(0)};
+  for (int g = 0; g < CG; ++g)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) nxt[g][q] = ok[q] ? sp[(size_t)g * plane + off[q]] : cx<T>{T(0), T(0)};
   load_twiddles<T, NZ, NT>(s_tw, static_cast<const cx<T>*>(a.twz), tid);
 
 #pragma unroll 1
-  for (int c = 0; c < 6; ++c) {
+  for (int c0 = 0; c0 < 6; c0 += CG) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int s = tid + q * NT;
-      if (s < SL) buf[s] = nxt[q];
-    }
-    if (c < 5) {
+    for (int g = 0; g < CG; ++g)
 #pragma unroll
-      for (int q = 0; q < Q; ++q) nxt[q] = ok[q] ? sp[(size_t)(c + 1) * plane + off[q]] : cx<T>{T(0), T(0)};
+      for (int q = 0; q < Q; ++q)
+        if (tid + q * NT < SL) buf[lds[q] + g * W] = nxt[g][q];
+    if (c0 + CG < 6) {
+#pragma unroll
+      for (int g = 0; g < CG; ++g)
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+          nxt[g][q] = ok[q] ? sp[(size_t)(c0 + CG + g) * plane + off[q]] : cx<T>{T(0), T(0)};
     }
     __syncthreads();
-    fft_lines<T, NZ, W, NT, -1>(buf, s_tw, tid);
+    fft_lines<T, NZ, LW, NT, -1, LD>(buf, s_tw, tid);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int s = tid + q * NT;
-      if (s < SL) fold_component<T>(c, buf[s], z[q]);
-    }
+    for (int g = 0; g < CG; ++g)
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        if (tid + q * NT < SL) fold_component<T>(c0 + g, buf[lds[q] + g * W], z[q]);
     __syncthreads();
   }
 
@@ -453,23 +467,25 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
     na[q] = cx<T>{z[q].a0.x * z[q].n0 + z[q].a1.x * z[q].n1 + z[q].a2.x * z[q].n2,
                   z[q].a0.y * z[q].n0 + z[q].a1.y * z[q].n1 + z[q].a2.y * z[q].n2};
 #pragma unroll 1
-  for (int c = 0; c < 6; ++c) {
-    const T Ec = T(P.E[load * 6 + c]);
+  for (int c0 = 0; c0 < 6; c0 += CG) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int s = tid + q * NT;
-      if (s < SL) {
-        const bool zero = z[q].n0 == T(0) && z[q].n1 == T(0) && z[q].n2 == T(0);
-        buf[s] = zero ? cx<T>{Ec, T(0)} : strain_component<T>(c, z[q], na[q], inv2mu, cc, m);
+    for (int g = 0; g < CG; ++g) {
+      const T Ec = T(P.E[load * 6 + c0 + g]);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        if (tid + q * NT < SL) {
+          const bool zero = z[q].n0 == T(0) && z[q].n1 == T(0) && z[q].n2 == T(0);
+          buf[lds[q] + g * W] = zero ? cx<T>{Ec, T(0)} : strain_component<T>(c0 + g, z[q], na[q], inv2mu, cc, m);
+        }
       }
     }
     __syncthreads();
-    fft_lines<T, NZ, W, NT, +1>(buf, s_tw, tid);
+    fft_lines<T, NZ, LW, NT, +1, LD>(buf, s_tw, tid);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int s = tid + q * NT;
-      if (s < SL && ok[q]) sp[(size_t)c * plane + off[q]] = buf[s];
-    }
+    for (int g = 0; g < CG; ++g)
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        if (tid + q * NT < SL && ok[q]) sp[(size_t)(c0 + g) * plane + off[q]] = buf[lds[q] + g * W];
     __syncthreads();
   }
   const double tot = block_sum<NT>(S, red);
@@ -595,6 +611,7 @@ struct ZKern {
   solve_launch_fn run;
   int width;    // kx columns per block
   int threads;  // block size
+  int groups;   // components per LDS transform
 };
 constexpr int kMaxVariants = 3;
 struct AxisKernels {
@@ -624,11 +641,18 @@ template <typename T, int N, int V> struct YTile {
 // would need more than 1024 threads); threads so that each holds at most QT
 // frequency slots (2 in FP64, 4 in FP32; half that when radix-7 butterflies
 // are in play) under a 128-register cap.
+// Variant 2 transforms CG = 3 (or 2) components per LDS pass at width
+// 128 B when that fits in 56 KB of LDS.
+// Variant 2 holds one frequency slot per thread (so needs W N <= 1024).
 template <typename T, int N, int V> struct ZTile {
-  static constexpr int QT = (sizeof(T) == 8 ? 2 : 4) / (N % 7 == 0 ? 2 : 1);
   static constexpr int W0 = 128 / (int)sizeof(cx<T>);
   static constexpr int W1 = 256 / (int)sizeof(cx<T>);
-  static constexpr int W = V == 0 ? W0 : ((W1 * N + QT - 1) / QT <= 1024 ? W1 : W0 / 2);
+  static constexpr int QT = V == 2 ? 1 : (sizeof(T) == 8 ? 2 : 4) / (N % 7 == 0 ? 2 : 1);
+  static constexpr int W = V == 1 ? ((W1 * N + QT - 1) / QT <= 1024 ? W1 : W0 / 2) : W0;
+  static constexpr int lds3 = N * ((3 * W) | 1) * (int)sizeof(cx<T>);
+  static constexpr int lds2 = N * ((2 * W) | 1) * (int)sizeof(cx<T>);
+  static constexpr int CG =
+      (V == 2 && W * N <= 1024) ? (lds3 <= 56 * 1024 ? 3 : (lds2 <= 56 * 1024 ? 2 : 1)) : 1;
   static constexpr int NT = clamp_int(round64((W * N + QT - 1) / QT), 64, 1024);
 };
 
@@ -648,7 +672,8 @@ hipError_t launch_y(const SolveArgs& a, hipStream_t s) {
 template <typename T, int NZ, int V>
 hipError_t launch_z(const SolveArgs& a, hipStream_t s) {
   using TL = ZTile<T, NZ, V>;
-  hipLaunchKernelGGL((k_zsweep<T, NZ, TL::W, TL::NT>), dim3(a.ntx4, a.ny, a.n_load), dim3(TL::NT), 0, s, a);
+  hipLaunchKernelGGL((k_zsweep<T, NZ, TL::W, TL::NT, TL::CG>), dim3(a.ntx4, a.ny, a.n_load), dim3(TL::NT), 0, s,
+                     a);
   return hipGetLastError();
 }
 
@@ -660,7 +685,7 @@ template <typename T, int N, int V> YKern make_y() {
   return YKern{&launch_y<T, N, -1, V>, &launch_y<T, N, +1, V>, YTile<T, N, V>::W};
 }
 template <typename T, int N, int V> ZKern make_z() {
-  return ZKern{&launch_z<T, N, V>, ZTile<T, N, V>::W, ZTile<T, N, V>::NT};
+  return ZKern{&launch_z<T, N, V>, ZTile<T, N, V>::W, ZTile<T, N, V>::NT, ZTile<T, N, V>::CG};
 }
 
 template <typename T, int N>
@@ -677,6 +702,7 @@ AxisKernels make_axis_kernels() {
   k.z[0] = make_z<T, N, 0>();
   k.z[1] = make_z<T, N, 1>();
   k.nzv = 2;
+  if (ZTile<T, N, 2>::CG > 1) k.z[k.nzv++] = make_z<T, N, 2>();
   return k;
 }
 
