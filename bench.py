@@ -15,11 +15,18 @@ path's effective-tensor error against a tightly converged FP64 solve.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
        python bench.py --kernel-pass   (a few profiled iterations, for rocprofv3)
+       python bench.py --summarize TRACE_DIR FETCH_DIR WRITE_DIR --out FILE
+           (turns the rocprofv3 CSVs of three --kernel-pass runs into the
+           text summary kept under profiles/)
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
+import re
 import math
 import os
 import sys
@@ -34,6 +41,91 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "voxel-iterations/s of LS fixed point, mixed vs FP64 at equal C_eff error; %HBM peak"
 CONTRASTS = (100.0, 0.01)
+
+
+KERNEL_SOURCES = ("hm_solve_kernels.hpp", "hm_fft.hpp", "hm_material.hpp", "hm_common.hpp")
+PROFILE_GLOB = os.path.join(ROOT, "profiles", "hbm_traffic_*.txt")
+
+
+def kernel_source_hash():
+    """sha256 over the sources of the solver kernels (counters go stale when it changes)."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1412_3228_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _short(name):
+    m = re.search(r"k_(\w+?)<(double|float), (\d+)((?:, -?\d+)*)>", name)
+    if m:
+        return "%s<%s,%s%s>" % (m.group(1), m.group(2), m.group(3), m.group(4).replace(" ", ""))
+    return name.split("(")[0][:60]
+
+
+def summarize(trace_dir, fetch_dir, write_dir, out):
+    """Writes the per-kernel duration and calibrated HBM traffic summary."""
+    def rows(d, pat):
+        fs = glob.glob(os.path.join(d, "**", pat), recursive=True)
+        return list(csv.DictReader(open(fs[0]))) if fs else []
+    stats = rows(trace_dir, "*kernel_stats.csv")
+    fetch = rows(fetch_dir, "*counter_collection.csv")
+    write = rows(write_dir, "*counter_collection.csv")
+    calib = 1 << 28  # bytes of the calibration copy in --kernel-pass
+
+    def per_kernel(rr, counter):
+        out_ = {}
+        for r in rr:
+            if r["Counter_Name"] == counter:
+                out_.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        return out_
+    fk, wk = per_kernel(fetch, "FETCH_SIZE"), per_kernel(write, "WRITE_SIZE")
+    cal_f = [v for k, vs in fk.items() if "copyBuffer" in k for v in vs if v > 1e5]
+    cal_w = [v for k, vs in wk.items() if "copyBuffer" in k for v in vs if v > 1e5]
+    sf = calib / 1024.0 / (sum(cal_f) / len(cal_f))
+    sw = calib / 1024.0 / (sum(cal_w) / len(cal_w))
+    lines = ["# rocprofv3 summary: solver sweeps, centred-sphere 125^3 cell, 6 load cases",
+             "# commands (run from /tmp with TMPDIR=/tmp, repository at $R):",
+             "#   rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof/trace -o kp -- "
+             "python3 -u $R/bench.py --kernel-pass",
+             "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/prof/fetch -o kp -- "
+             "python3 -u $R/bench.py --kernel-pass",
+             "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/prof/write -o kp -- "
+             "python3 -u $R/bench.py --kernel-pass",
+             "#   python3 bench.py --summarize <trace> <fetch> <write> --out <this file>",
+             "# calibration: a %d-byte device copy reads FETCH_SIZE x %.4f and WRITE_SIZE x %.4f of its bytes;"
+             % (calib, 1.0 / sf, 1.0 / sw),
+             "# traffic below = counter (KiB) x 1024 x scale (fetch %.4f, write %.4f)" % (sf, sw),
+             "source_hash: %s" % kernel_source_hash(),
+             "scale_fetch: %.6f" % sf,
+             "scale_write: %.6f" % sw,
+             "# kernel | calls | avg_us | fetch_MB | write_MB | traffic_MB (per dispatch, averages)"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        k = _short(r["Name"])
+        f = fk.get(k)
+        w = wk.get(k)
+        fm = sum(f) / len(f) * 1024 * sf / 1e6 if f else float("nan")
+        wm = sum(w) / len(w) * 1024 * sw / 1e6 if w else float("nan")
+        lines.append("kernel: %s | %s | %.2f | %.1f | %.1f | %.1f" % (k, r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                                  fm, wm, fm + wm))
+    with open(out, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def measured_traffic(kernel_key):
+    """Calibrated HBM bytes per dispatch of a kernel from profiles/, or None if stale/absent."""
+    h = kernel_source_hash()
+    for path in sorted(glob.glob(PROFILE_GLOB)):
+        txt = open(path).read()
+        m = re.search(r"^source_hash: (\w+)", txt, re.M)
+        if not m or m.group(1) != h:
+            continue
+        for line in txt.splitlines():
+            if line.startswith("kernel: %s |" % kernel_key):
+                parts = [p.strip() for p in line.split("|")]
+                return {"bytes": float(parts[5]) * 1e6, "file": os.path.relpath(path, ROOT)}
+    return None
 
 
 def _sync():
@@ -85,6 +177,18 @@ def run_path(hm, w, prec, contrast, dev, profile=True, C_target=None, max_iter=5
             "dLdphase": dph}
 
 
+def _kernel_key(dom, prec, n, sched):
+    """Name of the dominant kernel's instantiation, as in the rocprofv3 summaries."""
+    t = "double" if prec == "fp64" else "float"
+    if dom == "xsweep":
+        return "xsweep<%s,%d,%d,256,1>" % (t, n[0], sched["x_lines"])
+    if dom in ("ysweep_fwd", "ysweep_inv"):
+        return "ysweep<%s,%d,%d,256,%d>" % (t, n[1], sched["y_width"], -1 if dom == "ysweep_fwd" else 1)
+    if dom == "zsweep":
+        return "zsweep<%s,%d,%d,%d,%d>" % (t, n[2], sched["z_width"], sched["z_threads"], sched["z_groups"])
+    return dom
+
+
 def roofline(timings, n, prec, reports):
     """Dominant kernel of the profiled solves, its algorithmic bandwidth vs peak."""
     tot = {}
@@ -98,8 +202,13 @@ def roofline(timings, n, prec, reports):
     ms = tot[dom] / its
     bytes_launch = kernel_bytes(n, prec, dom) * active
     achieved = bytes_launch / (ms * 1e-3) / 1e9
-    return {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "ms_per_launch": ms,
+    key = _kernel_key(dom, prec, n, timings[-1]["schedule"])
+    tr = measured_traffic(key)
+    # the counters were taken with all load cases active: scale to the average active count
+    traffic = None if tr is None else tr["bytes"] * active / 6.0
+    return {"kernel": dom, "instance": key, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_source": None if tr is None else tr["file"], "ms_per_launch": ms,
             "algorithmic_bytes_per_launch": bytes_launch, "active_loads_per_launch": active,
             "ms_per_kernel": {k: v / its for k, v in tot.items()}}
 
@@ -142,7 +251,12 @@ def main():
     ap.add_argument("--kernel-pass", action="store_true",
                     help="run a few profiled iterations of each path (for rocprofv3)")
     ap.add_argument("--n", type=int, default=125)
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"))
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "hbm_traffic_sweeps_c2_125.txt"))
     args = ap.parse_args()
+    if args.summarize:
+        summarize(*args.summarize, args.out)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
