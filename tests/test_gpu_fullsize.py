@@ -1,0 +1,196 @@
+"""GPU tests at the full sizes of the measured workloads.
+
+* 125^3 centred sphere (the benchmark cell): the whole count field is
+  compared with the oracle bit for bit, and one fixed-point iteration of the
+  FP64 path is compared field by field with the oracle at 1e-10.  The oracle
+  counts every voxel within the filter radius plus 2 voxels of the sphere
+  surface; all other voxels are pure, which the CPU suite pins
+  (test_pure_voxels_away_from_interface).
+* 243^3 cell with 40 spheres: sampled voxels against the oracle's counts
+  (radius 1 and 2), and properties of the batched six-load solves that hold
+  at any size (symmetry, phase bounds, mixed vs FP64 agreement).
+* 135^3 cell with 25 spheres: the adjoint gradient against central finite
+  differences (step 1e-4) of tightly converged solves, and through the
+  torch.autograd.Function.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import log, oracle_fields_to_comps, rel
+from oracle import filter as ofilter, rules as orules, solver as osolver
+from workloads import target_perturbation, workload_c2, workload_c3, workload_c5
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import paper_1412_3228_amd as hm_mod
+    assert torch.cuda.is_available() and hm_mod.device_ok()
+    return hm_mod
+
+
+def _band_oracle_filter(w, margin=2.0):
+    """Oracle counts on the voxels near the single sphere's surface; pure elsewhere."""
+    vox = ofilter.all_voxels(w.n)
+    c = w.spheres[0, :3]
+    R = w.spheres[0, 3]
+    d = np.linalg.norm(vox + 0.5 - c, axis=1)
+    near = np.abs(d - R) <= w.radius_vox + margin
+    cnt = np.where(d < R, 1, 0).astype(np.int64)
+    M = ofilter.stencil_offsets(w.radius_vox, w.subsamples, w.dim).shape[0]
+    cnt *= M
+    cb, M2 = ofilter.counts_at(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, vox[near])
+    assert M2 == M
+    cnt[near] = cb
+    frac = cnt.astype(np.float64) / np.float64(M)
+    incl = np.where((cnt > 0) & (cnt < M), 0, -1)
+    return cnt, frac, incl, M
+
+
+def test_c2_full_size_filter_and_iteration(hm):
+    w = workload_c2(100.0)
+    log("c2 full size: oracle band filter")
+    cnt_o, frac_o, incl_o, M = _band_oracle_filter(w)
+    cnt, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", DEV)
+    assert np.array_equal(cnt.cpu().numpy(), cnt_o)
+    assert np.array_equal(frac.cpu().numpy(), frac_o)
+    assert np.array_equal(incl.cpu().numpy(), incl_o)
+    log("c2 full size: one iteration, oracle vs GPU")
+    E = np.array([[0.0, 0.0, 0.0, 0.0, 0.0, 0.01], [0.01, -0.003, 0.002, 0.0, 0.001, 0.0]])
+    out = hm.hm_solve(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, E, prec="fp64", tol=0.0,
+                      max_iter=1, want_eps=True)
+    vox = ofilter.all_voxels(w.n)
+    nrm = ofilter.interface_normals(w.n, 3, w.spheres, incl_o, vox)
+    fld = osolver.StiffnessField(w.n, 3, w.phases, w.rule, frac_o, nrm)
+    c0 = osolver.reference_medium(w.phases)
+    r = osolver.solve(fld, E[0], c0, 0.0, 1)
+    sig = np.array([r["sig_mean"][i, j] for (i, j) in [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]])
+    assert rel(out["sig_mean"][0], sig) < 1e-10
+    assert abs(out["reports"][0]["err"] - r["err"]) <= 1e-10 * r["err"] + 1e-13
+    assert rel(out["eps"][0].cpu().numpy(), oracle_fields_to_comps(r["eps"])) < 1e-10
+
+
+@pytest.mark.parametrize("radius", [1.0, 2.0])
+def test_c3_filter_sampled_voxels(hm, radius):
+    w = workload_c3(radius_vox=radius)
+    log("c3 filter r=%g" % radius)
+    for prec in ("fp64", "mixed"):
+        cnt, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, prec, DEV)
+        cnt = cnt.cpu().numpy()
+        frac = frac.cpu().numpy()
+        incl = incl.cpu().numpy()
+        M = ofilter.stencil_offsets(radius, w.subsamples, 3).shape[0]
+        rng = np.random.default_rng(17)
+        mixed_idx = np.nonzero((cnt > 0) & (cnt < M))[0]
+        k = 200 if radius == 1.0 else 80
+        pick = np.concatenate([rng.choice(cnt.size, k, replace=False), rng.choice(mixed_idx, k, replace=False)])
+        vox = ofilter.all_voxels(w.n)[pick]
+        ref = ofilter.filter_field(w, "f64" if prec == "fp64" else "f32", vox)
+        assert np.array_equal(cnt[pick], ref["count"])
+        assert np.array_equal(frac[pick], ref["frac"])
+        assert np.array_equal(incl[pick], ref["incl"])
+        # realised inclusion volume fraction close to the drawn geometry's
+        assert abs(frac.astype(np.float64).mean() - w.meta["nominal_fraction"]) < 0.01
+
+
+@pytest.mark.parametrize("rule", ["laminate", "voigt", "reuss"])
+def test_c3_batched_six_loads_properties(hm, rule):
+    w = workload_c3(radius_vox=1.0, rule=rule)
+    log("c3 solve %s" % rule)
+    outs = {}
+    for prec in ("fp64", "mixed"):
+        cnt, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, prec, DEV)
+        outs[prec] = hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, prec=prec,
+                                            tol=1e-4, max_iter=3000, check_every=16,
+                                            stall_window=20 if prec == "mixed" else 0, use_graph=True)
+        del frac, incl, cnt
+    C64, C32 = outs["fp64"]["C"], outs["mixed"]["C"]
+    log("c3 %s iters fp64 %s mixed %s, mixed vs fp64 %.2e" % (
+        rule, [r["iters"] for r in outs["fp64"]["reports"]], [r["iters"] for r in outs["mixed"]["reports"]],
+        rel(C32, C64)))
+    assert all(r["status"] == 0 for r in outs["fp64"]["reports"])
+    assert rel(C64, C64.T) < 1e-5
+    assert rel(C32, C64) < 1e-5
+    Cm = orules.to_mandel(orules.iso_tensor(*w.phases[0]))
+    Ci = orules.to_mandel(orules.iso_tensor(*w.phases[1]))
+    S = 0.5 * (C64 + C64.T)
+    assert np.min(np.linalg.eigvalsh(S - Cm)) > 0
+    assert np.min(np.linalg.eigvalsh(Ci - S)) > 0
+
+
+def test_c5_gradient_against_finite_differences(hm):
+    w = workload_c5()
+    log("c5 gradient")
+    cnt, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", DEV)
+    kw = dict(prec="fp64", tol=1e-11, max_iter=6000, check_every=16, use_graph=True)
+    base = hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, want_eps=True, **kw)
+    C = base["C"]
+    u = target_perturbation(5, (6, 6))
+    Ct = C * (1.0 + 0.05 * u)
+    Ct = 0.5 * (Ct + Ct.T)
+    G = 2.0 * (C - Ct)
+    dph, dfr = hm.hm_solve_adjoint(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, G, base["eps"])
+
+    def loss(phases, fr):
+        o = hm.hm_effective_tensor(w.n, w.dim, phases, w.rule, fr, incl, w.spheres, **kw)
+        return float(np.sum((o["C"] - Ct) ** 2))
+
+    h = 1e-4
+    for q in range(4):
+        pp = [list(p) for p in w.phases]
+        pm = [list(p) for p in w.phases]
+        pp[q // 2][q % 2] += h
+        pm[q // 2][q % 2] -= h
+        fd = (loss(pp, frac) - loss(pm, frac)) / (2 * h)
+        log("dL/dtheta_%d adjoint %.10e fd %.10e" % (q, dph[q], fd))
+        assert abs(fd - dph[q]) <= 1e-6 * max(abs(fd), 1e-3)
+    cn = cnt.cpu().numpy()
+    M = ofilter.stencil_offsets(w.radius_vox, w.subsamples, 3).shape[0]
+    mixed = np.nonzero((cn > 0) & (cn < M))[0]
+    for v in mixed[[0, len(mixed) // 3, 2 * len(mixed) // 3]]:
+        fp = frac.clone()
+        fm = frac.clone()
+        fp[v] += h
+        fm[v] -= h
+        fd = (loss(w.phases, fp) - loss(w.phases, fm)) / (2 * h)
+        ad = float(dfr[v])
+        log("dL/df[%d] adjoint %.6e fd %.6e" % (v, ad, fd))
+        assert abs(fd - ad) <= 5e-3 * abs(ad) + 1e-12
+
+
+def test_c5_autograd_function_and_mixed_gradient(hm):
+    w = workload_c5()
+    log("c5 autograd")
+    cnt, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", DEV)
+    cell = {"n": w.n, "dim": 3, "rule": w.rule, "incl": incl, "spheres": w.spheres, "prec": "fp64",
+            "tol": 1e-10, "max_iter": 6000}
+    lame = torch.tensor([w.phases[0][0], w.phases[0][1], w.phases[1][0], w.phases[1][1]],
+                        dtype=torch.float64, requires_grad=True)
+    f = frac.clone().requires_grad_(True)
+    C = hm.EffectiveTensor.apply(lame, f, cell)
+    Ct = C.detach() * 1.03
+    L = torch.sum((C - Ct) ** 2)
+    L.backward()
+    G = (2.0 * (C - Ct)).detach().numpy()
+    ref = hm.hm_effective_tensor(w.n, 3, w.phases, w.rule, frac, incl, w.spheres, prec="fp64", tol=1e-10,
+                                 max_iter=6000, check_every=8, want_eps=True)
+    dph, dfr = hm.hm_solve_adjoint(w.n, 3, w.phases, w.rule, frac, incl, w.spheres, G, ref["eps"])
+    assert rel(lame.grad.numpy(), dph) < 1e-9
+    assert rel(f.grad.cpu().numpy(), dfr.cpu().numpy()) < 1e-9
+    # checkpointed variant recomputes the fields in backward
+    lame2 = lame.detach().clone().requires_grad_(True)
+    C2 = hm.EffectiveTensor.apply(lame2, frac, dict(cell, checkpoint=True))
+    torch.sum((C2 - Ct) ** 2).backward()
+    assert rel(lame2.grad.numpy(), dph) < 1e-9
+    # mixed path (FP32 fraction field): same gradient to FP32 accuracy
+    _, frac32, incl32 = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "mixed", DEV)
+    m = hm.hm_effective_tensor(w.n, 3, w.phases, w.rule, frac32, incl32, w.spheres, prec="mixed", tol=1e-4,
+                               max_iter=6000, check_every=8, stall_window=20, want_eps=True)
+    d32, f32 = hm.hm_solve_adjoint(w.n, 3, w.phases, w.rule, frac32, incl32, w.spheres, G, m["eps"], prec="mixed")
+    log("mixed vs fp64 gradient: phases %.2e" % rel(d32, dph))
+    assert rel(d32, dph) < 1e-4
