@@ -186,6 +186,7 @@ int hm_filter(const hm_grid* grid, const hm_sphere* spheres, int n_spheres,
  *          field produced by the update from the reported iterate).
  * Returns the largest status over load cases, or a negative error.
  * HM_E_DATA: a fractional voxel with HM_RULE_NONE, or d_incl out of range.
+ * n_load is at most 4096.
  */
 int hm_solve(const hm_grid* grid, const hm_iso phases[2], hm_rule rule,
              const void* d_frac, const int32_t* d_incl,
@@ -207,6 +208,34 @@ int hm_effective_tensor(const hm_grid* grid, const hm_iso phases[2], hm_rule rul
                         const hm_sphere* spheres, int n_spheres,
                         const hm_solve_opts* opts, double* C_mandel,
                         void* d_eps, hm_report* rep, void* stream);
+
+/* One cell of a batch: grid, phases, rule and its device fraction / normal
+ * fields and host sphere table, with the meanings of hm_solve. */
+typedef struct {
+  hm_grid grid;
+  hm_iso phases[2];
+  hm_rule rule;
+  const void* d_frac;
+  const int32_t* d_incl;
+  const hm_sphere* spheres;
+  int n_spheres;
+} hm_problem;
+
+/*
+ * hm_effective_tensor_batch - effective tensors of many cells at once.
+ *
+ * The cells may have different grid sizes.  Cells that share a grid are
+ * solved together: every launch of the iteration covers all load cases of
+ * all of them (each load case with its own cell's material and reference
+ * medium and its own stop decision), and the grid groups are iterated side
+ * by side (one captured graph per block of check_every iterations when
+ * opts->use_graph is set).  Outputs, in the order of `problems`:
+ * C_mandel (host, 36 doubles per 3D cell and 9 per 2D cell, row-major) and
+ * rep (host, 6 or 3 entries per cell, nullable).  Returns the largest
+ * status, or a negative error (profiling is not available for batches).
+ */
+int hm_effective_tensor_batch(const hm_problem* problems, int n_problems, const hm_solve_opts* opts,
+                              double* C_mandel, hm_report* rep, void* stream);
 
 /*
  * hm_solve_adjoint - gradient of a loss L(C_eff) with respect to the phase

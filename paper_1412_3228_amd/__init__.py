@@ -9,6 +9,7 @@ from .api import (  # noqa: F401
     EffectiveTensor,
     device_ok,
     hm_effective_tensor,
+    hm_effective_tensor_batch,
     hm_filter,
     hm_solve,
     hm_solve_adjoint,

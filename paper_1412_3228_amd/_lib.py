@@ -20,7 +20,7 @@ RULES = {"none": 0, "voigt": 1, "reuss": 2, "laminate": 3}
 PRECS = {"fp64": 0, "mixed": 1}
 
 # Every symbol include/hm.h declares.
-EXPORTS = ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_solve_adjoint",
+EXPORTS = ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_effective_tensor_batch", "hm_solve_adjoint",
            "hm_last_error", "hm_last_timing", "hm_release_plans", "hm_device_ok")
 
 
@@ -47,6 +47,11 @@ class HmTiming(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("n_load", ctypes.c_int), ("ms", ctypes.c_double * 5),
                 ("x_lines", ctypes.c_int), ("y_width", ctypes.c_int), ("z_width", ctypes.c_int),
                 ("z_threads", ctypes.c_int), ("z_groups", ctypes.c_int)]
+
+
+class HmProblem(ctypes.Structure):
+    _fields_ = [("grid", HmGrid), ("phases", HmIso * 2), ("rule", ctypes.c_int), ("d_frac", ctypes.c_void_p),
+                ("d_incl", ctypes.c_void_p), ("spheres", ctypes.POINTER(HmSphere)), ("n_spheres", ctypes.c_int)]
 
 
 class HmReport(ctypes.Structure):
@@ -80,9 +85,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                              _dp, ctypes.c_int, _P(HmSolveOpts), _vp, _dp, _P(HmReport), _vp]
     lib.hm_effective_tensor.argtypes = [_P(HmGrid), _P(HmIso), ctypes.c_int, _vp, _vp, _P(HmSphere),
                                         ctypes.c_int, _P(HmSolveOpts), _dp, _vp, _P(HmReport), _vp]
+    lib.hm_effective_tensor_batch.argtypes = [_P(HmProblem), ctypes.c_int, _P(HmSolveOpts), _dp, _P(HmReport),
+                                              _vp]
     lib.hm_solve_adjoint.argtypes = [_P(HmGrid), _P(HmIso), ctypes.c_int, _vp, _vp, _P(HmSphere),
                                      ctypes.c_int, ctypes.c_int, _dp, _vp, ctypes.c_int, _dp, _vp, _vp]
-    for f in ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_solve_adjoint", "hm_device_ok"):
+    for f in ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_effective_tensor_batch", "hm_solve_adjoint",
+              "hm_device_ok"):
         getattr(lib, f).restype = ctypes.c_int
     lib.hm_last_timing.argtypes = [_P(HmTiming)]
     lib.hm_last_timing.restype = ctypes.c_int

@@ -110,7 +110,7 @@ def hm_filter(n, dim, spheres, radius_vox: float, subsamples: int, rule: str, pr
 def hm_solve(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres, E,
              prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
              check_every: int = 1, stall_window: int = 0, use_graph: bool = False, want_eps: bool = False,
-             profile: bool = False):
+             profile: bool = False, autotune: bool = True):
     """Fixed-point solve for the rows of E (n_load x 6 tensor components)."""
     dev = frac.device
     N = int(n[0] * n[1] * n[2])
@@ -123,7 +123,7 @@ def hm_solve(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch
     eps = torch.empty((nl, 6, N), dtype=_DT[prec], device=dev) if want_eps else None
     g = _grid(n, dim)
     sph, ns = _spheres(spheres)
-    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, autotune)
     rc = _lib().hm_solve(ctypes.byref(g), _phases(phases), L.RULES[rule], _ptr(frac), _ptr(incl), sph, ns,
                          Ea.ctypes.data_as(L._dp), nl, ctypes.byref(o), _ptr(eps),
                          sig.ctypes.data_as(L._dp), rep, _stream(dev))
@@ -134,7 +134,7 @@ def hm_solve(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch
 def hm_effective_tensor(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres,
                         prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
                         check_every: int = 1, stall_window: int = 0, use_graph: bool = False,
-                        want_eps: bool = False, profile: bool = False):
+                        want_eps: bool = False, profile: bool = False, autotune: bool = True):
     """Effective Mandel tensor from the unit-strain solves (6 in 3D, 3 in 2D)."""
     dev = frac.device
     N = int(n[0] * n[1] * n[2])
@@ -146,12 +146,55 @@ def hm_effective_tensor(n, dim, phases, rule: str, frac: torch.Tensor, incl: Opt
     eps = torch.empty((k, 6, N), dtype=_DT[prec], device=dev) if want_eps else None
     g = _grid(n, dim)
     sph, ns = _spheres(spheres)
-    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, autotune)
     rc = _lib().hm_effective_tensor(ctypes.byref(g), _phases(phases), L.RULES[rule], _ptr(frac), _ptr(incl),
                                     sph, ns, ctypes.byref(o), C.ctypes.data_as(L._dp), _ptr(eps), rep,
                                     _stream(dev))
     L.check(rc)
     return {"status": rc, "C": C, "reports": _reports(rep, k), "eps": eps}
+
+
+def hm_effective_tensor_batch(problems, prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000,
+                              c0_alpha: float = 1.0, check_every: int = 16, stall_window: int = 0,
+                              use_graph: bool = True, autotune: bool = True):
+    """Effective tensors of many cells (dicts with n, dim, phases, rule, frac, incl, spheres) in one batch."""
+    if not problems:
+        raise ValueError("no problems")
+    dev = problems[0]["frac"].device
+    arr = (L.HmProblem * len(problems))()
+    keep = []
+    ks = []
+    for i, pr in enumerate(problems):
+        n = pr["n"]
+        N = int(n[0] * n[1] * n[2])
+        _check_field(pr["frac"], N, _DT[prec], dev, "frac")
+        _check_field(pr.get("incl"), N, torch.int32, dev, "incl")
+        arr[i].grid = _grid(n, pr["dim"])
+        ph = _phases(pr["phases"])
+        arr[i].phases[0] = ph[0]
+        arr[i].phases[1] = ph[1]
+        arr[i].rule = L.RULES[pr["rule"]]
+        arr[i].d_frac = pr["frac"].data_ptr()
+        arr[i].d_incl = 0 if pr.get("incl") is None else pr["incl"].data_ptr()
+        sph, ns = _spheres(pr["spheres"])
+        keep.append(sph)
+        arr[i].spheres = ctypes.cast(sph, ctypes.POINTER(L.HmSphere))
+        arr[i].n_spheres = ns
+        ks.append(3 if pr["dim"] == 2 else 6)
+    C = np.zeros(sum(k * k for k in ks))
+    rep = (L.HmReport * sum(ks))()
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, False, autotune)
+    rc = _lib().hm_effective_tensor_batch(arr, len(problems), ctypes.byref(o), C.ctypes.data_as(L._dp), rep,
+                                          _stream(dev))
+    L.check(rc)
+    out = []
+    co = ro = 0
+    allrep = _reports(rep, sum(ks))
+    for k in ks:
+        out.append({"C": C[co:co + k * k].reshape(k, k).copy(), "reports": allrep[ro:ro + k]})
+        co += k * k
+        ro += k
+    return {"status": rc, "results": out}
 
 
 def hm_solve_adjoint(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres,

@@ -81,7 +81,7 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(HM_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int kMaxLoads = 8;
+constexpr int kMaxLoads = 4096;  // load cases per grid group (the y-sweep grid has 6 per load)
 
 bool supported_length(int n) {
   if (n < 1 || n > 243) return false;
@@ -177,10 +177,9 @@ struct Plan {
   SolverState* state_host = nullptr;  // pinned
   double* errhist = nullptr;
   int hist_cap = 0;
-  SolveParams* prm = nullptr;
-  SolveParams* prm_host = nullptr;  // pinned staging
-  double* sph = nullptr;
-  int sph_cap = 0;
+  char* prm = nullptr;       // parameter blob: SolveParams, loads, problems, spheres
+  char* prm_host = nullptr;  // pinned staging of the blob
+  size_t prm_cap = 0;
   void* tw[3] = {nullptr, nullptr, nullptr};
   SolveArgs args;
   hipStream_t cap_stream = nullptr;
@@ -201,7 +200,6 @@ void free_plan(Plan* p) {
   (void)hipFree(p->state);
   (void)hipFree(p->errhist);
   (void)hipFree(p->prm);
-  (void)hipFree(p->sph);
   for (int a = 0; a < 3; ++a) (void)hipFree(p->tw[a]);
   if (p->state_host) (void)hipHostFree(p->state_host);
   if (p->prm_host) (void)hipHostFree(p->prm_host);
@@ -272,14 +270,11 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, Plan** out) {
   if (!rc) rc = device_alloc((void**)&p->taupart, (size_t)n_load * g2 * 6 * sizeof(double), "tau partials");
   if (!rc) rc = device_alloc((void**)&p->errpart, (size_t)n_load * n[1] * ntx4 * sizeof(double), "error partials");
   if (!rc) rc = device_alloc((void**)&p->state, (size_t)n_load * sizeof(SolverState), "state");
-  if (!rc) rc = device_alloc((void**)&p->prm, sizeof(SolveParams), "params");
   if (!rc) rc = upload_twiddles(p, 0, n[0]);
   if (!rc) rc = upload_twiddles(p, 1, n[1]);
   if (!rc) rc = upload_twiddles(p, 2, n[2]);
   if (!rc && hipHostMalloc((void**)&p->state_host, (size_t)n_load * sizeof(SolverState), 0) != hipSuccess)
     rc = fail(HM_E_NOMEM, "pinned state buffer");
-  if (!rc && hipHostMalloc((void**)&p->prm_host, sizeof(SolveParams), 0) != hipSuccess)
-    rc = fail(HM_E_NOMEM, "pinned params buffer");
   if (rc) {
     free_plan(p);
     return rc;
@@ -291,7 +286,6 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, Plan** out) {
   a.taupart = p->taupart;
   a.errpart = p->errpart;
   a.state = p->state;
-  a.prm = p->prm;
   a.twx = p->tw[0];
   a.twy = p->tw[1];
   a.twz = p->tw[2];
@@ -339,17 +333,6 @@ int ensure_hist(Plan* p, int cap) {
   return HM_OK;
 }
 
-int ensure_spheres(Plan* p, int ns) {
-  if (p->sph_cap >= ns && p->sph) return HM_OK;
-  if (p->sph) (void)hipFree(p->sph);
-  p->sph = nullptr;
-  const int cap = ns > 16 ? ns : 16;
-  int rc = device_alloc((void**)&p->sph, (size_t)cap * 4 * sizeof(double), "sphere table");
-  if (rc) return rc;
-  p->sph_cap = cap;
-  return HM_OK;
-}
-
 hipError_t launch_iteration(Plan* p, const SolveArgs& a, bool first, hipStream_t s) {
   hipError_t e;
   if ((e = (first ? p->X->first : p->X->iter)(a, s)) != hipSuccess) return e;
@@ -360,12 +343,38 @@ hipError_t launch_iteration(Plan* p, const SolveArgs& a, bool first, hipStream_t
   return hipGetLastError();
 }
 
+// Copies the stop flags of the plan's load cases to the host (stream synchronised).
 int poll_done(Plan* p, hipStream_t s, bool* all_done) {
   HM_HIP(hipMemcpyAsync(p->state_host, p->state, (size_t)p->n_load * sizeof(SolverState), hipMemcpyDeviceToHost, s));
   HM_HIP(hipStreamSynchronize(s));
   bool d = true;
   for (int l = 0; l < p->n_load; ++l) d = d && p->state_host[l].done;
   *all_done = d;
+  return HM_OK;
+}
+
+// Captures k iterations of each listed plan (in order) into an executable graph.
+int capture_graph(std::vector<Plan*>& plans, int k, hipStream_t cap, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  HM_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  for (int i = 0; i < k && le == hipSuccess; ++i)
+    for (Plan* p : plans) {
+      SolveArgs a = p->args;
+      a.first = 0;
+      if (le == hipSuccess) le = launch_iteration(p, a, false, cap);
+    }
+  hipError_t ce = hipStreamEndCapture(cap, &g);
+  if (le != hipSuccess || ce != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(HM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(le != hipSuccess ? le : ce));
+  }
+  hipError_t ie = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    *out = nullptr;
+    return fail(HM_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ie));
+  }
   return HM_OK;
 }
 
@@ -376,127 +385,11 @@ int build_graph(Plan* p, int k) {
     p->graph = nullptr;
   }
   if (!p->cap_stream) HM_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
-  SolveArgs a = p->args;
-  a.first = 0;
-  hipGraph_t g = nullptr;
-  HM_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-  hipError_t le = hipSuccess;
-  for (int i = 0; i < k && le == hipSuccess; ++i) le = launch_iteration(p, a, false, p->cap_stream);
-  hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
-  if (le != hipSuccess || ce != hipSuccess) {
-    if (g) (void)hipGraphDestroy(g);
-    return fail(HM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(le != hipSuccess ? le : ce));
-  }
-  hipError_t ie = hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (ie != hipSuccess) {
-    p->graph = nullptr;
-    return fail(HM_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ie));
-  }
+  std::vector<Plan*> one{p};
+  int rc = capture_graph(one, k, p->cap_stream, &p->graph);
+  if (rc) return rc;
   p->graph_k = k;
   return HM_OK;
-}
-
-int finish_solve(Plan* p, SolveArgs a, hipStream_t s, void* d_eps, double* sig_mean, hm_report* rep,
-                 std::chrono::steady_clock::time_point t0) {
-  int rc;
-  bool done = false;
-  if (d_eps) {
-    a.eps_out = d_eps;
-    HM_HIP(p->X->exp(a, s));
-  }
-  if ((rc = poll_done(p, s, &done))) return rc;
-  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  int worst = HM_OK;
-  int flags = 0;
-  for (int l = 0; l < p->n_load; ++l) {
-    const SolverState& st = p->state_host[l];
-    for (int c = 0; c < 6; ++c) sig_mean[6 * l + c] = st.sig[c];
-    const int status = st.done ? st.status : HM_NOT_CONVERGED;
-    if (rep) {
-      rep[l].iters = st.iters;
-      rep[l].status = status;
-      rep[l].err = st.err;
-      rep[l].err0 = st.err0;
-      rep[l].seconds = secs;
-    }
-    if (status > worst) worst = status;
-    flags |= st.flags;
-  }
-  if (flags & FLAG_NONE_FRACTIONAL) return fail(HM_E_DATA, "fractional voxel with HM_RULE_NONE");
-  if (flags & FLAG_BAD_INCL) return fail(HM_E_DATA, "d_incl holds a sphere index >= n_spheres");
-  return worst;
-}
-
-// Direct launches with a HIP event before and after every kernel; durations
-// are read back at each poll and averaged over the iterations that the
-// longest load case evaluated.
-int profiled_loop(Plan* p, SolveArgs a, const hm_solve_opts* opts, hipStream_t s, void* d_eps, double* sig_mean,
-                  hm_report* rep, std::chrono::steady_clock::time_point t0) {
-  const int k = opts->check_every;
-  std::vector<hipEvent_t> ev((size_t)6 * k, nullptr);
-  for (auto& e : ev)
-    if (hipEventCreate(&e) != hipSuccess) {
-      for (auto& q : ev)
-        if (q) (void)hipEventDestroy(q);
-      return fail(HM_E_DEVICE, "hipEventCreate failed");
-    }
-  std::vector<double> dur;  // 5 per iteration
-  bool done = false;
-  int it = 0, rc = HM_OK;
-  hipError_t err = hipSuccess;
-  while (!done && it <= opts->max_iter && err == hipSuccess && rc == HM_OK) {
-    int nb = 0;
-    for (; nb < k && it <= opts->max_iter; ++nb, ++it) {
-      hipEvent_t* e = &ev[(size_t)6 * nb];
-      a.first = it == 0 ? 1 : 0;
-      err = hipEventRecord(e[0], s);
-      if (err == hipSuccess) err = (it == 0 ? p->X->first : p->X->iter)(a, s);
-      if (err == hipSuccess) err = hipEventRecord(e[1], s);
-      if (err == hipSuccess) err = p->Y->fwd(a, s);
-      if (err == hipSuccess) err = hipEventRecord(e[2], s);
-      if (err == hipSuccess) err = p->Z->run(a, s);
-      if (err == hipSuccess) err = hipEventRecord(e[3], s);
-      if (err == hipSuccess) err = p->Y->inv(a, s);
-      if (err == hipSuccess) err = hipEventRecord(e[4], s);
-      if (err == hipSuccess) {
-        hipLaunchKernelGGL((k_finalize<kFinalizeThreads>), dim3(a.n_load), dim3(kFinalizeThreads), 0, s, a);
-        err = hipGetLastError();
-      }
-      if (err == hipSuccess) err = hipEventRecord(e[5], s);
-      if (err != hipSuccess) break;
-    }
-    if (err != hipSuccess) break;
-    rc = poll_done(p, s, &done);
-    for (int b = 0; b < nb && rc == HM_OK; ++b) {
-      for (int q = 0; q < 5; ++q) {
-        float ms = 0.0f;
-        err = hipEventElapsedTime(&ms, ev[(size_t)6 * b + q], ev[(size_t)6 * b + q + 1]);
-        dur.push_back((double)ms);
-      }
-    }
-  }
-  for (auto& e : ev) (void)hipEventDestroy(e);
-  if (err != hipSuccess) return fail(HM_E_DEVICE, "profiled loop: %s", hipGetErrorString(err));
-  if (rc) return rc;
-  int last = 0;
-  for (int l = 0; l < p->n_load; ++l) last = std::max(last, p->state_host[l].iters);
-  const int nit = std::min((int)(dur.size() / 5), last + 1);
-  hm_timing t;
-  memset(&t, 0, sizeof t);
-  t.iterations = nit;
-  t.n_load = p->n_load;
-  t.x_lines = p->X->lines;
-  t.y_width = p->Y->width;
-  t.z_width = p->Z->width;
-  t.z_threads = p->Z->threads;
-  t.z_groups = p->Z->groups;
-  for (int i = 0; i < nit; ++i)
-    for (int q = 0; q < 5; ++q) t.ms[q] += dur[(size_t)5 * i + q];
-  for (int q = 0; q < 5; ++q) t.ms[q] /= nit > 0 ? nit : 1;
-  g_last_timing = t;
-  g_have_timing = true;
-  return finish_solve(p, a, s, d_eps, sig_mean, rep, t0);
 }
 
 // Times every compiled schedule of the three sweeps on this plan's own
@@ -511,7 +404,7 @@ int tune_plan(Plan* p, hipStream_t s) {
   const size_t plane = (size_t)p->n[2] * p->n[1] * p->args.Hp;
   hipError_t err = hipMemsetAsync(p->spec, 0, (size_t)p->n_load * 6 * plane * cplx, s);
   if (err == hipSuccess) err = hipMemsetAsync(p->hist, 0, (size_t)p->n_load * 3 * plane * cplx, s);
-  hipLaunchKernelGGL((k_reset_state<64>), dim3(1), dim3(64), 0, s, p->state, p->n_load);
+  hipLaunchKernelGGL((k_reset_state<64>), dim3((p->n_load + 63) / 64), dim3(64), 0, s, p->state, p->n_load);
   if (err == hipSuccess) err = hipGetLastError();
   auto time_it = [&](solve_launch_fn f, const SolveArgs& a, float* best) -> hipError_t {
     hipError_t e = f(a, s);  // warm-up
@@ -567,91 +460,351 @@ int tune_plan(Plan* p, hipStream_t s) {
   return HM_OK;
 }
 
-// The solve shared by hm_solve and hm_effective_tensor.
-int solve_impl(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,
-               const int32_t* d_incl, const hm_sphere* spheres, int n_spheres, const double* E, int n_load,
-               const hm_solve_opts* opts, void* d_eps, double* sig_mean, hm_report* rep, hipStream_t s) {
-  const auto t0 = std::chrono::steady_clock::now();
+// One problem (cell) of a solve, as given by the caller.
+struct ProblemIn {
+  hm_grid grid;
+  hm_iso phases[2];
+  hm_rule rule;
+  const void* frac;
+  const int32_t* incl;
+  const hm_sphere* sph;
+  int nsph;
+};
+
+// The load cases of one or more problems sharing a grid, solved together.
+struct Group {
+  Plan* p = nullptr;
+  std::vector<int> probs;         // indices into the problem list
+  std::vector<LoadParams> loads;  // LoadParams::prob indexes `probs`
+  void* eps_out = nullptr;        // export target (nullable)
+  bool active = true;
+};
+
+int check_problem(const ProblemIn& d) {
   int rc;
-  if ((rc = check_grid(grid))) return rc;
-  if ((rc = check_phases(phases))) return rc;
+  if ((rc = check_grid(&d.grid))) return rc;
+  if ((rc = check_phases(d.phases))) return rc;
+  if ((rc = check_spheres(&d.grid, d.sph, d.nsph))) return rc;
+  if (d.rule < HM_RULE_NONE || d.rule > HM_RULE_LAMINATE) return fail(HM_E_ARG, "unknown rule %d", (int)d.rule);
+  if (!d.frac) return fail(HM_E_ARG, "d_frac is NULL");
+  if (d.rule == HM_RULE_LAMINATE && !d.incl) return fail(HM_E_ARG, "the 2-layer rule needs d_incl");
+  return HM_OK;
+}
+
+size_t align16(size_t v) { return (v + 15) / 16 * 16; }
+
+// Writes the group's parameter blob (header, loads, problems, sphere tables)
+// to pinned staging and queues its copy to the plan's device buffer.
+int upload_params(Group& g, const std::vector<ProblemIn>& all, const hm_solve_opts* opts, hipStream_t s) {
+  Plan* p = g.p;
+  const int nl = (int)g.loads.size(), np = (int)g.probs.size();
+  size_t nsph_tot = 0;
+  for (int q : g.probs) nsph_tot += (size_t)all[q].nsph;
+  const size_t o_loads = align16(sizeof(SolveParams));
+  const size_t o_probs = align16(o_loads + nl * sizeof(LoadParams));
+  const size_t o_sph = align16(o_probs + np * sizeof(ProblemParams));
+  const size_t bytes = o_sph + nsph_tot * 4 * sizeof(double) + 16;
+  if (bytes > p->prm_cap) {
+    (void)hipFree(p->prm);
+    if (p->prm_host) (void)hipHostFree(p->prm_host);
+    p->prm = nullptr;
+    p->prm_host = nullptr;
+    p->prm_cap = 0;
+    const size_t cap = std::max(bytes, (size_t)4096);
+    int rc = device_alloc((void**)&p->prm, cap, "parameters");
+    if (rc) return rc;
+    if (hipHostMalloc((void**)&p->prm_host, cap, 0) != hipSuccess) return fail(HM_E_NOMEM, "pinned parameters");
+    p->prm_cap = cap;
+    p->args.prm = reinterpret_cast<const SolveParams*>(p->prm);
+    if (p->graph) {
+      (void)hipGraphExecDestroy(p->graph);
+      p->graph = nullptr;
+    }
+  }
+  char* h = p->prm_host;
+  memset(h, 0, bytes);
+  SolveParams* S = reinterpret_cast<SolveParams*>(h);
+  S->tol = opts->tol;
+  S->max_iter = opts->max_iter;
+  S->stall_window = opts->stall_window;
+  S->n_load = nl;
+  S->n_prob = np;
+  S->loads = reinterpret_cast<const LoadParams*>(p->prm + o_loads);
+  S->probs = reinterpret_cast<const ProblemParams*>(p->prm + o_probs);
+  memcpy(h + o_loads, g.loads.data(), nl * sizeof(LoadParams));
+  ProblemParams* PP = reinterpret_cast<ProblemParams*>(h + o_probs);
+  double* sph = reinterpret_cast<double*>(h + o_sph);
+  size_t so = 0;
+  for (int j = 0; j < np; ++j) {
+    const ProblemIn& d = all[g.probs[j]];
+    ProblemParams& q = PP[j];
+    for (int ph = 0; ph < 2; ++ph) {
+      q.pl[ph] = d.phases[ph].lambda;
+      q.pm[ph] = d.phases[ph].mu;
+    }
+    const double lmin = fmin(q.pl[0], q.pl[1]), lmax = fmax(q.pl[0], q.pl[1]);
+    const double mmin = fmin(q.pm[0], q.pm[1]), mmax = fmax(q.pm[0], q.pm[1]);
+    q.rl = opts->c0_alpha * 0.5 * (lmin + lmax);
+    q.rm = opts->c0_alpha * 0.5 * (mmin + mmax);
+    if (!(q.rm > 0.0) || !(q.rl + 2.0 * q.rm > 0.0)) return fail(HM_E_ARG, "reference medium is not positive");
+    q.rule = (int)d.rule;
+    q.nsph = d.nsph;
+    q.frac = d.frac;
+    q.incl = d.incl;
+    q.sph = reinterpret_cast<const double*>(p->prm + o_sph) + so;
+    for (int k = 0; k < d.nsph; ++k) {
+      for (int c = 0; c < 3; ++c) sph[so + 4 * k + c] = d.sph[k].c[c];
+      sph[so + 4 * k + 3] = d.sph[k].r;
+    }
+    so += 4 * (size_t)d.nsph;
+  }
+  HM_HIP(hipMemcpyAsync(p->prm, p->prm_host, bytes, hipMemcpyHostToDevice, s));
+  return HM_OK;
+}
+
+// Direct launches with a HIP event before and after every kernel of one
+// group; durations are read back at each poll and averaged over the
+// iterations that the longest load case evaluated.
+int profiled_loop(Plan* p, const hm_solve_opts* opts, hipStream_t s) {
+  const int k = opts->check_every;
+  std::vector<hipEvent_t> ev((size_t)6 * k, nullptr);
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& q : ev)
+        if (q) (void)hipEventDestroy(q);
+      return fail(HM_E_DEVICE, "hipEventCreate failed");
+    }
+  SolveArgs a = p->args;
+  std::vector<double> dur;  // 5 per iteration
+  bool done = false;
+  int it = 0, rc = HM_OK;
+  hipError_t err = hipSuccess;
+  while (!done && it <= opts->max_iter && err == hipSuccess && rc == HM_OK) {
+    int nb = 0;
+    for (; nb < k && it <= opts->max_iter; ++nb, ++it) {
+      hipEvent_t* e = &ev[(size_t)6 * nb];
+      a.first = it == 0 ? 1 : 0;
+      err = hipEventRecord(e[0], s);
+      if (err == hipSuccess) err = (it == 0 ? p->X->first : p->X->iter)(a, s);
+      if (err == hipSuccess) err = hipEventRecord(e[1], s);
+      if (err == hipSuccess) err = p->Y->fwd(a, s);
+      if (err == hipSuccess) err = hipEventRecord(e[2], s);
+      if (err == hipSuccess) err = p->Z->run(a, s);
+      if (err == hipSuccess) err = hipEventRecord(e[3], s);
+      if (err == hipSuccess) err = p->Y->inv(a, s);
+      if (err == hipSuccess) err = hipEventRecord(e[4], s);
+      if (err == hipSuccess) {
+        hipLaunchKernelGGL((k_finalize<kFinalizeThreads>), dim3(a.n_load), dim3(kFinalizeThreads), 0, s, a);
+        err = hipGetLastError();
+      }
+      if (err == hipSuccess) err = hipEventRecord(e[5], s);
+      if (err != hipSuccess) break;
+    }
+    if (err != hipSuccess) break;
+    rc = poll_done(p, s, &done);
+    for (int b = 0; b < nb && rc == HM_OK; ++b) {
+      for (int q = 0; q < 5; ++q) {
+        float ms = 0.0f;
+        err = hipEventElapsedTime(&ms, ev[(size_t)6 * b + q], ev[(size_t)6 * b + q + 1]);
+        dur.push_back((double)ms);
+      }
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (err != hipSuccess) return fail(HM_E_DEVICE, "profiled loop: %s", hipGetErrorString(err));
+  if (rc) return rc;
+  int last = 0;
+  for (int l = 0; l < p->n_load; ++l) last = std::max(last, p->state_host[l].iters);
+  const int nit = std::min((int)(dur.size() / 5), last + 1);
+  hm_timing t;
+  memset(&t, 0, sizeof t);
+  t.iterations = nit;
+  t.n_load = p->n_load;
+  t.x_lines = p->X->lines;
+  t.y_width = p->Y->width;
+  t.z_width = p->Z->width;
+  t.z_threads = p->Z->threads;
+  t.z_groups = p->Z->groups;
+  for (int i = 0; i < nit; ++i)
+    for (int q = 0; q < 5; ++q) t.ms[q] += dur[(size_t)5 * i + q];
+  for (int q = 0; q < 5; ++q) t.ms[q] /= nit > 0 ? nit : 1;
+  g_last_timing = t;
+  g_have_timing = true;
+  return HM_OK;
+}
+
+// Solves every group to its stop (or max_iter): iterate 0 directly, then
+// blocks of check_every iterations (one captured graph over all active
+// groups, or direct launches), polling the device-side stop flags between
+// blocks.  On return every group's state_host holds its final states.
+int run_groups(std::vector<Group>& G, const std::vector<ProblemIn>& all, const hm_solve_opts* opts, hipStream_t s) {
+  int rc;
+  for (Group& g : G) {
+    if ((rc = ensure_hist(g.p, opts->max_iter + 1))) return rc;
+    if ((rc = upload_params(g, all, opts, s))) return rc;
+    if (opts->autotune && !g.p->tuned)
+      if ((rc = tune_plan(g.p, s))) return rc;
+    hipLaunchKernelGGL((k_reset_state<64>), dim3((g.p->n_load + 63) / 64), dim3(64), 0, s, g.p->state,
+                       g.p->n_load);
+    HM_HIP(hipGetLastError());
+    g.active = true;
+  }
+  if (opts->profile) {
+    if (G.size() != 1) return fail(HM_E_ARG, "profiling times a single grid group");
+    if ((rc = profiled_loop(G[0].p, opts, s))) return rc;
+  } else {
+    const int k = opts->check_every;
+    for (Group& g : G) {
+      SolveArgs a = g.p->args;
+      a.first = 1;
+      HM_HIP(launch_iteration(g.p, a, true, s));
+    }
+    auto poll_all = [&](int* n_active, bool* changed) -> int {
+      *n_active = 0;
+      *changed = false;
+      for (Group& g : G) {
+        if (!g.active) continue;
+        bool d = false;
+        int r = poll_done(g.p, s, &d);
+        if (r) return r;
+        if (d) {
+          g.active = false;
+          *changed = true;
+        } else {
+          ++*n_active;
+        }
+      }
+      return HM_OK;
+    };
+    int n_active = (int)G.size();
+    bool changed = false;
+    if (opts->max_iter == 0 || k == 1)
+      if ((rc = poll_all(&n_active, &changed))) return rc;
+    int it = 1;
+    hipGraphExec_t multi = nullptr;
+    hipStream_t cap = nullptr;
+    while (n_active > 0 && it <= opts->max_iter) {
+      if (opts->use_graph) {
+        if (G.size() == 1) {
+          if ((rc = build_graph(G[0].p, k))) return rc;
+          HM_HIP(hipGraphLaunch(G[0].p->graph, s));
+        } else {
+          if (!multi || changed) {
+            if (multi) (void)hipGraphExecDestroy(multi);
+            multi = nullptr;
+            if (!cap) HM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            std::vector<Plan*> act;
+            for (Group& g : G)
+              if (g.active) act.push_back(g.p);
+            if ((rc = capture_graph(act, k, cap, &multi))) {
+              (void)hipStreamDestroy(cap);
+              return rc;
+            }
+          }
+          hipError_t e = hipGraphLaunch(multi, s);
+          if (e != hipSuccess) {
+            (void)hipGraphExecDestroy(multi);
+            (void)hipStreamDestroy(cap);
+            return fail(HM_E_DEVICE, "graph launch: %s", hipGetErrorString(e));
+          }
+        }
+        it += k;
+      } else {
+        for (int b = 0; b < k && it <= opts->max_iter; ++b, ++it)
+          for (Group& g : G)
+            if (g.active) {
+              SolveArgs a = g.p->args;
+              a.first = 0;
+              HM_HIP(launch_iteration(g.p, a, false, s));
+            }
+      }
+      if ((rc = poll_all(&n_active, &changed))) break;
+    }
+    if (multi) (void)hipGraphExecDestroy(multi);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (rc) return rc;
+  }
+  for (Group& g : G) {
+    if (g.eps_out) {
+      SolveArgs a = g.p->args;
+      a.eps_out = g.eps_out;
+      HM_HIP(g.p->X->exp(a, s));
+    }
+    bool d = false;
+    if ((rc = poll_done(g.p, s, &d))) return rc;
+  }
+  return HM_OK;
+}
+
+// Status of one load case and the data flags of a group.
+int load_status(const SolverState& st) { return st.done ? st.status : HM_NOT_CONVERGED; }
+
+int data_flags_error(int flags) {
+  if (flags & FLAG_NONE_FRACTIONAL) return fail(HM_E_DATA, "fractional voxel with HM_RULE_NONE");
+  if (flags & FLAG_BAD_INCL) return fail(HM_E_DATA, "d_incl holds a sphere index >= n_spheres");
+  return HM_OK;
+}
+
+// Unit Mandel strains (tensor components) of a dimension: 6 in 3D, 3 in 2D.
+int unit_loads(int dim, double E[36], const int** idx_out) {
+  static const int idx3[6] = {0, 1, 2, 3, 4, 5};
+  static const int idx2[3] = {0, 1, 5};
+  const int k = dim == 2 ? 3 : 6;
+  const int* idx = dim == 2 ? idx2 : idx3;
+  const double r2 = 1.0 / sqrt(2.0);
+  for (int i = 0; i < 36; ++i) E[i] = 0.0;
+  for (int J = 0; J < k; ++J) E[6 * J + idx[J]] = idx[J] < 3 ? 1.0 : r2;
+  *idx_out = idx;
+  return k;
+}
+
+// Mandel matrix from the mean stresses of the unit strains.
+void assemble_mandel(int k, const int* idx, const SolverState* st, double* C) {
+  const double w[6] = {1.0, 1.0, 1.0, sqrt(2.0), sqrt(2.0), sqrt(2.0)};
+  for (int I = 0; I < k; ++I)
+    for (int J = 0; J < k; ++J) C[I * k + J] = w[idx[I]] * st[J].sig[idx[I]];
+}
+
+// The single-problem solve shared by hm_solve and hm_effective_tensor.
+int solve_one(const ProblemIn& d, const double* E, int n_load, const hm_solve_opts* opts, void* d_eps,
+              hipStream_t s, Plan** plan_out) {
+  int rc;
+  if ((rc = check_problem(d))) return rc;
   if ((rc = check_opts(opts))) return rc;
-  if ((rc = check_spheres(grid, spheres, n_spheres))) return rc;
-  if (rule < HM_RULE_NONE || rule > HM_RULE_LAMINATE) return fail(HM_E_ARG, "unknown rule %d", (int)rule);
-  if (!d_frac) return fail(HM_E_ARG, "d_frac is NULL");
-  if (rule == HM_RULE_LAMINATE && !d_incl) return fail(HM_E_ARG, "the 2-layer rule needs d_incl");
   if (n_load < 1 || n_load > kMaxLoads) return fail(HM_E_ARG, "n_load must be in 1..%d", kMaxLoads);
-  if (!E || !sig_mean) return fail(HM_E_ARG, "E and sig_mean must not be NULL");
   for (int i = 0; i < 6 * n_load; ++i)
     if (!isfinite(E[i])) return fail(HM_E_ARG, "E has a non-finite entry");
-  const bool fp64 = opts->prec == HM_FP64;
-  Plan* p = nullptr;
-  if ((rc = get_plan(fp64, grid->n, grid->dim, n_load, &p))) return rc;
-  if ((rc = ensure_hist(p, opts->max_iter + 1))) return rc;
-  if ((rc = ensure_spheres(p, n_spheres))) return rc;
-
-  SolveParams& P = *p->prm_host;
-  memset(&P, 0, sizeof P);
-  P.pl[0] = phases[0].lambda;
-  P.pl[1] = phases[1].lambda;
-  P.pm[0] = phases[0].mu;
-  P.pm[1] = phases[1].mu;
-  const double lmin = fmin(phases[0].lambda, phases[1].lambda), lmax = fmax(phases[0].lambda, phases[1].lambda);
-  const double mmin = fmin(phases[0].mu, phases[1].mu), mmax = fmax(phases[0].mu, phases[1].mu);
-  P.rl = opts->c0_alpha * 0.5 * (lmin + lmax);
-  P.rm = opts->c0_alpha * 0.5 * (mmin + mmax);
-  if (!(P.rm > 0.0) || !(P.rl + 2.0 * P.rm > 0.0)) return fail(HM_E_ARG, "reference medium is not positive");
-  P.tol = opts->tol;
-  P.max_iter = opts->max_iter;
-  P.stall_window = opts->stall_window;
-  P.rule = (int)rule;
-  P.nsph = n_spheres;
-  P.frac = d_frac;
-  P.incl = d_incl;
-  P.sph = p->sph;
-  for (int i = 0; i < 6 * n_load; ++i) P.E[i] = E[i];
-
-  std::vector<double> sph(4 * (size_t)(n_spheres > 0 ? n_spheres : 1), 0.0);
-  for (int k = 0; k < n_spheres; ++k) {
-    for (int a = 0; a < 3; ++a) sph[4 * k + a] = spheres[k].c[a];
-    sph[4 * k + 3] = spheres[k].r;
+  std::vector<ProblemIn> all{d};
+  std::vector<Group> G(1);
+  if ((rc = get_plan(opts->prec == HM_FP64, d.grid.n, d.grid.dim, n_load, &G[0].p))) return rc;
+  G[0].probs = {0};
+  G[0].loads.resize(n_load);
+  for (int l = 0; l < n_load; ++l) {
+    for (int c = 0; c < 6; ++c) G[0].loads[l].E[c] = E[6 * l + c];
+    G[0].loads[l].prob = 0;
+    G[0].loads[l].pad = 0;
   }
-  if (n_spheres > 0)
-    HM_HIP(hipMemcpyAsync(p->sph, sph.data(), (size_t)n_spheres * 4 * sizeof(double), hipMemcpyHostToDevice, s));
-  HM_HIP(hipMemcpyAsync(p->prm, p->prm_host, sizeof(SolveParams), hipMemcpyHostToDevice, s));
-  if (opts->autotune && !p->tuned)
-    if ((rc = tune_plan(p, s))) return rc;
-  hipLaunchKernelGGL((k_reset_state<64>), dim3(1), dim3(64), 0, s, p->state, n_load);
-  HM_HIP(hipGetLastError());
+  G[0].eps_out = d_eps;
+  if ((rc = run_groups(G, all, opts, s))) return rc;
+  *plan_out = G[0].p;
+  return HM_OK;
+}
 
-  SolveArgs a = p->args;
-  const int k = opts->check_every;
-  bool done = false;
-  if (opts->profile) return profiled_loop(p, a, opts, s, d_eps, sig_mean, rep, t0);
-  a.first = 1;
-  HM_HIP(launch_iteration(p, a, true, s));
-  a.first = 0;
-  int it = 1;
-  if (opts->max_iter == 0 || k == 1) {
-    if ((rc = poll_done(p, s, &done))) return rc;
+ProblemIn make_problem(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,
+                       const int32_t* d_incl, const hm_sphere* spheres, int n_spheres) {
+  ProblemIn d;
+  memset(&d, 0, sizeof d);
+  if (grid) d.grid = *grid;
+  if (phases) {
+    d.phases[0] = phases[0];
+    d.phases[1] = phases[1];
   }
-  if (opts->use_graph && !done && opts->max_iter > 0) {
-    if ((rc = build_graph(p, k))) return rc;
-    while (!done && it <= opts->max_iter) {
-      HM_HIP(hipGraphLaunch(p->graph, s));
-      it += k;
-      if ((rc = poll_done(p, s, &done))) return rc;
-    }
-  } else {
-    while (!done && it <= opts->max_iter) {
-      HM_HIP(launch_iteration(p, a, false, s));
-      ++it;
-      if (it % k == 0 || it > opts->max_iter)
-        if ((rc = poll_done(p, s, &done))) return rc;
-    }
-  }
-  if (!done && (rc = poll_done(p, s, &done))) return rc;
-  return finish_solve(p, a, s, d_eps, sig_mean, rep, t0);
+  d.rule = rule;
+  d.frac = d_frac;
+  d.incl = d_incl;
+  d.sph = spheres;
+  d.nsph = n_spheres;
+  return d;
 }
 
 }  // namespace
@@ -759,32 +912,130 @@ int hm_filter(const hm_grid* grid, const hm_sphere* spheres, int n_spheres, doub
 int hm_solve(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac, const int32_t* d_incl,
              const hm_sphere* spheres, int n_spheres, const double* E, int n_load, const hm_solve_opts* opts,
              void* d_eps, double* sig_mean, hm_report* rep, void* stream) {
-  return solve_impl(grid, phases, rule, d_frac, d_incl, spheres, n_spheres, E, n_load, opts, d_eps, sig_mean, rep,
-                    (hipStream_t)stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!phases) return fail(HM_E_ARG, "phases is NULL");
+  if (!E || !sig_mean) return fail(HM_E_ARG, "E and sig_mean must not be NULL");
+  Plan* p = nullptr;
+  int rc = solve_one(make_problem(grid, phases, rule, d_frac, d_incl, spheres, n_spheres), E, n_load, opts, d_eps,
+                     (hipStream_t)stream, &p);
+  if (rc) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = HM_OK, flags = 0;
+  for (int l = 0; l < n_load; ++l) {
+    const SolverState& st = p->state_host[l];
+    for (int c = 0; c < 6; ++c) sig_mean[6 * l + c] = st.sig[c];
+    const int status = load_status(st);
+    if (rep) rep[l] = hm_report{st.iters, status, st.err, st.err0, secs};
+    worst = std::max(worst, status);
+    flags |= st.flags;
+  }
+  if ((rc = data_flags_error(flags))) return rc;
+  return worst;
 }
 
 int hm_effective_tensor(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,
                         const int32_t* d_incl, const hm_sphere* spheres, int n_spheres, const hm_solve_opts* opts,
                         double* C_mandel, void* d_eps, hm_report* rep, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
   int rc;
   if ((rc = check_grid(grid))) return rc;
+  if (!phases) return fail(HM_E_ARG, "phases is NULL");
   if (!C_mandel) return fail(HM_E_ARG, "C_mandel is NULL");
-  const double r2 = 1.0 / sqrt(2.0);
-  // unit Mandel strains as tensor components (11, 22, 33, 23, 13, 12)
-  static const int idx3[6] = {0, 1, 2, 3, 4, 5};
-  static const int idx2[3] = {0, 1, 5};
-  const int k = grid->dim == 2 ? 3 : 6;
-  const int* idx = grid->dim == 2 ? idx2 : idx3;
-  double E[36] = {0};
-  for (int J = 0; J < k; ++J) E[6 * J + idx[J]] = idx[J] < 3 ? 1.0 : r2;
-  double sig[36];
-  rc = solve_impl(grid, phases, rule, d_frac, d_incl, spheres, n_spheres, E, k, opts, d_eps, sig, rep,
-                  (hipStream_t)stream);
-  if (rc < 0) return rc;
-  const double w[6] = {1.0, 1.0, 1.0, sqrt(2.0), sqrt(2.0), sqrt(2.0)};
-  for (int I = 0; I < k; ++I)
-    for (int J = 0; J < k; ++J) C_mandel[I * k + J] = w[idx[I]] * sig[6 * J + idx[I]];
-  return rc;
+  double E[36];
+  const int* idx = nullptr;
+  const int k = unit_loads(grid->dim, E, &idx);
+  Plan* p = nullptr;
+  rc = solve_one(make_problem(grid, phases, rule, d_frac, d_incl, spheres, n_spheres), E, k, opts, d_eps,
+                 (hipStream_t)stream, &p);
+  if (rc) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  assemble_mandel(k, idx, p->state_host, C_mandel);
+  int worst = HM_OK, flags = 0;
+  for (int l = 0; l < k; ++l) {
+    const SolverState& st = p->state_host[l];
+    const int status = load_status(st);
+    if (rep) rep[l] = hm_report{st.iters, status, st.err, st.err0, secs};
+    worst = std::max(worst, status);
+    flags |= st.flags;
+  }
+  if ((rc = data_flags_error(flags))) return rc;
+  return worst;
+}
+
+int hm_effective_tensor_batch(const hm_problem* problems, int n_problems, const hm_solve_opts* opts,
+                              double* C_mandel, hm_report* rep, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  int rc;
+  if (!problems || n_problems < 1) return fail(HM_E_ARG, "no problems");
+  if (!C_mandel) return fail(HM_E_ARG, "C_mandel is NULL");
+  if ((rc = check_opts(opts))) return rc;
+  if (opts->profile) return fail(HM_E_ARG, "profiling is not available for batches");
+  std::vector<ProblemIn> all((size_t)n_problems);
+  for (int q = 0; q < n_problems; ++q) {
+    const hm_problem& h = problems[q];
+    all[q] = make_problem(&h.grid, h.phases, h.rule, h.d_frac, h.d_incl, h.spheres, h.n_spheres);
+    if ((rc = check_problem(all[q]))) {
+      g_last_error = "problem " + std::to_string(q) + ": " + g_last_error;
+      return rc;
+    }
+  }
+  // group the problems by grid, keeping their order within a group
+  std::vector<Group> G;
+  std::map<std::tuple<int, int, int, int>, int> gid;
+  std::vector<int> where((size_t)n_problems);
+  for (int q = 0; q < n_problems; ++q) {
+    const hm_grid& g = all[q].grid;
+    auto key = std::make_tuple(g.dim, g.n[0], g.n[1], g.n[2]);
+    auto it = gid.find(key);
+    if (it == gid.end()) {
+      gid[key] = (int)G.size();
+      G.emplace_back();
+      it = gid.find(key);
+    }
+    where[q] = it->second;
+    G[it->second].probs.push_back(q);
+  }
+  for (Group& g : G) {
+    const ProblemIn& d0 = all[g.probs[0]];
+    double E[36];
+    const int* idx = nullptr;
+    const int k = unit_loads(d0.grid.dim, E, &idx);
+    const int nl = k * (int)g.probs.size();
+    if (nl > kMaxLoads) return fail(HM_E_ARG, "more than %d load cases on one grid", kMaxLoads);
+    if ((rc = get_plan(opts->prec == HM_FP64, d0.grid.n, d0.grid.dim, nl, &g.p))) return rc;
+    g.loads.resize(nl);
+    for (int j = 0; j < (int)g.probs.size(); ++j)
+      for (int J = 0; J < k; ++J) {
+        LoadParams& L = g.loads[(size_t)j * k + J];
+        for (int c = 0; c < 6; ++c) L.E[c] = E[6 * J + c];
+        L.prob = j;
+        L.pad = 0;
+      }
+  }
+  if ((rc = run_groups(G, all, opts, (hipStream_t)stream))) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = HM_OK, flags = 0;
+  size_t cofs = 0, rofs = 0;
+  for (int q = 0; q < n_problems; ++q) {
+    const Group& g = G[where[q]];
+    int j = 0;
+    while (g.probs[j] != q) ++j;
+    double E[36];
+    const int* idx = nullptr;
+    const int k = unit_loads(all[q].grid.dim, E, &idx);
+    const SolverState* st = g.p->state_host + (size_t)j * k;
+    assemble_mandel(k, idx, st, C_mandel + cofs);
+    for (int l = 0; l < k; ++l) {
+      const int status = load_status(st[l]);
+      if (rep) rep[rofs + l] = hm_report{st[l].iters, status, st[l].err, st[l].err0, secs};
+      worst = std::max(worst, status);
+      flags |= st[l].flags;
+    }
+    cofs += (size_t)k * k;
+    rofs += (size_t)k;
+  }
+  if ((rc = data_flags_error(flags))) return rc;
+  return worst;
 }
 
 int hm_solve_adjoint(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,

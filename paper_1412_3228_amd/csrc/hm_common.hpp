@@ -43,20 +43,35 @@ struct SolverState {
   double sig[6];  // <sigma> of the last evaluated (or reported) iterate
 };
 
-// Per-solve values read by the kernels through a device pointer, so that a
-// captured graph stays valid from one solve to the next.
-struct SolveParams {
+// Material of one problem (cell) of a solve.
+struct ProblemParams {
   double pl[2], pm[2];  // phase Lame parameters (0: matrix, 1: inclusion)
   double rl, rm;        // reference medium
-  double tol;
-  int max_iter;
-  int stall_window;
   int rule;
   int nsph;
   const void* frac;   // T[N]
   const int* incl;    // int32[N] or null
   const double* sph;  // [nsph][4]: centre x, y, z, radius (voxel units)
-  double E[6 * 8];    // macroscopic strains, tensor components, per load case
+};
+
+// One load case: its macroscopic strain (tensor components) and problem.
+struct LoadParams {
+  double E[6];
+  int prob;
+  int pad;
+};
+
+// Per-solve values read by the kernels through a device pointer, so that a
+// captured graph stays valid from one solve to the next.  The load and
+// problem arrays follow the header in the same device allocation.
+struct SolveParams {
+  double tol;
+  int max_iter;
+  int stall_window;
+  int n_load;
+  int n_prob;
+  const LoadParams* loads;      // [n_load]
+  const ProblemParams* probs;   // [n_prob]
 };
 
 // Plan-stable launch arguments.

@@ -56,7 +56,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // Polarization at one voxel: tau = (c~ - c0) : e, from the voxel's
 // fraction f and normal-sphere id k.
 template <typename T>
-__device__ __forceinline__ void voxel_tau(const SolveArgs& a, const SolveParams& P, SolverState* st, T f, int k,
+__device__ __forceinline__ void voxel_tau(const SolveArgs& a, const ProblemParams& P, SolverState* st, T f, int k,
                                           int x, int y, int z, const T e[6], T tau[6]) {
   Coef<T> c;
   c.aniso = false;
@@ -113,7 +113,8 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
   const int load = blockIdx.y;
   SolverState* st = a.state + load;
   if (MODE != MODE_EXPORT && st->done) return;
-  const SolveParams& P = *a.prm;
+  const LoadParams& LP = a.prm->loads[load];
+  const ProblemParams& P = a.prm->probs[LP.prob];
   const int nlines = a.ny * a.nz;
   const int line0 = blockIdx.x * L;
   const int Hp = a.Hp;
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
     T e[6];
     if (MODE == MODE_FIRST) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) e[c] = T(P.E[load * 6 + c]);
+      for (int c = 0; c < 6; ++c) e[c] = T(LP.E[c]);
     } else {
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
@@ -363,7 +364,8 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
   const int tid = threadIdx.x;
   const int tile = blockIdx.x, ky = blockIdx.y, load = blockIdx.z;
   if (a.state[load].done) return;
-  const SolveParams& P = *a.prm;
+  const LoadParams& LP = a.prm->loads[load];
+  const ProblemParams& P = a.prm->probs[LP.prob];
   const int H = a.H, Hp = a.Hp, ny = a.ny;
   const int kx0 = tile * W;
   const size_t zs = (size_t)ny * Hp;
@@ -470,7 +472,7 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
   for (int c0 = 0; c0 < 6; c0 += CG) {
 #pragma unroll
     for (int g = 0; g < CG; ++g) {
-      const T Ec = T(P.E[load * 6 + c0 + g]);
+      const T Ec = T(LP.E[c0 + g]);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         if (tid + q * NT < SL) {
@@ -531,7 +533,9 @@ __global__ __launch_bounds__(NT) void k_finalize(SolveArgs a) {
   const int load = blockIdx.x;
   SolverState* st = a.state + load;
   if (st->done) return;
-  const SolveParams& P = *a.prm;
+  const SolveParams& S0 = *a.prm;
+  const LoadParams& LP = S0.loads[load];
+  const ProblemParams& P = S0.probs[LP.prob];
   double tsum[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c)
@@ -540,7 +544,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SolveArgs a) {
   const double S = block_compensated_sum<NT>(a.errpart + (size_t)load * ne, ne, 1, ss, sc);
   if (threadIdx.x != 0) return;
   const double N = (double)a.nx * (double)a.ny * (double)a.nz;
-  const double* E = P.E + 6 * load;
+  const double* E = LP.E;
   const double trE = E[0] + E[1] + E[2];
   double sig[6];
 #pragma unroll
@@ -553,7 +557,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SolveArgs a) {
   if (i < a.hist_cap) a.errhist[(size_t)load * a.hist_cap + i] = e;
   if (i == 0) st->err0 = e;
   int status = ST_RUNNING;
-  if (e < P.tol) {
+  if (e < S0.tol) {
     status = ST_CONVERGED;
   } else if (!isfinite(e) || (st->err0 > 0.0 && e > kDivergenceFactor * st->err0)) {
     status = ST_DIVERGED;
@@ -562,9 +566,9 @@ __global__ __launch_bounds__(NT) void k_finalize(SolveArgs a) {
       st->ref = e;
       st->iref = i;
     }
-    if (P.stall_window > 0 && i - st->iref >= P.stall_window)
+    if (S0.stall_window > 0 && i - st->iref >= S0.stall_window)
       status = ST_STALLED;
-    else if (i >= P.max_iter)
+    else if (i >= S0.max_iter)
       status = ST_NOT_CONVERGED;
   }
   st->err = e;
