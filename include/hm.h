@@ -107,6 +107,9 @@ typedef struct {
                        `stream` (forces direct launches); see hm_last_timing */
   int autotune;     /* nonzero: on a plan's first solve, time every compiled
                        tile schedule of the sweeps and keep the fastest     */
+  int schedule;     /* with autotune == 0: -1 for the first compiled schedule,
+                       else xv | yv << 4 | zv << 8 selecting the variants
+                       counted by hm_schedule_count (for tests)             */
 } hm_solve_opts;
 
 /* Average device duration per launch of each kernel of the iteration, over
@@ -265,6 +268,10 @@ int hm_solve_adjoint(const hm_grid* grid, const hm_iso phases[2], hm_rule rule,
 /* Timing of the calling thread's last solve run with opts->profile set.
  * Returns HM_E_ARG when there is none. */
 int hm_last_timing(hm_timing* out);
+
+/* Number of compiled tile-schedule variants of the x, y and z sweeps for a
+ * grid and precision (all > 0 on success). */
+int hm_schedule_count(const hm_grid* grid, hm_prec prec, int* nx, int* ny, int* nz);
 
 /* Message of the calling thread's last failed call ("" if none). */
 const char* hm_last_error(void);

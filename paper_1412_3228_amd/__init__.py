@@ -15,5 +15,6 @@ from .api import (  # noqa: F401
     hm_solve_adjoint,
     last_timing,
     release_plans,
+    schedule_count,
 )
 from ._lib import EXPORTS, HmError, LIB_PATH, load  # noqa: F401

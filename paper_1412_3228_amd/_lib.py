@@ -21,7 +21,8 @@ PRECS = {"fp64": 0, "mixed": 1}
 
 # Every symbol include/hm.h declares.
 EXPORTS = ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_effective_tensor_batch", "hm_solve_adjoint",
-           "hm_last_error", "hm_last_timing", "hm_release_plans", "hm_device_ok")
+           "hm_last_error", "hm_last_timing", "hm_schedule_count", "hm_release_plans",
+           "hm_device_ok")
 
 
 class HmGrid(ctypes.Structure):
@@ -40,7 +41,7 @@ class HmSolveOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("c0_alpha", ctypes.c_double), ("check_every", ctypes.c_int),
                 ("stall_window", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("profile", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("autotune", ctypes.c_int), ("schedule", ctypes.c_int)]
 
 
 class HmTiming(ctypes.Structure):
@@ -92,6 +93,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     for f in ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_effective_tensor_batch", "hm_solve_adjoint",
               "hm_device_ok"):
         getattr(lib, f).restype = ctypes.c_int
+    lib.hm_schedule_count.argtypes = [_P(HmGrid), ctypes.c_int, _P(ctypes.c_int), _P(ctypes.c_int),
+                                      _P(ctypes.c_int)]
+    lib.hm_schedule_count.restype = ctypes.c_int
     lib.hm_last_timing.argtypes = [_P(HmTiming)]
     lib.hm_last_timing.restype = ctypes.c_int
     lib.hm_last_error.argtypes = []

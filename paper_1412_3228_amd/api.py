@@ -65,7 +65,7 @@ def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
 
 
 def _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile=False,
-          autotune=True) -> L.HmSolveOpts:
+          autotune=True, schedule=None) -> L.HmSolveOpts:
     o = L.HmSolveOpts()
     o.prec = L.PRECS[prec]
     o.tol = float(tol)
@@ -75,7 +75,8 @@ def _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, p
     o.stall_window = int(stall_window)
     o.use_graph = 1 if use_graph else 0
     o.profile = 1 if profile else 0
-    o.autotune = 1 if autotune else 0
+    o.autotune = 1 if (autotune and schedule is None) else 0
+    o.schedule = -1 if schedule is None else int(schedule[0]) | int(schedule[1]) << 4 | int(schedule[2]) << 8
     return o
 
 
@@ -134,7 +135,8 @@ def hm_solve(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch
 def hm_effective_tensor(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres,
                         prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
                         check_every: int = 1, stall_window: int = 0, use_graph: bool = False,
-                        want_eps: bool = False, profile: bool = False, autotune: bool = True):
+                        want_eps: bool = False, profile: bool = False, autotune: bool = True,
+                        schedule=None):
     """Effective Mandel tensor from the unit-strain solves (6 in 3D, 3 in 2D)."""
     dev = frac.device
     N = int(n[0] * n[1] * n[2])
@@ -146,7 +148,7 @@ def hm_effective_tensor(n, dim, phases, rule: str, frac: torch.Tensor, incl: Opt
     eps = torch.empty((k, 6, N), dtype=_DT[prec], device=dev) if want_eps else None
     g = _grid(n, dim)
     sph, ns = _spheres(spheres)
-    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, autotune)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, autotune, schedule)
     rc = _lib().hm_effective_tensor(ctypes.byref(g), _phases(phases), L.RULES[rule], _ptr(frac), _ptr(incl),
                                     sph, ns, ctypes.byref(o), C.ctypes.data_as(L._dp), _ptr(eps), rep,
                                     _stream(dev))
@@ -227,6 +229,15 @@ def last_timing():
     return {"iterations": t.iterations, "n_load": t.n_load, "ms": {n: t.ms[i] for i, n in enumerate(names)},
             "schedule": {"x_lines": t.x_lines, "y_width": t.y_width, "z_width": t.z_width,
                          "z_threads": t.z_threads, "z_groups": t.z_groups}}
+
+
+def schedule_count(n, dim, prec="fp64"):
+    """Numbers of compiled schedule variants of the x, y and z sweeps."""
+    g = _grid(n, dim)
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    L.check(_lib().hm_schedule_count(ctypes.byref(g), L.PRECS[prec], ctypes.byref(a), ctypes.byref(b),
+                                     ctypes.byref(c)))
+    return a.value, b.value, c.value
 
 
 def release_plans():

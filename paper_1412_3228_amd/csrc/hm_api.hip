@@ -642,8 +642,18 @@ int run_groups(std::vector<Group>& G, const std::vector<ProblemIn>& all, const h
   for (Group& g : G) {
     if ((rc = ensure_hist(g.p, opts->max_iter + 1))) return rc;
     if ((rc = upload_params(g, all, opts, s))) return rc;
-    if (opts->autotune && !g.p->tuned)
-      if ((rc = tune_plan(g.p, s))) return rc;
+    if (opts->autotune) {
+      if (!g.p->tuned && (rc = tune_plan(g.p, s))) return rc;
+    } else if (opts->schedule >= 0) {
+      const int xv = opts->schedule & 15, yv = (opts->schedule >> 4) & 15, zv = (opts->schedule >> 8) & 15;
+      if (xv >= g.p->kx->nxv || yv >= g.p->ky->nyv || zv >= g.p->kz->nzv)
+        return fail(HM_E_ARG, "schedule %#x out of range", opts->schedule);
+      set_schedule(g.p, &g.p->kx->x[xv], &g.p->ky->y[yv], &g.p->kz->z[zv]);
+      g.p->tuned = false;
+    } else if (g.p->tuned || g.p->X != &g.p->kx->x[0] || g.p->Y != &g.p->ky->y[0] || g.p->Z != &g.p->kz->z[0]) {
+      set_schedule(g.p, &g.p->kx->x[0], &g.p->ky->y[0], &g.p->kz->z[0]);
+      g.p->tuned = false;
+    }
     hipLaunchKernelGGL((k_reset_state<64>), dim3((g.p->n_load + 63) / 64), dim3(64), 0, s, g.p->state,
                        g.p->n_load);
     HM_HIP(hipGetLastError());
@@ -831,6 +841,21 @@ int hm_device_ok(void) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
   return strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+}
+
+int hm_schedule_count(const hm_grid* grid, hm_prec prec, int* nx, int* ny, int* nz) {
+  int rc;
+  if ((rc = check_grid(grid))) return rc;
+  if (!nx || !ny || !nz) return fail(HM_E_ARG, "NULL output");
+  const bool fp64 = prec == HM_FP64;
+  const AxisKernels* kx = axis_kernels(fp64, grid->n[0]);
+  const AxisKernels* ky = axis_kernels(fp64, grid->n[1]);
+  const AxisKernels* kz = axis_kernels(fp64, grid->n[2]);
+  if (!kx || !ky || !kz) return fail(HM_E_SIZE, "no kernels for this grid");
+  *nx = kx->nxv;
+  *ny = ky->nyv;
+  *nz = kz->nzv;
+  return HM_OK;
 }
 
 void hm_release_plans(void) {

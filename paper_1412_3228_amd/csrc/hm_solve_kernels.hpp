@@ -24,6 +24,8 @@
 // (w = 1 at kx = 0, 2 elsewhere).
 #pragma once
 
+#include <algorithm>
+
 #include "hm_common.hpp"
 #include "hm_fft.hpp"
 #include "hm_material.hpp"
@@ -494,6 +496,142 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
   if (tid == 0) a.errpart[(size_t)load * ((size_t)ny * a.ntx4) + (size_t)ky * a.ntx4 + tile] = tot;
 }
 
+// ------------------------------------------------------ zsweep, pipelined --
+// Persistent form of the z-sweep: each block walks the (load, ky, kx-tile)
+// tiles with a grid stride, one frequency slot per thread (W NZ <= NT), and
+// issues the global reads of its next tile's six components before it
+// transforms the current one, so that a tile's worth of input is always in
+// flight while the block computes.  Same arithmetic as k_zsweep.
+//
+// Tiles are 64 bytes wide, so two consecutive tiles share each 128-byte
+// line.  Workgroups are dispatched to the 8 XCDs round-robin by id, and the
+// grid is a multiple of 8 blocks; the logical order below hands the two
+// tiles of a line to blocks 8 apart (the same XCD, hence the same L2) in the
+// same round.
+__device__ __forceinline__ int xcd_pair_order(int L) {
+  const int g = L >> 4, r = L & 15;
+  return 2 * (g * 8 + (r & 7)) + (r >> 3);
+}
+
+template <typename T, int NZ, int W, int NT>
+__global__ __launch_bounds__(NT) void k_zsweep_pipe(SolveArgs a) {
+  constexpr int SL = W * NZ;
+  static_assert(SL <= NT, "one slot per thread");
+  constexpr int LD = W | 1;
+  __shared__ cx<T> buf[NZ * LD];
+  __shared__ cx<T> s_tw[NZ];
+  __shared__ double red[NT / 64];
+  const int tid = threadIdx.x;
+  const int H = a.H, Hp = a.Hp, ny = a.ny;
+  const size_t zs = (size_t)ny * Hp;
+  const size_t plane = (size_t)NZ * zs;
+  const int ntiles = a.ntx4 * ny * a.n_load;
+  const double twopi = 6.283185307179586476925286766559;
+  const bool slot = tid < SL;
+  const int kz = tid / W, w = tid - (tid / W) * W;
+  const int az = kz <= (NZ - 1) / 2 ? kz : kz - NZ;
+  const unsigned lds = (unsigned)(kz * LD + w);
+  load_twiddles<T, NZ, NT>(s_tw, static_cast<const cx<T>*>(a.twz), tid);
+
+  // tile t -> (load, ky, kx tile); reads of its six components
+  auto fetch = [&](int t, cx<T>* v, bool* okp, bool* skip) {
+    const int tile = t % a.ntx4;
+    const int rest = t / a.ntx4;
+    const int ky = rest % ny, load = rest / ny;
+    *skip = a.state[load].done != 0;
+    const int kx = tile * W + w;
+    const bool ok = slot && kx < H && !*skip;
+    *okp = ok;
+    const cx<T>* sp = static_cast<const cx<T>*>(a.spec) + (size_t)load * 6 * plane + (size_t)ky * Hp + tile * W;
+    const size_t o = (size_t)kz * zs + w;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = ok ? sp[(size_t)c * plane + o] : cx<T>{T(0), T(0)};
+  };
+  const int nlog = (ntiles + 15) / 16 * 16;
+  cx<T> nv6[6];
+  bool nok = false, nskip = true;
+  int L = blockIdx.x;
+  {
+    const int t0 = xcd_pair_order(L);
+    if (L < nlog && t0 < ntiles) fetch(t0, nv6, &nok, &nskip);
+  }
+  for (; L < nlog; L += gridDim.x) {
+    const int t = xcd_pair_order(L);
+    cx<T> cur[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) cur[c] = nv6[c];
+    const bool ok = nok, skip = nskip;
+    const int tn = xcd_pair_order(L + gridDim.x);
+    if (L + (int)gridDim.x < nlog && tn < ntiles) fetch(tn, nv6, &nok, &nskip);
+    if (t >= ntiles || skip) continue;  // uniform over the block
+    const int tile = t % a.ntx4;
+    const int rest = t / a.ntx4;
+    const int ky = rest % ny, load = rest / ny;
+    const LoadParams& LP = a.prm->loads[load];
+    const ProblemParams& P = a.prm->probs[LP.prob];
+    const int kx = tile * W + w;
+    const int ay = ky <= (ny - 1) / 2 ? ky : ky - ny;
+    cx<T>* sp = static_cast<cx<T>*>(a.spec) + (size_t)load * 6 * plane + (size_t)ky * Hp + tile * W;
+    cx<T>* hp = static_cast<cx<T>*>(a.hist) + (size_t)load * 3 * plane + (size_t)ky * Hp + tile * W;
+    const size_t o = (size_t)kz * zs + w;
+    cx<T> h0 = {T(0), T(0)}, h1 = {T(0), T(0)}, h2 = {T(0), T(0)};
+    if (ok && !a.first) {
+      h0 = hp[o];
+      h1 = hp[plane + o];
+      h2 = hp[2 * plane + o];
+    }
+    const double x0 = twopi * kx, x1 = twopi * ay, x2 = twopi * az;
+    const double q2 = x0 * x0 + x1 * x1 + x2 * x2;
+    const double rinv = q2 > 0.0 ? 1.0 / sqrt(q2) : 0.0;
+    Slot<T> z;
+    z.n0 = T(x0 * rinv);
+    z.n1 = T(x1 * rinv);
+    z.n2 = T(x2 * rinv);
+    z.a0 = z.a1 = z.a2 = cx<T>{T(0), T(0)};
+#pragma unroll 1
+    for (int c = 0; c < 6; ++c) {
+      cx<T> v = cur[0];
+#pragma unroll
+      for (int d = 1; d < 6; ++d)
+        if (c == d) v = cur[d];
+      if (slot) buf[lds] = v;
+      __syncthreads();
+      fft_lines<T, NZ, W, NT, -1, LD>(buf, s_tw, tid);
+      if (slot) fold_component<T>(c, buf[lds], z);
+      __syncthreads();
+    }
+    double S = 0.0;
+    if (ok) {
+      if (q2 == 0.0) {
+        hp[o] = hp[plane + o] = hp[2 * plane + o] = cx<T>{T(0), T(0)};
+      } else {
+        const double d0x = (double)z.a0.x - (double)h0.x, d0y = (double)z.a0.y - (double)h0.y;
+        const double d1x = (double)z.a1.x - (double)h1.x, d1y = (double)z.a1.y - (double)h1.y;
+        const double d2x = (double)z.a2.x - (double)h2.x, d2y = (double)z.a2.y - (double)h2.y;
+        hp[o] = z.a0;
+        hp[plane + o] = z.a1;
+        hp[2 * plane + o] = z.a2;
+        S = (kx == 0 ? 1.0 : 2.0) * q2 * (d0x * d0x + d0y * d0y + d1x * d1x + d1y * d1y + d2x * d2x + d2y * d2y);
+      }
+    }
+    const double rl = P.rl, rm = P.rm;
+    const T inv2mu = T(1.0 / (2.0 * rm));
+    const T cc = T((rl + rm) / (rm * (rl + 2.0 * rm)));
+    const T m = T(-1.0 / ((double)a.nx * (double)ny * (double)NZ));
+    const cx<T> na = {z.a0.x * z.n0 + z.a1.x * z.n1 + z.a2.x * z.n2, z.a0.y * z.n0 + z.a1.y * z.n1 + z.a2.y * z.n2};
+#pragma unroll 1
+    for (int c = 0; c < 6; ++c) {
+      if (slot) buf[lds] = q2 == 0.0 ? cx<T>{T(LP.E[c]), T(0)} : strain_component<T>(c, z, na, inv2mu, cc, m);
+      __syncthreads();
+      fft_lines<T, NZ, W, NT, +1, LD>(buf, s_tw, tid);
+      if (ok) sp[(size_t)c * plane + o] = buf[lds];
+      __syncthreads();
+    }
+    const double tot = block_sum<NT>(S, red);
+    if (tid == 0) a.errpart[(size_t)load * ((size_t)ny * a.ntx4) + (size_t)ky * a.ntx4 + tile] = tot;
+  }
+}
+
 // -------------------------------------------------------------- finalize --
 __device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
   const double t = s + x;
@@ -615,9 +753,9 @@ struct ZKern {
   solve_launch_fn run;
   int width;    // kx columns per block
   int threads;  // block size
-  int groups;   // components per LDS transform
+  int groups;   // components per LDS transform (-1: persistent pipelined form)
 };
-constexpr int kMaxVariants = 3;
+constexpr int kMaxVariants = 4;
 struct AxisKernels {
   int n;
   int nxv, nyv, nzv;
@@ -673,6 +811,30 @@ hipError_t launch_y(const SolveArgs& a, hipStream_t s) {
                      s, a);
   return hipGetLastError();
 }
+// Persistent grid of the pipelined z-sweep: the resident block count.
+template <typename T, int NZ, int W, int NT>
+int pipe_blocks() {
+  static int blocks = 0;
+  if (blocks == 0) {
+    int dev = 0, cus = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_zsweep_pipe<T, NZ, W, NT>, NT, 0);
+    blocks = (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
+  }
+  return blocks;
+}
+
+template <typename T, int NZ>
+hipError_t launch_z_pipe(const SolveArgs& a, hipStream_t s) {
+  constexpr int W = 64 / (int)sizeof(cx<T>);
+  constexpr int NT = clamp_int(round64(W * NZ), 64, 1024);
+  const int tiles = a.ntx4 * a.ny * a.n_load;
+  const int blocks = std::min((tiles + 15) / 16 * 16, pipe_blocks<T, NZ, W, NT>() / 8 * 8);
+  hipLaunchKernelGGL((k_zsweep_pipe<T, NZ, W, NT>), dim3(blocks), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int NZ, int V>
 hipError_t launch_z(const SolveArgs& a, hipStream_t s) {
   using TL = ZTile<T, NZ, V>;
@@ -707,6 +869,10 @@ AxisKernels make_axis_kernels() {
   k.z[1] = make_z<T, N, 1>();
   k.nzv = 2;
   if (ZTile<T, N, 2>::CG > 1) k.z[k.nzv++] = make_z<T, N, 2>();
+  if constexpr ((64 / (int)sizeof(cx<T>)) * N <= (sizeof(T) == 8 ? 512 : 1024)) {
+    constexpr int W = 64 / (int)sizeof(cx<T>);
+    k.z[k.nzv++] = ZKern{&launch_z_pipe<T, N>, W, clamp_int(round64(W * N), 64, 1024), -1};
+  }
   return k;
 }
 

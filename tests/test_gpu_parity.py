@@ -206,3 +206,26 @@ def test_profiled_solve_matches_and_reports_timing(hm):
     t = hm.last_timing()
     assert t["iterations"] == max(r["iters"] for r in b["reports"]) + 1
     assert all(v > 0 for v in t["ms"].values())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", [(45, 45, 45), (27, 21, 25), (63, 15, 35)])
+def test_every_compiled_schedule_matches_oracle(hm, prec, n):
+    """Each tile-schedule variant the autotuner may pick gives the oracle's iterate."""
+    w = small_sphere_case(n=n, fraction=0.2, contrast=20.0, rule="laminate", radius_vox=1.0, subsamples=4,
+                          offset=(0.5, -0.25, 0.125))
+    nx, ny, nz = hm.schedule_count(w.n, 3, prec)
+    log("schedules %s %s: %d x %d x %d" % (prec, n, nx, ny, nz))
+    _, _, _, frac, incl = _gpu_filter(hm, w, prec)
+    ref_f = ofilter.filter_field(w)
+    k = 3
+    refs = oracle_solve(w, ref_f["frac"], ref_f["incl"], w.loads[[0, 5]], 0.0, k)
+    tol = 1e-10 if prec == "fp64" else 2e-5
+    combos = [(x, 0, 0) for x in range(nx)] + [(0, y, 0) for y in range(ny)] + [(0, 0, z) for z in range(nz)]
+    for sch in combos:
+        out = hm.hm_effective_tensor(w.n, 3, w.phases, w.rule, frac, incl, w.spheres, prec=prec, tol=0.0,
+                                     max_iter=k, schedule=sch, want_eps=True)
+        for col, r in zip((0, 5), refs):
+            e = out["eps"][col].cpu().numpy().astype(np.float64)
+            err = rel(e, oracle_fields_to_comps(r["eps"]))
+            assert err < tol, (sch, col, err)
