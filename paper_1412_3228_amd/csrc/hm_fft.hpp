@@ -109,7 +109,25 @@ template <int N> struct FftPlan {
   static_assert(passes() >= 0, "line length must be a product of 3, 5 and 7");
 };
 
-template <typename T, int N, int L, int NT, int R, int NS, int SIGN, int LD>
+// Ordering of LDS accesses between the lanes of one wavefront: LDS executes
+// a wave's instructions in order, so a code-motion barrier for the compiler
+// is all that is needed (no s_barrier, no wait).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// WAVE = false: all NT threads of the block cooperate (block barriers).
+// WAVE = true: one wavefront (NT = 64, tid = lane) owns the lines.
+template <bool WAVE> __device__ __forceinline__ void pass_sync() {
+  if constexpr (WAVE)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
+template <typename T, int N, int L, int NT, int R, int NS, int SIGN, int LD, bool WAVE = false>
 __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid) {
   constexpr int NB = N / R;
   constexpr int TOT = L * NB;
@@ -125,7 +143,7 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid) {
       for (int r = 0; r < R; ++r) v[q][r] = buf[(j + r * NB) * LD + l];
     }
   }
-  __syncthreads();
+  pass_sync<WAVE>();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int b = tid + q * NT;
@@ -147,7 +165,7 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid) {
       for (int r = 0; r < R; ++r) buf[(base + r * NS) * LD + l] = v[q][r];
     }
   }
-  __syncthreads();
+  pass_sync<WAVE>();
 }
 
 // Transforms the L lines in buf.  The caller synchronises before the call
@@ -157,6 +175,16 @@ __device__ __forceinline__ void fft_lines(cx<T>* buf, const cx<T>* tw, int tid) 
   if constexpr (P < FftPlan<N>::passes()) {
     fft_pass<T, N, L, NT, FftPlan<N>::radix(P), FftPlan<N>::stride(P), SIGN, LD>(buf, tw, tid);
     fft_lines<T, N, L, NT, SIGN, LD, P + 1>(buf, tw, tid);
+  }
+}
+
+// Wavefront form: the 64 lanes of one wave transform the L lines in buf;
+// the caller orders its own LDS writes before the call with wave_sync().
+template <typename T, int N, int L, int SIGN, int LD = L, int P = 0>
+__device__ __forceinline__ void fft_lines_wave(cx<T>* buf, const cx<T>* tw, int lane) {
+  if constexpr (P < FftPlan<N>::passes()) {
+    fft_pass<T, N, L, 64, FftPlan<N>::radix(P), FftPlan<N>::stride(P), SIGN, LD, true>(buf, tw, lane);
+    fft_lines_wave<T, N, L, SIGN, LD, P + 1>(buf, tw, lane);
   }
 }
 

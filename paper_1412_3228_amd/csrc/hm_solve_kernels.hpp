@@ -342,6 +342,13 @@ __device__ __forceinline__ void fold_component(int c, cx<T> v, Slot<T>& z) {
   z.a2.y += v.y * w2;
 }
 
+// Entry (i, j) of m * [(n (x) a + a (x) n) / (2 mu0) - cc (n.a) n (x) n].
+template <typename T>
+__device__ __forceinline__ cx<T> gamma_entry(T ni, T nj, cx<T> ai, cx<T> aj, cx<T> na, T inv2mu, T cc, T m) {
+  const T g = cc * ni * nj;
+  return cx<T>{m * ((ni * aj.x + nj * ai.x) * inv2mu - g * na.x), m * ((ni * aj.y + nj * ai.y) * inv2mu - g * na.y)};
+}
+
 // Component c of m * [(n (x) a + a (x) n) / (2 mu0) - cc (n.a) n (x) n].
 template <typename T>
 __device__ __forceinline__ cx<T> strain_component(int c, const Slot<T>& z, cx<T> na, T inv2mu, T cc, T m) {
@@ -496,140 +503,302 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
   if (tid == 0) a.errpart[(size_t)load * ((size_t)ny * a.ntx4) + (size_t)ky * a.ntx4 + tile] = tot;
 }
 
-// ------------------------------------------------------ zsweep, pipelined --
-// Persistent form of the z-sweep: each block walks the (load, ky, kx-tile)
-// tiles with a grid stride, one frequency slot per thread (W NZ <= NT), and
-// issues the global reads of its next tile's six components before it
-// transforms the current one, so that a tile's worth of input is always in
-// flight while the block computes.  Same arithmetic as k_zsweep.
-//
-// Tiles are 64 bytes wide, so two consecutive tiles share each 128-byte
-// line.  Workgroups are dispatched to the 8 XCDs round-robin by id, and the
-// grid is a multiple of 8 blocks; the logical order below hands the two
-// tiles of a line to blocks 8 apart (the same XCD, hence the same L2) in the
-// same round.
+// ------------------------------------------------------ wavefront sweeps --
+// Variants in which each wavefront owns whole FFT lines, so the radix passes
+// need no block barrier (see wave_sync).
+
+// x-sweep: each of the NW waves of a block owns LW consecutive (y, z) lines
+// (3 LW complex lines); one block barrier publishes the twiddles, one more
+// combines the per-wave tau sums.
+template <typename T, int NX, int LW, int NW, int MODE>
+__global__ __launch_bounds__(64 * NW) void k_xsweep_wave(SolveArgs a) {
+  constexpr int NT = 64 * NW;
+  constexpr int LL = 3 * LW;
+  constexpr int LD = LL | 1;
+  constexpr int H = (NX + 1) / 2;
+  constexpr int NLD = 3 * LW * H;  // (pair, line, kx) items of one wave
+  constexpr int QL = (NLD + 63) / 64;
+  constexpr int NV = LW * NX;  // voxels of one wave
+  constexpr int QV = (NV + 63) / 64;
+  __shared__ cx<T> bufs[NW][NX * LD];
+  __shared__ cx<T> s_tw[NX];
+  __shared__ double red[6][NW];
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int load = blockIdx.y;
+  SolverState* st = a.state + load;
+  if (MODE != MODE_EXPORT && st->done) return;
+  const LoadParams& LP = a.prm->loads[load];
+  const ProblemParams& P = a.prm->probs[LP.prob];
+  const int nlines = a.ny * a.nz;
+  const int line0 = (blockIdx.x * NW + wv) * LW;
+  const int Hp = a.Hp;
+  const size_t cs = (size_t)nlines * Hp;
+  cx<T>* spec = static_cast<cx<T>*>(a.spec) + (size_t)load * 6 * cs;
+  cx<T>* buf = bufs[wv];
+
+  cx<T> pa[QL], pb[QL];
+  if (MODE != MODE_FIRST) {
+#pragma unroll
+    for (int q = 0; q < QL; ++q) {
+      const int idx = lane + 64 * q;
+      pa[q] = cx<T>{T(0), T(0)};
+      pb[q] = cx<T>{T(0), T(0)};
+      if (idx < NLD) {
+        const int p = idx / (LW * H);
+        const int rem = idx - p * (LW * H);
+        const int l = rem / H;
+        const int k = rem - l * H;
+        const int line = line0 + l;
+        if (line < nlines) {
+          pa[q] = spec[(size_t)(2 * p) * cs + (size_t)line * Hp + k];
+          pb[q] = spec[(size_t)(2 * p + 1) * cs + (size_t)line * Hp + k];
+        }
+      }
+    }
+  }
+  T fv[QV];
+  int iv[QV];
+  if (MODE != MODE_EXPORT) {
+    const T* frac = static_cast<const T*>(P.frac);
+#pragma unroll
+    for (int q = 0; q < QV; ++q) {
+      const int idx = lane + 64 * q;
+      const int l = idx / NX, x = idx - l * NX, line = line0 + l;
+      fv[q] = T(0);
+      iv[q] = -1;
+      if (idx < NV && line < nlines) {
+        const size_t v = (size_t)line * NX + x;
+        fv[q] = frac[v];
+        if (P.incl) iv[q] = P.incl[v];
+      }
+    }
+  }
+  load_twiddles<T, NX, NT>(s_tw, static_cast<const cx<T>*>(a.twx), tid);
+  __syncthreads();
+
+  if (MODE != MODE_FIRST) {
+#pragma unroll
+    for (int q = 0; q < QL; ++q) {
+      const int idx = lane + 64 * q;
+      if (idx < NLD) {
+        const int p = idx / (LW * H);
+        const int rem = idx - p * (LW * H);
+        const int l = rem / H;
+        const int k = rem - l * H;
+        const cx<T> A = pa[q], B = pb[q];
+        buf[k * LD + p * LW + l] = cx<T>{A.x - B.y, A.y + B.x};
+        if (k > 0) buf[(NX - k) * LD + p * LW + l] = cx<T>{A.x + B.y, B.x - A.y};
+      }
+    }
+    wave_sync();
+    fft_lines_wave<T, NX, LL, +1, LD>(buf, s_tw, lane);
+  }
+
+  if (MODE == MODE_EXPORT) {
+    const size_t N = (size_t)nlines * NX;
+    T* out = static_cast<T*>(a.eps_out) + (size_t)load * 6 * N;
+    for (int idx = lane; idx < NV; idx += 64) {
+      const int l = idx / NX, x = idx - l * NX, line = line0 + l;
+      if (line < nlines) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          const cx<T> Z = buf[x * LD + p * LW + l];
+          out[(size_t)(2 * p) * N + (size_t)line * NX + x] = Z.x;
+          out[(size_t)(2 * p + 1) * N + (size_t)line * NX + x] = Z.y;
+        }
+      }
+    }
+    return;
+  }
+
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < QV; ++q) {
+    const int idx = lane + 64 * q;
+    if (idx >= NV) continue;
+    const int l = idx / NX, x = idx - l * NX, line = line0 + l;
+    T e[6];
+    if (MODE == MODE_FIRST) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) e[c] = T(LP.E[c]);
+    } else {
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const cx<T> Z = buf[x * LD + p * LW + l];
+        e[2 * p] = Z.x;
+        e[2 * p + 1] = Z.y;
+      }
+    }
+    T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    if (line < nlines) {
+      const int y = line % a.ny, z = line / a.ny;
+      voxel_tau<T>(a, P, st, fv[q], iv[q], x, y, z, e, tau);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[c] += (double)tau[c];
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p) buf[x * LD + p * LW + l] = cx<T>{tau[2 * p], tau[2 * p + 1]};
+  }
+  wave_sync();
+  fft_lines_wave<T, NX, LL, -1, LD>(buf, s_tw, lane);
+
+  for (int idx = lane; idx < NLD; idx += 64) {
+    const int p = idx / (LW * H);
+    const int rem = idx - p * (LW * H);
+    const int l = rem / H;
+    const int k = rem - l * H;
+    const int line = line0 + l;
+    if (line < nlines) {
+      const cx<T> Z = buf[k * LD + p * LW + l];
+      const cx<T> Zc = c_conj(buf[((NX - k) % NX) * LD + p * LW + l]);
+      const cx<T> A = {T(0.5) * (Z.x + Zc.x), T(0.5) * (Z.y + Zc.y)};
+      const cx<T> B = {T(0.5) * (Z.y - Zc.y), T(-0.5) * (Z.x - Zc.x)};
+      spec[(size_t)(2 * p) * cs + (size_t)line * Hp + k] = A;
+      spec[(size_t)(2 * p + 1) * cs + (size_t)line * Hp + k] = B;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    double v = acc[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[c][wv] = v;
+  }
+  __syncthreads();
+  if (tid < 6) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) s += red[tid][i];
+    a.taupart[((size_t)load * a.g2 + blockIdx.x) * 6 + tid] = s;
+  }
+}
+
+// z-sweep: six waves per tile of W kx columns, wave c owning strain
+// component c.  Each wave reads its component's tile and transforms it in
+// its own LDS region; after one block barrier every thread applies the Green
+// operator to its frequency slots across the six regions; after a second
+// barrier each wave inverse-transforms and stores its component.  Tiles are
+// taken in XCD-paired order (see xcd_pair_order) on a one-dimensional grid.
 __device__ __forceinline__ int xcd_pair_order(int L) {
   const int g = L >> 4, r = L & 15;
   return 2 * (g * 8 + (r & 7)) + (r >> 3);
 }
 
-template <typename T, int NZ, int W, int NT>
-__global__ __launch_bounds__(NT) void k_zsweep_pipe(SolveArgs a) {
+template <typename T, int NZ, int W>
+__global__ __launch_bounds__(384) void k_zsweep_wave(SolveArgs a) {
+  constexpr int NT = 384;
   constexpr int SL = W * NZ;
-  static_assert(SL <= NT, "one slot per thread");
   constexpr int LD = W | 1;
-  __shared__ cx<T> buf[NZ * LD];
+  constexpr int RS = NZ * LD;
+  constexpr int QC = (SL + 63) / 64;
+  constexpr int QS = (SL + NT - 1) / NT;
+  __shared__ cx<T> rg[6 * RS];
   __shared__ cx<T> s_tw[NZ];
   __shared__ double red[NT / 64];
-  const int tid = threadIdx.x;
-  const int H = a.H, Hp = a.Hp, ny = a.ny;
+  const int tid = threadIdx.x, c = tid >> 6, lane = tid & 63;
+  const int ntiles = a.ntx4 * a.ny * a.n_load;
+  const int t = xcd_pair_order(blockIdx.x);
+  if (t >= ntiles) return;
+  const int tile = t % a.ntx4;
+  const int rest = t / a.ntx4;
+  const int ny = a.ny;
+  const int ky = rest % ny, load = rest / ny;
+  if (a.state[load].done) return;
+  const LoadParams& LP = a.prm->loads[load];
+  const ProblemParams& P = a.prm->probs[LP.prob];
+  const int H = a.H, Hp = a.Hp;
+  const int kx0 = tile * W;
   const size_t zs = (size_t)ny * Hp;
   const size_t plane = (size_t)NZ * zs;
-  const int ntiles = a.ntx4 * ny * a.n_load;
+  cx<T>* sp = static_cast<cx<T>*>(a.spec) + (size_t)load * 6 * plane + (size_t)ky * Hp + kx0;
+  cx<T>* hp = static_cast<cx<T>*>(a.hist) + (size_t)load * 3 * plane + (size_t)ky * Hp + kx0;
+  const int ay = ky <= (ny - 1) / 2 ? ky : ky - ny;
   const double twopi = 6.283185307179586476925286766559;
-  const bool slot = tid < SL;
-  const int kz = tid / W, w = tid - (tid / W) * W;
-  const int az = kz <= (NZ - 1) / 2 ? kz : kz - NZ;
-  const unsigned lds = (unsigned)(kz * LD + w);
-  load_twiddles<T, NZ, NT>(s_tw, static_cast<const cx<T>*>(a.twz), tid);
+  cx<T>* mine = rg + c * RS;
 
-  // tile t -> (load, ky, kx tile); reads of its six components
-  auto fetch = [&](int t, cx<T>* v, bool* okp, bool* skip) {
-    const int tile = t % a.ntx4;
-    const int rest = t / a.ntx4;
-    const int ky = rest % ny, load = rest / ny;
-    *skip = a.state[load].done != 0;
-    const int kx = tile * W + w;
-    const bool ok = slot && kx < H && !*skip;
-    *okp = ok;
-    const cx<T>* sp = static_cast<const cx<T>*>(a.spec) + (size_t)load * 6 * plane + (size_t)ky * Hp + tile * W;
-    const size_t o = (size_t)kz * zs + w;
+  cx<T> v[QC];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) v[c] = ok ? sp[(size_t)c * plane + o] : cx<T>{T(0), T(0)};
-  };
-  const int nlog = (ntiles + 15) / 16 * 16;
-  cx<T> nv6[6];
-  bool nok = false, nskip = true;
-  int L = blockIdx.x;
-  {
-    const int t0 = xcd_pair_order(L);
-    if (L < nlog && t0 < ntiles) fetch(t0, nv6, &nok, &nskip);
+  for (int q = 0; q < QC; ++q) {
+    const int e = lane + 64 * q;
+    const int kz = e / W, w = e - (e / W) * W;
+    v[q] = (e < SL && kx0 + w < H) ? sp[(size_t)c * plane + (size_t)kz * zs + w] : cx<T>{T(0), T(0)};
   }
-  for (; L < nlog; L += gridDim.x) {
-    const int t = xcd_pair_order(L);
-    cx<T> cur[6];
+  cx<T> h[QS][3];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) cur[c] = nv6[c];
-    const bool ok = nok, skip = nskip;
-    const int tn = xcd_pair_order(L + gridDim.x);
-    if (L + (int)gridDim.x < nlog && tn < ntiles) fetch(tn, nv6, &nok, &nskip);
-    if (t >= ntiles || skip) continue;  // uniform over the block
-    const int tile = t % a.ntx4;
-    const int rest = t / a.ntx4;
-    const int ky = rest % ny, load = rest / ny;
-    const LoadParams& LP = a.prm->loads[load];
-    const ProblemParams& P = a.prm->probs[LP.prob];
-    const int kx = tile * W + w;
-    const int ay = ky <= (ny - 1) / 2 ? ky : ky - ny;
-    cx<T>* sp = static_cast<cx<T>*>(a.spec) + (size_t)load * 6 * plane + (size_t)ky * Hp + tile * W;
-    cx<T>* hp = static_cast<cx<T>*>(a.hist) + (size_t)load * 3 * plane + (size_t)ky * Hp + tile * W;
-    const size_t o = (size_t)kz * zs + w;
-    cx<T> h0 = {T(0), T(0)}, h1 = {T(0), T(0)}, h2 = {T(0), T(0)};
-    if (ok && !a.first) {
-      h0 = hp[o];
-      h1 = hp[plane + o];
-      h2 = hp[2 * plane + o];
+  for (int q = 0; q < QS; ++q) {
+    const int s = tid + NT * q;
+    const int kz = s / W, w = s - (s / W) * W;
+    const bool ok = s < SL && kx0 + w < H && !a.first;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      h[q][d] = ok ? hp[(size_t)d * plane + (size_t)kz * zs + w] : cx<T>{T(0), T(0)};
+  }
+  load_twiddles<T, NZ, NT>(s_tw, static_cast<const cx<T>*>(a.twz), tid);
+#pragma unroll
+  for (int q = 0; q < QC; ++q) {
+    const int e = lane + 64 * q;
+    if (e < SL) mine[(e / W) * LD + (e % W)] = v[q];
+  }
+  __syncthreads();
+  fft_lines_wave<T, NZ, W, -1, LD>(mine, s_tw, lane);
+  __syncthreads();
+
+  const double rl = P.rl, rm = P.rm;
+  const T inv2mu = T(1.0 / (2.0 * rm));
+  const T cc = T((rl + rm) / (rm * (rl + 2.0 * rm)));
+  const T m = T(-1.0 / ((double)a.nx * (double)ny * (double)NZ));
+  double S = 0.0;
+#pragma unroll
+  for (int q = 0; q < QS; ++q) {
+    const int s = tid + NT * q;
+    if (s >= SL) continue;
+    const int kz = s / W, w = s - kz * W;
+    const int kx = kx0 + w;
+    if (kx >= H) continue;
+    const int az = kz <= (NZ - 1) / 2 ? kz : kz - NZ;
+    const int o = kz * LD + w;
+    const size_t go = (size_t)kz * zs + w;
+    if (kx == 0 && ay == 0 && az == 0) {
+#pragma unroll
+      for (int d = 0; d < 6; ++d) rg[d * RS + o] = cx<T>{T(LP.E[d]), T(0)};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) hp[(size_t)d * plane + go] = cx<T>{T(0), T(0)};
+      continue;
     }
     const double x0 = twopi * kx, x1 = twopi * ay, x2 = twopi * az;
     const double q2 = x0 * x0 + x1 * x1 + x2 * x2;
-    const double rinv = q2 > 0.0 ? 1.0 / sqrt(q2) : 0.0;
-    Slot<T> z;
-    z.n0 = T(x0 * rinv);
-    z.n1 = T(x1 * rinv);
-    z.n2 = T(x2 * rinv);
-    z.a0 = z.a1 = z.a2 = cx<T>{T(0), T(0)};
-#pragma unroll 1
-    for (int c = 0; c < 6; ++c) {
-      cx<T> v = cur[0];
-#pragma unroll
-      for (int d = 1; d < 6; ++d)
-        if (c == d) v = cur[d];
-      if (slot) buf[lds] = v;
-      __syncthreads();
-      fft_lines<T, NZ, W, NT, -1, LD>(buf, s_tw, tid);
-      if (slot) fold_component<T>(c, buf[lds], z);
-      __syncthreads();
-    }
-    double S = 0.0;
-    if (ok) {
-      if (q2 == 0.0) {
-        hp[o] = hp[plane + o] = hp[2 * plane + o] = cx<T>{T(0), T(0)};
-      } else {
-        const double d0x = (double)z.a0.x - (double)h0.x, d0y = (double)z.a0.y - (double)h0.y;
-        const double d1x = (double)z.a1.x - (double)h1.x, d1y = (double)z.a1.y - (double)h1.y;
-        const double d2x = (double)z.a2.x - (double)h2.x, d2y = (double)z.a2.y - (double)h2.y;
-        hp[o] = z.a0;
-        hp[plane + o] = z.a1;
-        hp[2 * plane + o] = z.a2;
-        S = (kx == 0 ? 1.0 : 2.0) * q2 * (d0x * d0x + d0y * d0y + d1x * d1x + d1y * d1y + d2x * d2x + d2y * d2y);
-      }
-    }
-    const double rl = P.rl, rm = P.rm;
-    const T inv2mu = T(1.0 / (2.0 * rm));
-    const T cc = T((rl + rm) / (rm * (rl + 2.0 * rm)));
-    const T m = T(-1.0 / ((double)a.nx * (double)ny * (double)NZ));
-    const cx<T> na = {z.a0.x * z.n0 + z.a1.x * z.n1 + z.a2.x * z.n2, z.a0.y * z.n0 + z.a1.y * z.n1 + z.a2.y * z.n2};
-#pragma unroll 1
-    for (int c = 0; c < 6; ++c) {
-      if (slot) buf[lds] = q2 == 0.0 ? cx<T>{T(LP.E[c]), T(0)} : strain_component<T>(c, z, na, inv2mu, cc, m);
-      __syncthreads();
-      fft_lines<T, NZ, W, NT, +1, LD>(buf, s_tw, tid);
-      if (ok) sp[(size_t)c * plane + o] = buf[lds];
-      __syncthreads();
-    }
-    const double tot = block_sum<NT>(S, red);
-    if (tid == 0) a.errpart[(size_t)load * ((size_t)ny * a.ntx4) + (size_t)ky * a.ntx4 + tile] = tot;
+    const double rinv = 1.0 / sqrt(q2);
+    const T n0 = T(x0 * rinv), n1 = T(x1 * rinv), n2 = T(x2 * rinv);
+    const cx<T> t11 = rg[o], t22 = rg[RS + o], t33 = rg[2 * RS + o];
+    const cx<T> t23 = rg[3 * RS + o], t13 = rg[4 * RS + o], t12 = rg[5 * RS + o];
+    const cx<T> a0 = {t11.x * n0 + t12.x * n1 + t13.x * n2, t11.y * n0 + t12.y * n1 + t13.y * n2};
+    const cx<T> a1 = {t12.x * n0 + t22.x * n1 + t23.x * n2, t12.y * n0 + t22.y * n1 + t23.y * n2};
+    const cx<T> a2 = {t13.x * n0 + t23.x * n1 + t33.x * n2, t13.y * n0 + t23.y * n1 + t33.y * n2};
+    const cx<T> na = {a0.x * n0 + a1.x * n1 + a2.x * n2, a0.y * n0 + a1.y * n1 + a2.y * n2};
+    const double d0x = (double)a0.x - (double)h[q][0].x, d0y = (double)a0.y - (double)h[q][0].y;
+    const double d1x = (double)a1.x - (double)h[q][1].x, d1y = (double)a1.y - (double)h[q][1].y;
+    const double d2x = (double)a2.x - (double)h[q][2].x, d2y = (double)a2.y - (double)h[q][2].y;
+    S += (kx == 0 ? 1.0 : 2.0) * q2 * (d0x * d0x + d0y * d0y + d1x * d1x + d1y * d1y + d2x * d2x + d2y * d2y);
+    hp[go] = a0;
+    hp[plane + go] = a1;
+    hp[2 * plane + go] = a2;
+    rg[o] = gamma_entry<T>(n0, n0, a0, a0, na, inv2mu, cc, m);
+    rg[RS + o] = gamma_entry<T>(n1, n1, a1, a1, na, inv2mu, cc, m);
+    rg[2 * RS + o] = gamma_entry<T>(n2, n2, a2, a2, na, inv2mu, cc, m);
+    rg[3 * RS + o] = gamma_entry<T>(n1, n2, a1, a2, na, inv2mu, cc, m);
+    rg[4 * RS + o] = gamma_entry<T>(n0, n2, a0, a2, na, inv2mu, cc, m);
+    rg[5 * RS + o] = gamma_entry<T>(n0, n1, a0, a1, na, inv2mu, cc, m);
   }
+  __syncthreads();
+  fft_lines_wave<T, NZ, W, +1, LD>(mine, s_tw, lane);
+#pragma unroll
+  for (int q = 0; q < QC; ++q) {
+    const int e = lane + 64 * q;
+    const int kz = e / W, w = e - (e / W) * W;
+    if (e < SL && kx0 + w < H) sp[(size_t)c * plane + (size_t)kz * zs + w] = mine[kz * LD + w];
+  }
+  const double tot = block_sum<NT>(S, red);
+  if (tid == 0) a.errpart[(size_t)load * ((size_t)ny * a.ntx4) + (size_t)ky * a.ntx4 + tile] = tot;
 }
 
 // -------------------------------------------------------------- finalize --
@@ -753,9 +922,9 @@ struct ZKern {
   solve_launch_fn run;
   int width;    // kx columns per block
   int threads;  // block size
-  int groups;   // components per LDS transform (-1: persistent pipelined form)
+  int groups;   // components per LDS transform (-1: one wavefront per component)
 };
-constexpr int kMaxVariants = 4;
+constexpr int kMaxVariants = 6;
 struct AxisKernels {
   int n;
   int nxv, nyv, nzv;
@@ -811,27 +980,16 @@ hipError_t launch_y(const SolveArgs& a, hipStream_t s) {
                      s, a);
   return hipGetLastError();
 }
-// Persistent grid of the pipelined z-sweep: the resident block count.
-template <typename T, int NZ, int W, int NT>
-int pipe_blocks() {
-  static int blocks = 0;
-  if (blocks == 0) {
-    int dev = 0, cus = 0, per = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_zsweep_pipe<T, NZ, W, NT>, NT, 0);
-    blocks = (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
-  }
-  return blocks;
+template <typename T, int NX, int MODE, int LW, int NW>
+hipError_t launch_x_wave(const SolveArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_xsweep_wave<T, NX, LW, NW, MODE>), dim3(a.g2, a.n_load), dim3(64 * NW), 0, s, a);
+  return hipGetLastError();
 }
 
-template <typename T, int NZ>
-hipError_t launch_z_pipe(const SolveArgs& a, hipStream_t s) {
-  constexpr int W = 64 / (int)sizeof(cx<T>);
-  constexpr int NT = clamp_int(round64(W * NZ), 64, 1024);
+template <typename T, int NZ, int W>
+hipError_t launch_z_wave(const SolveArgs& a, hipStream_t s) {
   const int tiles = a.ntx4 * a.ny * a.n_load;
-  const int blocks = std::min((tiles + 15) / 16 * 16, pipe_blocks<T, NZ, W, NT>() / 8 * 8);
-  hipLaunchKernelGGL((k_zsweep_pipe<T, NZ, W, NT>), dim3(blocks), dim3(NT), 0, s, a);
+  hipLaunchKernelGGL((k_zsweep_wave<T, NZ, W>), dim3((tiles + 15) / 16 * 16), dim3(384), 0, s, a);
   return hipGetLastError();
 }
 
@@ -869,9 +1027,20 @@ AxisKernels make_axis_kernels() {
   k.z[1] = make_z<T, N, 1>();
   k.nzv = 2;
   if (ZTile<T, N, 2>::CG > 1) k.z[k.nzv++] = make_z<T, N, 2>();
-  if constexpr ((64 / (int)sizeof(cx<T>)) * N <= (sizeof(T) == 8 ? 512 : 1024)) {
+  // wavefront x-sweeps: (2 lines per wave, 2 waves) and (1 line per wave, 4 waves)
+  if constexpr (2 * N * ((6 | 1)) * (int)sizeof(cx<T>) <= 56 * 1024) {
+    k.x[k.nxv++] = XKern{&launch_x_wave<T, N, MODE_FIRST, 2, 2>, &launch_x_wave<T, N, MODE_ITER, 2, 2>,
+                         &launch_x_wave<T, N, MODE_EXPORT, 2, 2>, 4};
+  }
+  if constexpr (4 * N * 3 * (int)sizeof(cx<T>) <= 56 * 1024) {
+    k.x[k.nxv++] = XKern{&launch_x_wave<T, N, MODE_FIRST, 1, 4>, &launch_x_wave<T, N, MODE_ITER, 1, 4>,
+                         &launch_x_wave<T, N, MODE_EXPORT, 1, 4>, 4};
+  }
+  // wavefront z-sweep on 64-byte tiles when its six regions fit in 64 KB
+  {
     constexpr int W = 64 / (int)sizeof(cx<T>);
-    k.z[k.nzv++] = ZKern{&launch_z_pipe<T, N>, W, clamp_int(round64(W * N), 64, 1024), -1};
+    if constexpr (6 * N * (W | 1) * (int)sizeof(cx<T>) <= 64 * 1024)
+      k.z[k.nzv++] = ZKern{&launch_z_wave<T, N, W>, W, 384, -1};
   }
   return k;
 }
