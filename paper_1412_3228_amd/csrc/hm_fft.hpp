@@ -1,5 +1,5 @@
-// Workgroup-cooperative mixed-radix (3, 5, 7) Stockham FFT on lines staged
-// in LDS.  The discrete Fourier transforms of Section 2 run on odd grids, so
+// Workgroup-cooperative mixed-radix Stockham FFT on lines staged in LDS;
+// radices are products of 3, 5 and 7 (composite ones computed in registers).  The discrete Fourier transforms of Section 2 run on odd grids, so
 // every line length is a product of odd radices; no power-of-two tricks.
 //
 // Layout: a workgroup transforms L lines of length N held in LDS as
@@ -18,29 +18,9 @@
 #pragma once
 
 #include "hm_common.hpp"
+#include "hm_roots.hpp"
 
 namespace hm {
-
-// cos / sin (2 pi j / R), j = 0..R-1.
-template <int R> struct Roots;
-template <> struct Roots<3> {
-  static constexpr double c[3] = {1.0, -0.5, -0.5};
-  static constexpr double s[3] = {0.0, 0.8660254037844386467637, -0.8660254037844386467637};
-};
-template <> struct Roots<5> {
-  static constexpr double c[5] = {1.0, 0.3090169943749474241023, -0.8090169943749474241023,
-                                  -0.8090169943749474241023, 0.3090169943749474241023};
-  static constexpr double s[5] = {0.0, 0.9510565162951535721164, 0.5877852522924731291687,
-                                  -0.5877852522924731291687, -0.9510565162951535721164};
-};
-template <> struct Roots<7> {
-  static constexpr double c[7] = {1.0, 0.623489801858733530525, -0.2225209339563144042889,
-                                  -0.9009688679024191262361, -0.9009688679024191262361,
-                                  -0.2225209339563144042889, 0.623489801858733530525};
-  static constexpr double s[7] = {0.0, 0.7818314824680298087084, 0.9749279121818236070181,
-                                  0.4338837391175581204758, -0.4338837391175581204758,
-                                  -0.9749279121818236070181, -0.7818314824680298087084};
-};
 
 // In-register DFT of odd size R with exponent sign SIGN (-1 forward, +1 inverse):
 // y_k = sum_m x_m w^(k m), w = exp(SIGN 2 pi i / R).  Pairs m, R - m share
@@ -85,28 +65,110 @@ __device__ __forceinline__ void dft_small(cx<T>* x) {
   for (int k = 0; k < R; ++k) x[k] = y[k];
 }
 
-// Compile-time radix schedule of a length: 7s, then 5s, then 3s.
-template <int N> struct FftPlan {
-  static constexpr int passes() {
+constexpr int smallest_factor(int r) { return r % 3 == 0 ? 3 : (r % 5 == 0 ? 5 : (r % 7 == 0 ? 7 : r)); }
+
+// In-register DFT of any radix R whose prime factors are 3, 5, 7, computed
+// as A x B with A the smallest factor: with n = B n1 + n2 and k = k1 + A k2,
+// X[k1 + A k2] = sum_n2 w_B^(n2 k2) w_R^(n2 k1) sum_n1 x[B n1 + n2] w_A^(n1 k1).
+// The inner DFTs leave Y[n2][k1] at position B k1 + n2, the constant twiddles
+// w_R^(n2 k1) follow, the outer DFTs leave X[k1 + A k2] at position
+// B k1 + k2, and a final register permutation restores natural order.
+template <typename T, int R, int SIGN>
+__device__ __forceinline__ void dft_radix(cx<T>* x) {
+  if constexpr (R == 3 || R == 5 || R == 7) {
+    dft_small<T, R, SIGN>(x);
+  } else {
+    constexpr int A = smallest_factor(R);
+    constexpr int B = R / A;
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+      cx<T> t[A];
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) t[n1] = x[B * n1 + n2];
+      dft_small<T, A, SIGN>(t);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) x[B * k1 + n2] = t[k1];
+    }
+#pragma unroll
+    for (int k1 = 1; k1 < A; ++k1) {
+#pragma unroll
+      for (int n2 = 1; n2 < B; ++n2) {
+        const int j = (n2 * k1) % R;
+        const cx<T> w = {T(Roots<R>::c[j]), T(SIGN) * T(Roots<R>::s[j])};
+        x[B * k1 + n2] = c_mul(x[B * k1 + n2], w);
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) dft_radix<T, B, SIGN>(x + B * k1);
+    cx<T> y[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) y[k] = x[B * (k % A) + k / A];
+#pragma unroll
+    for (int k = 0; k < R; ++k) x[k] = y[k];
+  }
+}
+
+// Largest radix of a precision's schedules: the butterflies live in
+// registers, so doubles get smaller ones.
+template <typename T> constexpr int max_radix() { return sizeof(T) == 8 ? 9 : 27; }
+
+// Compile-time radix schedule of a length: its prime factors (7s, then 5s,
+// then 3s) merged greedily into radices no larger than RMAX, largest first
+// (the first pass needs no twiddles).
+template <int N, int RMAX> struct FftPlan {
+  static constexpr int nprime() {
     int n = N, c = 0;
     while (n % 7 == 0) { n /= 7; ++c; }
     while (n % 5 == 0) { n /= 5; ++c; }
     while (n % 3 == 0) { n /= 3; ++c; }
     return n == 1 ? c : -1;
   }
-  static constexpr int radix(int p) {
+  static constexpr int prime(int i) {
     int n = N, c = 0;
-    while (n % 7 == 0) { if (c == p) return 7; n /= 7; ++c; }
-    while (n % 5 == 0) { if (c == p) return 5; n /= 5; ++c; }
-    while (n % 3 == 0) { if (c == p) return 3; n /= 3; ++c; }
+    while (n % 7 == 0) { if (c == i) return 7; n /= 7; ++c; }
+    while (n % 5 == 0) { if (c == i) return 5; n /= 5; ++c; }
+    while (n % 3 == 0) { if (c == i) return 3; n /= 3; ++c; }
     return 1;
+  }
+  // merged radices in factor order
+  static constexpr int merged(int p, bool count_only) {
+    int cnt = 0, cur = 1;
+    for (int i = 0; i < nprime(); ++i) {
+      const int f = prime(i);
+      if (cur * f > RMAX && cur > 1) {
+        if (!count_only && cnt == p) return cur;
+        ++cnt;
+        cur = 1;
+      }
+      cur *= f;
+    }
+    if (cur > 1) {
+      if (!count_only && cnt == p) return cur;
+      ++cnt;
+    }
+    return count_only ? cnt : 1;
+  }
+  static constexpr int passes() { return nprime() < 0 ? -1 : merged(0, true); }
+  // pass p uses the merged radices sorted by decreasing size
+  static constexpr int radix(int p) {
+    int r[16] = {};
+    const int n = passes();
+    for (int i = 0; i < n; ++i) r[i] = merged(i, false);
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j)
+        if (r[j] > r[i]) {
+          const int t = r[i];
+          r[i] = r[j];
+          r[j] = t;
+        }
+    return r[p];
   }
   static constexpr int stride(int p) {
     int s = 1;
     for (int q = 0; q < p; ++q) s *= radix(q);
     return s;
   }
-  static_assert(passes() >= 0, "line length must be a product of 3, 5 and 7");
+  static_assert(nprime() >= 0, "line length must be a product of 3, 5 and 7");
 };
 
 // Ordering of LDS accesses between the lanes of one wavefront: LDS executes
@@ -159,7 +221,7 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid) {
           v[q][r] = c_mul(v[q][r], w);
         }
       }
-      dft_small<T, R, SIGN>(v[q]);
+      dft_radix<T, R, SIGN>(v[q]);
       const int base = (j / NS) * NS * R + jm;
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[(base + r * NS) * LD + l] = v[q][r];
@@ -170,11 +232,12 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid) {
 
 // Transforms the L lines in buf.  The caller synchronises before the call
 // (data staged); the buffer is complete and synchronised on return.
-template <typename T, int N, int L, int NT, int SIGN, int LD = L, int P = 0>
+template <typename T, int N, int L, int NT, int SIGN, int LD = L, int RMAX = max_radix<T>(), int P = 0>
 __device__ __forceinline__ void fft_lines(cx<T>* buf, const cx<T>* tw, int tid) {
-  if constexpr (P < FftPlan<N>::passes()) {
-    fft_pass<T, N, L, NT, FftPlan<N>::radix(P), FftPlan<N>::stride(P), SIGN, LD>(buf, tw, tid);
-    fft_lines<T, N, L, NT, SIGN, LD, P + 1>(buf, tw, tid);
+  using PL = FftPlan<N, RMAX>;
+  if constexpr (P < PL::passes()) {
+    fft_pass<T, N, L, NT, PL::radix(P), PL::stride(P), SIGN, LD>(buf, tw, tid);
+    fft_lines<T, N, L, NT, SIGN, LD, RMAX, P + 1>(buf, tw, tid);
   }
 }
 
@@ -182,8 +245,9 @@ __device__ __forceinline__ void fft_lines(cx<T>* buf, const cx<T>* tw, int tid) 
 // the caller orders its own LDS writes before the call with wave_sync().
 template <typename T, int N, int L, int SIGN, int LD = L, int P = 0>
 __device__ __forceinline__ void fft_lines_wave(cx<T>* buf, const cx<T>* tw, int lane) {
-  if constexpr (P < FftPlan<N>::passes()) {
-    fft_pass<T, N, L, 64, FftPlan<N>::radix(P), FftPlan<N>::stride(P), SIGN, LD, true>(buf, tw, lane);
+  using PL = FftPlan<N, max_radix<T>()>;
+  if constexpr (P < PL::passes()) {
+    fft_pass<T, N, L, 64, PL::radix(P), PL::stride(P), SIGN, LD, true>(buf, tw, lane);
     fft_lines_wave<T, N, L, SIGN, LD, P + 1>(buf, tw, lane);
   }
 }

@@ -55,42 +55,73 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Material constants of one problem in the working precision, copied into
+// registers once per block (the voxel loop stores to global memory, so
+// values read through the parameter pointer would otherwise be re-read for
+// every voxel).
+template <typename T> struct VoxelMaterial {
+  T pl[2], pm[2];  // phase Lame parameters
+  T pure1[2];      // lambda_phase - lambda0
+  T pure2[2];      // 2 mu_phase - 2 mu0
+  T rl, rm2;       // lambda0, 2 mu0
+  int rule, nsph;
+  const double* sph;
+};
+
+template <typename T> __device__ __forceinline__ VoxelMaterial<T> load_material(const ProblemParams& P) {
+  VoxelMaterial<T> m;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    m.pl[i] = T(P.pl[i]);
+    m.pm[i] = T(P.pm[i]);
+  }
+  m.rl = T(P.rl);
+  m.rm2 = T(2.0 * P.rm);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    m.pure1[i] = m.pl[i] - m.rl;
+    m.pure2[i] = T(2.0 * P.pm[i]) - m.rm2;
+  }
+  m.rule = P.rule;
+  m.nsph = P.nsph;
+  m.sph = P.sph;
+  return m;
+}
+
 // Polarization at one voxel: tau = (c~ - c0) : e, from the voxel's
 // fraction f and normal-sphere id k.
 template <typename T>
-__device__ __forceinline__ void voxel_tau(const SolveArgs& a, const ProblemParams& P, SolverState* st, T f, int k,
-                                          int x, int y, int z, const T e[6], T tau[6]) {
+__device__ __forceinline__ void voxel_tau(const SolveArgs& a, const VoxelMaterial<T>& M, SolverState* st, T f,
+                                          int k, int x, int y, int z, const T e[6], T tau[6]) {
   Coef<T> c;
   c.aniso = false;
   c.a3 = c.a4 = c.a5 = T(0);
   if (f == T(0)) {
-    c.a1 = T(P.pl[0]);
-    c.a2 = T(2.0 * P.pm[0]);
+    c.a1 = M.pure1[0];
+    c.a2 = M.pure2[0];
   } else if (f == T(1)) {
-    c.a1 = T(P.pl[1]);
-    c.a2 = T(2.0 * P.pm[1]);
+    c.a1 = M.pure1[1];
+    c.a2 = M.pure2[1];
   } else {
-    const T pl[2] = {T(P.pl[0]), T(P.pl[1])};
-    const T pm[2] = {T(P.pm[0]), T(P.pm[1])};
-    int rule = P.rule;
+    int rule = M.rule;
     if (rule == RULE_NONE) {
       atomicOr(&st->flags, FLAG_NONE_FRACTIONAL);
       rule = RULE_VOIGT;
     }
-    rule_coefficients<T>(rule, f, pl, pm, c);
+    rule_coefficients<T>(rule, f, M.pl, M.pm, c);
     if (c.aniso) {
-      if (k >= P.nsph) atomicOr(&st->flags, FLAG_BAD_INCL);
-      if (k >= 0 && k < P.nsph) {
-        interface_normal<T>(P.sph, k, x, y, z, a.nx, a.ny, a.nz, a.dim, c.n);
+      if (k >= M.nsph) atomicOr(&st->flags, FLAG_BAD_INCL);
+      if (k >= 0 && k < M.nsph) {
+        interface_normal<T>(M.sph, k, x, y, z, a.nx, a.ny, a.nz, a.dim, c.n);
       } else {
         c.n[0] = T(1);
         c.n[1] = T(0);
         c.n[2] = T(0);
       }
     }
+    c.a1 -= M.rl;
+    c.a2 -= M.rm2;
   }
-  c.a1 -= T(P.rl);
-  c.a2 -= T(2.0 * P.rm);
   apply_form<T>(c, e, tau);
 }
 
@@ -98,65 +129,75 @@ __device__ __forceinline__ void voxel_tau(const SolveArgs& a, const ProblemParam
 // A block owns L consecutive (y, z) lines.  All of its global reads (the
 // six half-lines of each line and the material of its voxels) are issued
 // into registers before any LDS work, so each block keeps its whole input
-// in flight at once.
-template <typename T, int NX, int L, int NT, int MODE>
+// in flight at once.  Element loops give each wavefront whole rows (a
+// component pair of one line, or one line of voxels) with the lanes along
+// kx or x, so row indices are wave-uniform and need no per-lane division.
+template <typename T, int NX, int L, int NT, int MODE, int RMAX = max_radix<T>()>
 __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
   constexpr int LL = 3 * L;
   constexpr int LD = LL | 1;  // odd row stride: element rows spread over the banks
   constexpr int H = (NX + 1) / 2;
-  constexpr int NLD = 3 * L * H;  // (pair, line, kx) items
-  constexpr int QL = (NLD + NT - 1) / NT;
-  constexpr int NV = L * NX;  // voxels of the block
-  constexpr int QV = (NV + NT - 1) / NT;
+  constexpr int NW = NT / 64;                   // waves
+  constexpr int KH = (H + 63) / 64;             // 64-lane chunks of a half line
+  constexpr int KX = (NX + 63) / 64;            // 64-lane chunks of a line
+  constexpr int RP = (LL + NW - 1) / NW;        // (pair, line) rows per wave
+  constexpr int RV = (L + NW - 1) / NW;         // voxel lines per wave
   __shared__ cx<T> buf[NX * LD];
   __shared__ cx<T> s_tw[NX];
-  __shared__ double red[6][NT / 64];
+  __shared__ double red[6][NW];
   const int tid = threadIdx.x;
+  const int wv = tid >> 6, lane = tid & 63;
   const int load = blockIdx.y;
   SolverState* st = a.state + load;
   if (MODE != MODE_EXPORT && st->done) return;
   const LoadParams& LP = a.prm->loads[load];
   const ProblemParams& P = a.prm->probs[LP.prob];
+  const VoxelMaterial<T> MAT = load_material<T>(P);
   const int nlines = a.ny * a.nz;
   const int line0 = blockIdx.x * L;
   const int Hp = a.Hp;
   const size_t cs = (size_t)nlines * Hp;
   cx<T>* spec = static_cast<cx<T>*>(a.spec) + (size_t)load * 6 * cs;
 
-  cx<T> pa[QL], pb[QL];
+  // row r = p * L + l: component pair p of line l (wave-uniform)
+  cx<T> pa[RP][KH], pb[RP][KH];
   if (MODE != MODE_FIRST) {
 #pragma unroll
-    for (int q = 0; q < QL; ++q) {
-      const int idx = tid + q * NT;
-      pa[q] = cx<T>{T(0), T(0)};
-      pb[q] = cx<T>{T(0), T(0)};
-      if (idx < NLD) {
-        const int p = idx / (L * H);
-        const int rem = idx - p * (L * H);
-        const int l = rem / H;
-        const int k = rem - l * H;
-        const int line = line0 + l;
-        if (line < nlines) {
-          pa[q] = spec[(size_t)(2 * p) * cs + (size_t)line * Hp + k];
-          pb[q] = spec[(size_t)(2 * p + 1) * cs + (size_t)line * Hp + k];
-        }
+    for (int i = 0; i < RP; ++i) {
+      const int r = wv + NW * i;
+      const int p = r / L, l = r - (r / L) * L;
+      const int line = line0 + l;
+      const bool rok = r < LL && line < nlines;
+      const cx<T>* ra = spec + (size_t)(2 * p) * cs + (size_t)line * Hp;
+      const cx<T>* rb = ra + cs;
+#pragma unroll
+      for (int m = 0; m < KH; ++m) {
+        const int k = lane + 64 * m;
+        const bool ok = rok && k < H;
+        pa[i][m] = ok ? ra[k] : cx<T>{T(0), T(0)};
+        pb[i][m] = ok ? rb[k] : cx<T>{T(0), T(0)};
       }
     }
   }
-  T fv[QV];
-  int iv[QV];
+  T fv[RV][KX];
+  int iv[RV][KX];
   if (MODE != MODE_EXPORT) {
     const T* frac = static_cast<const T*>(P.frac);
 #pragma unroll
-    for (int q = 0; q < QV; ++q) {
-      const int idx = tid + q * NT;
-      const int l = idx / NX, x = idx - l * NX, line = line0 + l;
-      fv[q] = T(0);
-      iv[q] = -1;
-      if (idx < NV && line < nlines) {
-        const size_t v = (size_t)line * NX + x;
-        fv[q] = frac[v];
-        if (P.incl) iv[q] = P.incl[v];
+    for (int i = 0; i < RV; ++i) {
+      const int l = wv + NW * i;
+      const int line = line0 + l;
+      const bool rok = l < L && line < nlines;
+#pragma unroll
+      for (int m = 0; m < KX; ++m) {
+        const int x = lane + 64 * m;
+        fv[i][m] = T(0);
+        iv[i][m] = -1;
+        if (rok && x < NX) {
+          const size_t v = (size_t)line * NX + x;
+          fv[i][m] = frac[v];
+          if (P.incl) iv[i][m] = P.incl[v];
+        }
       }
     }
   }
@@ -164,28 +205,32 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
 
   if (MODE != MODE_FIRST) {
 #pragma unroll
-    for (int q = 0; q < QL; ++q) {
-      const int idx = tid + q * NT;
-      if (idx < NLD) {
-        const int p = idx / (L * H);
-        const int rem = idx - p * (L * H);
-        const int l = rem / H;
-        const int k = rem - l * H;
-        const cx<T> A = pa[q], B = pb[q];
-        buf[k * LD + p * L + l] = cx<T>{A.x - B.y, A.y + B.x};
-        if (k > 0) buf[(NX - k) * LD + p * L + l] = cx<T>{A.x + B.y, B.x - A.y};
+    for (int i = 0; i < RP; ++i) {
+      const int r = wv + NW * i;
+      if (r >= LL) continue;
+      const int p = r / L, l = r - (r / L) * L;
+      const int col = p * L + l;
+#pragma unroll
+      for (int m = 0; m < KH; ++m) {
+        const int k = lane + 64 * m;
+        if (k < H) {
+          const cx<T> A = pa[i][m], B = pb[i][m];
+          buf[k * LD + col] = cx<T>{A.x - B.y, A.y + B.x};
+          if (k > 0) buf[(NX - k) * LD + col] = cx<T>{A.x + B.y, B.x - A.y};
+        }
       }
     }
     __syncthreads();
-    fft_lines<T, NX, LL, NT, +1, LD>(buf, s_tw, tid);
+    fft_lines<T, NX, LL, NT, +1, LD, RMAX>(buf, s_tw, tid);
   }
 
   if (MODE == MODE_EXPORT) {
     const size_t N = (size_t)nlines * NX;
     T* out = static_cast<T*>(a.eps_out) + (size_t)load * 6 * N;
-    for (int idx = tid; idx < NV; idx += NT) {
-      const int l = idx / NX, x = idx - l * NX, line = line0 + l;
-      if (line < nlines) {
+    for (int l = wv; l < L; l += NW) {
+      const int line = line0 + l;
+      if (line >= nlines) continue;
+      for (int x = lane; x < NX; x += 64) {
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
           const cx<T> Z = buf[x * LD + p * L + l];
@@ -199,52 +244,62 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
 
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int q = 0; q < QV; ++q) {
-    const int idx = tid + q * NT;
-    if (idx >= NV) continue;
-    const int l = idx / NX, x = idx - l * NX, line = line0 + l;
-    T e[6];
-    if (MODE == MODE_FIRST) {
+  for (int i = 0; i < RV; ++i) {
+    const int l = wv + NW * i;
+    if (l >= L) continue;
+    const int line = line0 + l;
+    const int y = line % a.ny, z = line / a.ny;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) e[c] = T(LP.E[c]);
-    } else {
+    for (int m = 0; m < KX; ++m) {
+      const int x = lane + 64 * m;
+      if (x >= NX) continue;
+      T e[6];
+      if (MODE == MODE_FIRST) {
 #pragma unroll
-      for (int p = 0; p < 3; ++p) {
-        const cx<T> Z = buf[x * LD + p * L + l];
-        e[2 * p] = Z.x;
-        e[2 * p + 1] = Z.y;
+        for (int c = 0; c < 6; ++c) e[c] = T(LP.E[c]);
+      } else {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          const cx<T> Z = buf[x * LD + p * L + l];
+          e[2 * p] = Z.x;
+          e[2 * p + 1] = Z.y;
+        }
       }
-    }
-    T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-    if (line < nlines) {
-      const int y = line % a.ny, z = line / a.ny;
-      voxel_tau<T>(a, P, st, fv[q], iv[q], x, y, z, e, tau);
+      T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+      if (line < nlines) {
+        voxel_tau<T>(a, MAT, st, fv[i][m], iv[i][m], x, y, z, e, tau);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) acc[c] += (double)tau[c];
-    }
+        for (int c = 0; c < 6; ++c) acc[c] += (double)tau[c];
+      }
 #pragma unroll
-    for (int p = 0; p < 3; ++p) buf[x * LD + p * L + l] = cx<T>{tau[2 * p], tau[2 * p + 1]};
+      for (int p = 0; p < 3; ++p) buf[x * LD + p * L + l] = cx<T>{tau[2 * p], tau[2 * p + 1]};
+    }
   }
   __syncthreads();
-  fft_lines<T, NX, LL, NT, -1, LD>(buf, s_tw, tid);
+  fft_lines<T, NX, LL, NT, -1, LD, RMAX>(buf, s_tw, tid);
 
-  for (int idx = tid; idx < NLD; idx += NT) {
-    const int p = idx / (L * H);
-    const int rem = idx - p * (L * H);
-    const int l = rem / H;
-    const int k = rem - l * H;
+#pragma unroll
+  for (int i = 0; i < RP; ++i) {
+    const int r = wv + NW * i;
+    if (r >= LL) continue;
+    const int p = r / L, l = r - (r / L) * L;
     const int line = line0 + l;
-    if (line < nlines) {
-      const cx<T> Z = buf[k * LD + p * L + l];
-      const cx<T> Zc = c_conj(buf[((NX - k) % NX) * LD + p * L + l]);
-      const cx<T> A = {T(0.5) * (Z.x + Zc.x), T(0.5) * (Z.y + Zc.y)};
-      const cx<T> B = {T(0.5) * (Z.y - Zc.y), T(-0.5) * (Z.x - Zc.x)};
-      spec[(size_t)(2 * p) * cs + (size_t)line * Hp + k] = A;
-      spec[(size_t)(2 * p + 1) * cs + (size_t)line * Hp + k] = B;
+    if (line >= nlines) continue;
+    const int col = p * L + l;
+    cx<T>* ra = spec + (size_t)(2 * p) * cs + (size_t)line * Hp;
+    cx<T>* rb = ra + cs;
+#pragma unroll
+    for (int m = 0; m < KH; ++m) {
+      const int k = lane + 64 * m;
+      if (k < H) {
+        const cx<T> Z = buf[k * LD + col];
+        const cx<T> Zc = c_conj(buf[((NX - k) % NX) * LD + col]);
+        ra[k] = cx<T>{T(0.5) * (Z.x + Zc.x), T(0.5) * (Z.y + Zc.y)};
+        rb[k] = cx<T>{T(0.5) * (Z.y - Zc.y), T(-0.5) * (Z.x - Zc.x)};
+      }
     }
   }
   // deterministic block sums of the six tau components
-  const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     double v = acc[c];
@@ -256,7 +311,7 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
   if (tid < 6) {
     double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < NT / 64; ++i) s += red[tid][i];
+    for (int i = 0; i < NW; ++i) s += red[tid][i];
     a.taupart[((size_t)load * a.g2 + blockIdx.x) * 6 + tid] = s;
   }
 }
@@ -342,6 +397,8 @@ __device__ __forceinline__ void fold_component(int c, cx<T> v, Slot<T>& z) {
   z.a2.y += v.y * w2;
 }
 
+// The z-sweep parks several frequency slots per thread in registers, so its
+// butterflies stay at radix 9 or below.
 // Entry (i, j) of m * [(n (x) a + a (x) n) / (2 mu0) - cc (n.a) n (x) n].
 template <typename T>
 __device__ __forceinline__ cx<T> gamma_entry(T ni, T nj, cx<T> ai, cx<T> aj, cx<T> na, T inv2mu, T cc, T m) {
@@ -427,7 +484,7 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
           nxt[g][q] = ok[q] ? sp[(size_t)(c0 + CG + g) * plane + off[q]] : cx<T>{T(0), T(0)};
     }
     __syncthreads();
-    fft_lines<T, NZ, LW, NT, -1, LD>(buf, s_tw, tid);
+    fft_lines<T, NZ, LW, NT, -1, LD, 9>(buf, s_tw, tid);
 #pragma unroll
     for (int g = 0; g < CG; ++g)
 #pragma unroll
@@ -491,7 +548,7 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
       }
     }
     __syncthreads();
-    fft_lines<T, NZ, LW, NT, +1, LD>(buf, s_tw, tid);
+    fft_lines<T, NZ, LW, NT, +1, LD, 9>(buf, s_tw, tid);
 #pragma unroll
     for (int g = 0; g < CG; ++g)
 #pragma unroll
@@ -529,6 +586,7 @@ __global__ __launch_bounds__(64 * NW) void k_xsweep_wave(SolveArgs a) {
   if (MODE != MODE_EXPORT && st->done) return;
   const LoadParams& LP = a.prm->loads[load];
   const ProblemParams& P = a.prm->probs[LP.prob];
+  const VoxelMaterial<T> MAT = load_material<T>(P);
   const int nlines = a.ny * a.nz;
   const int line0 = (blockIdx.x * NW + wv) * LW;
   const int Hp = a.Hp;
@@ -632,7 +690,7 @@ __global__ __launch_bounds__(64 * NW) void k_xsweep_wave(SolveArgs a) {
     T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     if (line < nlines) {
       const int y = line % a.ny, z = line / a.ny;
-      voxel_tau<T>(a, P, st, fv[q], iv[q], x, y, z, e, tau);
+      voxel_tau<T>(a, MAT, st, fv[q], iv[q], x, y, z, e, tau);
 #pragma unroll
       for (int c = 0; c < 6; ++c) acc[c] += (double)tau[c];
     }
@@ -936,9 +994,12 @@ struct AxisKernels {
 constexpr int clamp_int(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 constexpr int round64(int v) { return (v + 63) / 64 * 64; }
 
-// xsweep variant v: lines per block from {8, 4, 2}, limited to 56 KB of LDS.
+// xsweep variant v: lines per block from {8, 4, 2}, limited to 56 KB of LDS;
+// v = 3 is v = 0 with butterflies of radix 9 or below (fewer registers than
+// the single-precision default of up to 27).
 template <typename T, int N, int V> struct XTile {
-  static constexpr int want = V == 0 ? 8 : (V == 1 ? 4 : 2);
+  static constexpr int want = (V == 0 || V == 3) ? 8 : (V == 1 ? 4 : 2);
+  static constexpr int RMAX = V == 3 ? 9 : max_radix<T>();
   static constexpr int cap = (56 * 1024) / (3 * N * (int)sizeof(cx<T>));
   static constexpr int L = clamp_int(want < cap ? want : cap, 1, 8);
   static constexpr int NT = 256;
@@ -970,7 +1031,8 @@ template <typename T, int N, int V> struct ZTile {
 template <typename T, int NX, int MODE, int V>
 hipError_t launch_x(const SolveArgs& a, hipStream_t s) {
   using TL = XTile<T, NX, V>;
-  hipLaunchKernelGGL((k_xsweep<T, NX, TL::L, TL::NT, MODE>), dim3(a.g2, a.n_load), dim3(TL::NT), 0, s, a);
+  hipLaunchKernelGGL((k_xsweep<T, NX, TL::L, TL::NT, MODE, TL::RMAX>), dim3(a.g2, a.n_load), dim3(TL::NT), 0, s,
+                     a);
   return hipGetLastError();
 }
 template <typename T, int NY, int SIGN, int V>
@@ -1020,6 +1082,8 @@ AxisKernels make_axis_kernels() {
   k.nxv = 1;
   if (XTile<T, N, 1>::L != k.x[0].lines) k.x[k.nxv++] = make_x<T, N, 1>();
   if (XTile<T, N, 2>::L != k.x[k.nxv - 1].lines) k.x[k.nxv++] = make_x<T, N, 2>();
+  if constexpr (FftPlan<N, XTile<T, N, 3>::RMAX>::passes() != FftPlan<N, XTile<T, N, 0>::RMAX>::passes())
+    k.x[k.nxv++] = make_x<T, N, 3>();
   k.y[0] = make_y<T, N, 0>();
   k.y[1] = make_y<T, N, 1>();
   k.nyv = 2;
