@@ -133,13 +133,15 @@ def _sync():
     torch.cuda.synchronize()
 
 
-def kernel_bytes(n, prec, kernel):
+def kernel_bytes(n, prec, kernel, n_frac=0):
     """Algorithmic HBM bytes of one launch of `kernel` for ONE load case.
 
     The stored state is the x-half-spectrum: 6 components x nz x ny x H
     complex values (H = (nx + 1) / 2).  xsweep reads and writes it and reads
-    the material (fraction + normal-sphere id); each ysweep reads and writes
-    it; zsweep also reads and writes the 3-component traction history.
+    the material: a 4-byte id per voxel and, for each of the n_frac
+    fractional voxels, its 8-real row of the stiffness table; each ysweep
+    reads and writes the spectrum; zsweep also reads and writes the
+    3-component traction history.
     """
     nx, ny, nz = n
     H = (nx + 1) // 2
@@ -147,7 +149,7 @@ def kernel_bytes(n, prec, kernel):
     plane = nz * ny * H
     spec = 2 * 6 * plane * cb
     if kernel == "xsweep":
-        return spec + nx * ny * nz * ((8 if prec == "fp64" else 4) + 4)
+        return spec + nx * ny * nz * 4 + n_frac * 8 * (cb // 2)
     if kernel in ("ysweep_fwd", "ysweep_inv"):
         return spec
     if kernel == "zsweep":
@@ -177,19 +179,7 @@ def run_path(hm, w, prec, contrast, dev, profile=True, C_target=None, max_iter=5
             "dLdphase": dph}
 
 
-def _kernel_key(dom, prec, n, sched):
-    """Name of the dominant kernel's instantiation, as in the rocprofv3 summaries."""
-    t = "double" if prec == "fp64" else "float"
-    if dom == "xsweep":
-        return "xsweep<%s,%d,%d,256,1>" % (t, n[0], sched["x_lines"])
-    if dom in ("ysweep_fwd", "ysweep_inv"):
-        return "ysweep<%s,%d,%d,256,%d>" % (t, n[1], sched["y_width"], -1 if dom == "ysweep_fwd" else 1)
-    if dom == "zsweep":
-        return "zsweep<%s,%d,%d,%d,%d>" % (t, n[2], sched["z_width"], sched["z_threads"], sched["z_groups"])
-    return dom
-
-
-def roofline(timings, n, prec, reports):
+def roofline(timings, n, prec, reports, n_frac=0):
     """Dominant kernel of the profiled solves, its algorithmic bandwidth vs peak."""
     tot = {}
     for t in timings:
@@ -200,9 +190,9 @@ def roofline(timings, n, prec, reports):
     its = sum(t["iterations"] for t in timings)
     active = sum(sum(r["iters"] + 1 for r in rep) for rep in reports) / max(1, its)
     ms = tot[dom] / its
-    bytes_launch = kernel_bytes(n, prec, dom) * active
+    bytes_launch = kernel_bytes(n, prec, dom, n_frac) * active
     achieved = bytes_launch / (ms * 1e-3) / 1e9
-    key = _kernel_key(dom, prec, n, timings[-1]["schedule"])
+    key = timings[-1]["kernels"][dom]
     tr = measured_traffic(key)
     # the counters were taken with all load cases active: scale to the average active count
     traffic = None if tr is None else tr["bytes"] * active / 6.0
@@ -295,6 +285,8 @@ def main():
         o = hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, prec="fp64", tol=1e-9,
                                    max_iter=20000, check_every=32, use_graph=True)
         ref[c] = o["C"]
+        # fractional voxels (rows of the stiffness table), a property of the geometry
+        n_frac = int(((frac > 0) & (frac < 1)).sum().item())
         u = target_perturbation(5, (6, 6))
         Ct = ref[c] * (1.0 + 0.05 * u)
         targets[c] = 0.5 * (Ct + Ct.T)
@@ -335,7 +327,7 @@ def main():
         paths[prec] = {"value": vit / secs, "seconds": secs, "voxel_iterations": vit,
                        "ceff_rel_err_vs_fp64_tol1e-9": errs, "iters": iters, "status": status,
                        "final_equilibrium_error": finals,
-                       "roofline": roofline(timings, n, prec, reps)}
+                       "roofline": roofline(timings, n, prec, reps, n_frac)}
     mixed, fp64 = paths["mixed"], paths["fp64"]
     line = {
         "metric": METRIC,

@@ -124,6 +124,9 @@ typedef struct {
   int z_width;    /*   kx columns per zsweep block                         */
   int z_threads;  /*   zsweep block size                                   */
   int z_groups;   /*   and components per zsweep LDS transform             */
+  char kernel[5][64]; /* instances of the five kernels (iteration mode), as
+                         name<template arguments>, e.g. zsweep<float,125,
+                         16,512,1,2> for k_zsweep                          */
 } hm_timing;
 
 /* Per-load-case outcome. */

@@ -180,6 +180,12 @@ struct Plan {
   char* prm = nullptr;       // parameter blob: SolveParams, loads, problems, spheres
   char* prm_host = nullptr;  // pinned staging of the blob
   size_t prm_cap = 0;
+  int* mid = nullptr;        // material ids of the group's problems, back to back
+  size_t mid_cap = 0;        // entries
+  void* coef = nullptr;      // stiffness table rows (8 reals each)
+  size_t coef_cap = 0;       // rows
+  int* mcount = nullptr;     // [2]: rows handed out, data flags
+  int* mcount_host = nullptr;
   void* tw[3] = {nullptr, nullptr, nullptr};
   SolveArgs args;
   hipStream_t cap_stream = nullptr;
@@ -200,6 +206,10 @@ void free_plan(Plan* p) {
   (void)hipFree(p->state);
   (void)hipFree(p->errhist);
   (void)hipFree(p->prm);
+  (void)hipFree(p->mid);
+  (void)hipFree(p->coef);
+  (void)hipFree(p->mcount);
+  if (p->mcount_host) (void)hipHostFree(p->mcount_host);
   for (int a = 0; a < 3; ++a) (void)hipFree(p->tw[a]);
   if (p->state_host) (void)hipHostFree(p->state_host);
   if (p->prm_host) (void)hipHostFree(p->prm_host);
@@ -521,6 +531,22 @@ int upload_params(Group& g, const std::vector<ProblemIn>& all, const hm_solve_op
       p->graph = nullptr;
     }
   }
+  size_t nmid = 0;
+  for (int q : g.probs) nmid += (size_t)all[q].grid.n[0] * all[q].grid.n[1] * all[q].grid.n[2];
+  if (nmid > p->mid_cap) {
+    (void)hipFree(p->mid);
+    p->mid = nullptr;
+    p->mid_cap = 0;
+    int rc = device_alloc((void**)&p->mid, nmid * sizeof(int), "material ids");
+    if (rc) return rc;
+    p->mid_cap = nmid;
+  }
+  if (!p->coef) {
+    const size_t rows = std::max<size_t>(4096, nmid / 16);
+    int rc = device_alloc(&p->coef, rows * 8 * (p->fp64 ? 8 : 4), "stiffness table");
+    if (rc) return rc;
+    p->coef_cap = rows;
+  }
   char* h = p->prm_host;
   memset(h, 0, bytes);
   SolveParams* S = reinterpret_cast<SolveParams*>(h);
@@ -534,7 +560,7 @@ int upload_params(Group& g, const std::vector<ProblemIn>& all, const hm_solve_op
   memcpy(h + o_loads, g.loads.data(), nl * sizeof(LoadParams));
   ProblemParams* PP = reinterpret_cast<ProblemParams*>(h + o_probs);
   double* sph = reinterpret_cast<double*>(h + o_sph);
-  size_t so = 0;
+  size_t so = 0, mo = 0;
   for (int j = 0; j < np; ++j) {
     const ProblemIn& d = all[g.probs[j]];
     ProblemParams& q = PP[j];
@@ -551,6 +577,9 @@ int upload_params(Group& g, const std::vector<ProblemIn>& all, const hm_solve_op
     q.nsph = d.nsph;
     q.frac = d.frac;
     q.incl = d.incl;
+    q.mid = p->mid + mo;
+    q.coef = p->coef;
+    mo += (size_t)d.grid.n[0] * d.grid.n[1] * d.grid.n[2];
     q.sph = reinterpret_cast<const double*>(p->prm + o_sph) + so;
     for (int k = 0; k < d.nsph; ++k) {
       for (int c = 0; c < 3; ++c) sph[so + 4 * k + c] = d.sph[k].c[c];
@@ -560,6 +589,60 @@ int upload_params(Group& g, const std::vector<ProblemIn>& all, const hm_solve_op
   }
   HM_HIP(hipMemcpyAsync(p->prm, p->prm_host, bytes, hipMemcpyHostToDevice, s));
   return HM_OK;
+}
+
+int data_flags_error(int flags) {
+  if (flags & FLAG_NONE_FRACTIONAL) return fail(HM_E_DATA, "fractional voxel with HM_RULE_NONE");
+  if (flags & FLAG_BAD_INCL) return fail(HM_E_DATA, "d_incl holds a sphere index >= n_spheres");
+  return HM_OK;
+}
+
+// Builds the group's material table (ids and stiffness rows of the
+// fractional voxels, k_material) on the stream, after its parameters were
+// queued by upload_params; grows the row table and rebuilds once if it was
+// too small.  Fails with HM_E_DATA on inconsistent input, before any
+// iteration runs.
+int prepare_material(Group& g, const std::vector<ProblemIn>& all, const hm_solve_opts* opts, hipStream_t s) {
+  Plan* p = g.p;
+  int rc;
+  if (!p->mcount) {
+    if ((rc = device_alloc((void**)&p->mcount, 2 * sizeof(int), "material counter"))) return rc;
+    if (hipHostMalloc((void**)&p->mcount_host, 2 * sizeof(int), 0) != hipSuccess)
+      return fail(HM_E_NOMEM, "pinned material counter");
+  }
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    HM_HIP(hipMemsetAsync(p->mcount, 0, 2 * sizeof(int), s));
+    size_t mo = 0;
+    for (int j = 0; j < (int)g.probs.size(); ++j) {
+      const hm_grid& gr = all[g.probs[j]].grid;
+      const int N = gr.n[0] * gr.n[1] * gr.n[2];
+      const SolveParams* prm = reinterpret_cast<const SolveParams*>(p->prm);
+      const int cap = (int)std::min<size_t>(p->coef_cap, (size_t)1 << 30);
+      if (p->fp64)
+        hipLaunchKernelGGL((k_material<double>), dim3((N + 255) / 256), dim3(256), 0, s, prm, j, gr.n[0], gr.n[1],
+                           gr.n[2], gr.dim, p->mid + mo, static_cast<double*>(p->coef), cap, p->mcount);
+      else
+        hipLaunchKernelGGL((k_material<float>), dim3((N + 255) / 256), dim3(256), 0, s, prm, j, gr.n[0], gr.n[1],
+                           gr.n[2], gr.dim, p->mid + mo, static_cast<float*>(p->coef), cap, p->mcount);
+      HM_HIP(hipGetLastError());
+      mo += (size_t)N;
+    }
+    HM_HIP(hipMemcpyAsync(p->mcount_host, p->mcount, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    if ((rc = data_flags_error(p->mcount_host[1]))) return rc;
+    const size_t rows = (size_t)p->mcount_host[0];
+    if (rows <= p->coef_cap) return HM_OK;
+    // too small: grow (stays allocated for later solves), re-queue the
+    // parameters with the new table address and build again
+    (void)hipFree(p->coef);
+    p->coef = nullptr;
+    p->coef_cap = 0;
+    const size_t want = rows + rows / 4 + 1024;
+    if ((rc = device_alloc(&p->coef, want * 8 * (p->fp64 ? 8 : 4), "stiffness table"))) return rc;
+    p->coef_cap = want;
+    if ((rc = upload_params(g, all, opts, s))) return rc;
+  }
+  return fail(HM_E_DEVICE, "material table did not fit after growing");
 }
 
 // Direct launches with a HIP event before and after every kernel of one
@@ -625,6 +708,9 @@ int profiled_loop(Plan* p, const hm_solve_opts* opts, hipStream_t s) {
   t.z_width = p->Z->width;
   t.z_threads = p->Z->threads;
   t.z_groups = p->Z->groups;
+  const char* names[4] = {p->X->name, p->Y->fwd_name, p->Z->name, p->Y->inv_name};
+  for (int q = 0; q < 4; ++q) snprintf(t.kernel[q], sizeof t.kernel[q], "%s", names[q]);
+  snprintf(t.kernel[4], sizeof t.kernel[4], "finalize<%d>", kFinalizeThreads);
   for (int i = 0; i < nit; ++i)
     for (int q = 0; q < 5; ++q) t.ms[q] += dur[(size_t)5 * i + q];
   for (int q = 0; q < 5; ++q) t.ms[q] /= nit > 0 ? nit : 1;
@@ -642,6 +728,7 @@ int run_groups(std::vector<Group>& G, const std::vector<ProblemIn>& all, const h
   for (Group& g : G) {
     if ((rc = ensure_hist(g.p, opts->max_iter + 1))) return rc;
     if ((rc = upload_params(g, all, opts, s))) return rc;
+    if ((rc = prepare_material(g, all, opts, s))) return rc;
     if (opts->autotune) {
       if (!g.p->tuned && (rc = tune_plan(g.p, s))) return rc;
     } else if (opts->schedule >= 0) {
@@ -746,14 +833,9 @@ int run_groups(std::vector<Group>& G, const std::vector<ProblemIn>& all, const h
   return HM_OK;
 }
 
-// Status of one load case and the data flags of a group.
+// Status of one load case.
 int load_status(const SolverState& st) { return st.done ? st.status : HM_NOT_CONVERGED; }
 
-int data_flags_error(int flags) {
-  if (flags & FLAG_NONE_FRACTIONAL) return fail(HM_E_DATA, "fractional voxel with HM_RULE_NONE");
-  if (flags & FLAG_BAD_INCL) return fail(HM_E_DATA, "d_incl holds a sphere index >= n_spheres");
-  return HM_OK;
-}
 
 // Unit Mandel strains (tensor components) of a dimension: 6 in 3D, 3 in 2D.
 int unit_loads(int dim, double E[36], const int** idx_out) {
@@ -945,16 +1027,14 @@ int hm_solve(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const vo
                      (hipStream_t)stream, &p);
   if (rc) return rc;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  int worst = HM_OK, flags = 0;
+  int worst = HM_OK;
   for (int l = 0; l < n_load; ++l) {
     const SolverState& st = p->state_host[l];
     for (int c = 0; c < 6; ++c) sig_mean[6 * l + c] = st.sig[c];
     const int status = load_status(st);
     if (rep) rep[l] = hm_report{st.iters, status, st.err, st.err0, secs};
     worst = std::max(worst, status);
-    flags |= st.flags;
   }
-  if ((rc = data_flags_error(flags))) return rc;
   return worst;
 }
 
@@ -975,15 +1055,13 @@ int hm_effective_tensor(const hm_grid* grid, const hm_iso phases[2], hm_rule rul
   if (rc) return rc;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   assemble_mandel(k, idx, p->state_host, C_mandel);
-  int worst = HM_OK, flags = 0;
+  int worst = HM_OK;
   for (int l = 0; l < k; ++l) {
     const SolverState& st = p->state_host[l];
     const int status = load_status(st);
     if (rep) rep[l] = hm_report{st.iters, status, st.err, st.err0, secs};
     worst = std::max(worst, status);
-    flags |= st.flags;
   }
-  if ((rc = data_flags_error(flags))) return rc;
   return worst;
 }
 
@@ -1039,7 +1117,7 @@ int hm_effective_tensor_batch(const hm_problem* problems, int n_problems, const 
   }
   if ((rc = run_groups(G, all, opts, (hipStream_t)stream))) return rc;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  int worst = HM_OK, flags = 0;
+  int worst = HM_OK;
   size_t cofs = 0, rofs = 0;
   for (int q = 0; q < n_problems; ++q) {
     const Group& g = G[where[q]];
@@ -1054,12 +1132,10 @@ int hm_effective_tensor_batch(const hm_problem* problems, int n_problems, const 
       const int status = load_status(st[l]);
       if (rep) rep[rofs + l] = hm_report{st[l].iters, status, st[l].err, st[l].err0, secs};
       worst = std::max(worst, status);
-      flags |= st[l].flags;
     }
     cofs += (size_t)k * k;
     rofs += (size_t)k;
   }
-  if ((rc = data_flags_error(flags))) return rc;
   return worst;
 }
 

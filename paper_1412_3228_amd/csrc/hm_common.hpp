@@ -22,7 +22,7 @@ template <typename C, typename T> __device__ __forceinline__ C c_scale(C a, T s)
 
 // Stop codes written by the finalize kernel (mirror the public HM_* codes).
 enum : int { ST_RUNNING = -1, ST_CONVERGED = 0, ST_NOT_CONVERGED = 1, ST_STALLED = 2, ST_DIVERGED = 3 };
-// Bits of SolverState::flags.
+// Data flags raised while the material table is built.
 enum : int { FLAG_NONE_FRACTIONAL = 1, FLAG_BAD_INCL = 2 };
 
 constexpr double kDivergenceFactor = 1.0e3;
@@ -34,7 +34,6 @@ struct SolverState {
   int done;    // nonzero once the load case has stopped
   int status;  // ST_*
   int iters;   // reported iterate index
-  int flags;   // data problems seen by the kernels
   int iref;    // iteration of the last 1% improvement
   int pad0, pad1;
   double err;   // error of the last evaluated (or reported) iterate
@@ -52,6 +51,12 @@ struct ProblemParams {
   const void* frac;   // T[N]
   const int* incl;    // int32[N] or null
   const double* sph;  // [nsph][4]: centre x, y, z, radius (voxel units)
+  // Material table built once per solve from frac / incl: mid[v] = -1 for
+  // a pure matrix voxel, -2 for a pure inclusion voxel, else the row of
+  // coef (T[rows][8]: a1 - lambda0, a2 - 2 mu0, a3, a4, a5, n0, n1, n2) that
+  // holds the voxel's filtered stiffness.
+  const int* mid;
+  const void* coef;
 };
 
 // One load case: its macroscopic strain (tensor components) and problem.

@@ -25,6 +25,7 @@
 #pragma once
 
 #include <algorithm>
+#include <cstdio>
 
 #include "hm_common.hpp"
 #include "hm_fft.hpp"
@@ -55,73 +56,128 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Filtered stiffness of every fractional voxel, computed once per solve
+// (one thread per voxel of problem `prob`): rows of coef are handed out per
+// wavefront through one atomic counter (count[0]); the row order does not
+// affect any result.  count[1] collects the data flags.  Rows at or beyond
+// `cap` are not written; the caller re-runs with a larger table.
+template <typename T>
+__global__ __launch_bounds__(256) void k_material(const SolveParams* prm, int prob, int nx, int ny, int nz, int dim,
+                                                  int* mid, T* coef, int cap, int* count) {
+  const ProblemParams& P = prm->probs[prob];
+  const int N = nx * ny * nz;
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  T f = T(0);
+  if (v < N) f = static_cast<const T*>(P.frac)[v];
+  const bool fr = v < N && f != T(0) && f != T(1);
+  const unsigned long long m = __ballot(fr);
+  int base = 0;
+  if (m) {
+    const int leader = __ffsll((long long)m) - 1;
+    if (lane == leader) base = atomicAdd(&count[0], __popcll(m));
+    base = __shfl(base, leader, 64);
+  }
+  if (v >= N) return;
+  if (!fr) {
+    mid[v] = f == T(0) ? -1 : -2;
+    return;
+  }
+  const int row = base + __popcll(m & ((1ull << lane) - 1ull));
+  mid[v] = row;
+  const T pl[2] = {T(P.pl[0]), T(P.pl[1])};
+  const T pm[2] = {T(P.pm[0]), T(P.pm[1])};
+  int rule = P.rule;
+  if (rule == RULE_NONE) {
+    atomicOr(&count[1], FLAG_NONE_FRACTIONAL);
+    rule = RULE_VOIGT;
+  }
+  Coef<T> c;
+  c.n[0] = c.n[1] = c.n[2] = T(0);
+  rule_coefficients<T>(rule, f, pl, pm, c);
+  if (c.aniso) {
+    const int k = P.incl ? P.incl[v] : -1;
+    if (k >= P.nsph) atomicOr(&count[1], FLAG_BAD_INCL);
+    if (k >= 0 && k < P.nsph) {
+      const int x = v % nx, y = (v / nx) % ny, z = v / (nx * ny);
+      interface_normal<T>(P.sph, k, x, y, z, nx, ny, nz, dim, c.n);
+    } else {
+      c.n[0] = T(1);
+      c.n[1] = T(0);
+      c.n[2] = T(0);
+    }
+  }
+  if (row < cap) {
+    T* r = coef + (size_t)row * 8;
+    r[0] = c.a1 - T(P.rl);
+    r[1] = c.a2 - T(2.0 * P.rm);
+    r[2] = c.a3;
+    r[3] = c.a4;
+    r[4] = c.a5;
+    r[5] = c.n[0];
+    r[6] = c.n[1];
+    r[7] = c.n[2];
+  }
+}
+
 // Material constants of one problem in the working precision, copied into
 // registers once per block (the voxel loop stores to global memory, so
 // values read through the parameter pointer would otherwise be re-read for
 // every voxel).
 template <typename T> struct VoxelMaterial {
-  T pl[2], pm[2];  // phase Lame parameters
-  T pure1[2];      // lambda_phase - lambda0
-  T pure2[2];      // 2 mu_phase - 2 mu0
-  T rl, rm2;       // lambda0, 2 mu0
-  int rule, nsph;
-  const double* sph;
+  T pure1[2];  // lambda_phase - lambda0
+  T pure2[2];  // 2 mu_phase - 2 mu0
+  const T* coef;
+  const int* mid;
+  bool aniso;  // the rule's table rows use the normal
 };
 
 template <typename T> __device__ __forceinline__ VoxelMaterial<T> load_material(const ProblemParams& P) {
   VoxelMaterial<T> m;
+  const T rl = T(P.rl), rm2 = T(2.0 * P.rm);
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    m.pl[i] = T(P.pl[i]);
-    m.pm[i] = T(P.pm[i]);
+    m.pure1[i] = T(P.pl[i]) - rl;
+    m.pure2[i] = T(2.0 * P.pm[i]) - rm2;
   }
-  m.rl = T(P.rl);
-  m.rm2 = T(2.0 * P.rm);
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    m.pure1[i] = m.pl[i] - m.rl;
-    m.pure2[i] = T(2.0 * P.pm[i]) - m.rm2;
-  }
-  m.rule = P.rule;
-  m.nsph = P.nsph;
-  m.sph = P.sph;
+  m.coef = static_cast<const T*>(P.coef);
+  m.mid = P.mid;
+  m.aniso = P.rule == RULE_LAMINATE;
   return m;
 }
 
-// Polarization at one voxel: tau = (c~ - c0) : e, from the voxel's
-// fraction f and normal-sphere id k.
-template <typename T>
-__device__ __forceinline__ void voxel_tau(const SolveArgs& a, const VoxelMaterial<T>& M, SolverState* st, T f,
-                                          int k, int x, int y, int z, const T e[6], T tau[6]) {
-  Coef<T> c;
-  c.aniso = false;
-  c.a3 = c.a4 = c.a5 = T(0);
-  if (f == T(0)) {
-    c.a1 = M.pure1[0];
-    c.a2 = M.pure2[0];
-  } else if (f == T(1)) {
-    c.a1 = M.pure1[1];
-    c.a2 = M.pure2[1];
+// Eight table entries as two (FP32) or four (FP64) 16-byte loads; rows are
+// 32 or 64 bytes, so every load is aligned.
+template <typename T> __device__ __forceinline__ void load_row8(const T* r, T v[8]) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 u0 = reinterpret_cast<const float4*>(r)[0];
+    const float4 u1 = reinterpret_cast<const float4*>(r)[1];
+    v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
+    v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w;
   } else {
-    int rule = M.rule;
-    if (rule == RULE_NONE) {
-      atomicOr(&st->flags, FLAG_NONE_FRACTIONAL);
-      rule = RULE_VOIGT;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double2 u = reinterpret_cast<const double2*>(r)[i];
+      v[2 * i] = u.x;
+      v[2 * i + 1] = u.y;
     }
-    rule_coefficients<T>(rule, f, M.pl, M.pm, c);
-    if (c.aniso) {
-      if (k >= M.nsph) atomicOr(&st->flags, FLAG_BAD_INCL);
-      if (k >= 0 && k < M.nsph) {
-        interface_normal<T>(M.sph, k, x, y, z, a.nx, a.ny, a.nz, a.dim, c.n);
-      } else {
-        c.n[0] = T(1);
-        c.n[1] = T(0);
-        c.n[2] = T(0);
-      }
-    }
-    c.a1 -= M.rl;
-    c.a2 -= M.rm2;
   }
+}
+
+// Polarization at one voxel: tau = (c~ - c0) : e for the voxel's material
+// id mv (a pure phase, or a row of the stiffness table).
+template <typename T>
+__device__ __forceinline__ void voxel_tau(const VoxelMaterial<T>& M, int mv, const T e[6], T tau[6]) {
+  T r[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+  bool aniso = false;
+  if (mv < 0) {
+    r[0] = mv == -1 ? M.pure1[0] : M.pure1[1];
+    r[1] = mv == -1 ? M.pure2[0] : M.pure2[1];
+  } else {
+    load_row8<T>(M.coef + (size_t)mv * 8, r);
+    aniso = M.aniso;
+  }
+  const Coef<T> c = {r[0], r[1], r[2], r[3], r[4], {r[5], r[6], r[7]}, aniso};
   apply_form<T>(c, e, tau);
 }
 
@@ -179,10 +235,8 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
       }
     }
   }
-  T fv[RV][KX];
-  int iv[RV][KX];
+  int mv[RV][KX];
   if (MODE != MODE_EXPORT) {
-    const T* frac = static_cast<const T*>(P.frac);
 #pragma unroll
     for (int i = 0; i < RV; ++i) {
       const int l = wv + NW * i;
@@ -191,13 +245,7 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
 #pragma unroll
       for (int m = 0; m < KX; ++m) {
         const int x = lane + 64 * m;
-        fv[i][m] = T(0);
-        iv[i][m] = -1;
-        if (rok && x < NX) {
-          const size_t v = (size_t)line * NX + x;
-          fv[i][m] = frac[v];
-          if (P.incl) iv[i][m] = P.incl[v];
-        }
+        mv[i][m] = (rok && x < NX) ? MAT.mid[(size_t)line * NX + x] : -1;
       }
     }
   }
@@ -248,7 +296,6 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
     const int l = wv + NW * i;
     if (l >= L) continue;
     const int line = line0 + l;
-    const int y = line % a.ny, z = line / a.ny;
 #pragma unroll
     for (int m = 0; m < KX; ++m) {
       const int x = lane + 64 * m;
@@ -267,7 +314,7 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
       }
       T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
       if (line < nlines) {
-        voxel_tau<T>(a, MAT, st, fv[i][m], iv[i][m], x, y, z, e, tau);
+        voxel_tau<T>(MAT, mv[i][m], e, tau);
 #pragma unroll
         for (int c = 0; c < 6; ++c) acc[c] += (double)tau[c];
       }
@@ -417,13 +464,21 @@ __device__ __forceinline__ cx<T> strain_component(int c, const Slot<T>& z, cx<T>
   return cx<T>{m * ((ni * ajx + nj * aix) * inv2mu - g * na.x), m * ((ni * ajy + nj * aiy) * inv2mu - g * na.y)};
 }
 
-template <typename T, int NZ, int W, int NT, int CG>
+// D is the prefetch depth: while one component group is transformed, the
+// global reads of the next D - 1 groups are in flight (a ring of register
+// buffers, so the forward loop is unrolled).  With single-component groups
+// the ring slots that run past the sixth component fetch the traction
+// history, which is then in flight during the last transforms.
+template <typename T, int NZ, int W, int NT, int CG, int D>
 __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
   static_assert(6 % CG == 0, "component groups must divide 6");
+  static_assert(D >= 1 && D <= 3, "prefetch depth 1..3");
+  constexpr int NG = 6 / CG;      // component groups
   constexpr int SL = W * NZ;
   constexpr int Q = (SL + NT - 1) / NT;
   constexpr int LW = CG * W;      // lines per transform: CG components x W columns
   constexpr int LD = LW | 1;      // odd row stride
+  constexpr int HR = CG == 1 ? (D < 3 ? D : 3) : 0;  // history components fetched through the ring
   __shared__ cx<T> buf[NZ * LD];
   __shared__ cx<T> s_tw[NZ];
   __shared__ double red[NT / 64];
@@ -462,26 +517,43 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
     z[q].n2 = T(x2 * rinv);
     z[q].a0 = z[q].a1 = z[q].a2 = cx<T>{T(0), T(0)};
   }
-  cx<T> nxt[CG][Q];
+  // ring[r] holds group r, r + D, ...; then (CG == 1) history components
+  cx<T> ring[D][CG][Q];
+  const bool hist_live = !a.first;
 #pragma unroll
-  for (int g = 0; g < CG; ++g)
-#pragma unroll
-    for (int q = 0; q < Q; ++q) nxt[g][q] = ok[q] ? sp[(size_t)g * plane + off[q]] : cx<T>{T(0), T(0)};
-  load_twiddles<T, NZ, NT>(s_tw, static_cast<const cx<T>*>(a.twz), tid);
-
-#pragma unroll 1
-  for (int c0 = 0; c0 < 6; c0 += CG) {
+  for (int r = 0; r < D; ++r)
 #pragma unroll
     for (int g = 0; g < CG; ++g)
 #pragma unroll
       for (int q = 0; q < Q; ++q)
-        if (tid + q * NT < SL) buf[lds[q] + g * W] = nxt[g][q];
-    if (c0 + CG < 6) {
+        ring[r][g][q] = (r < NG && ok[q]) ? sp[(size_t)(r * CG + g) * plane + off[q]] : cx<T>{T(0), T(0)};
+  load_twiddles<T, NZ, NT>(s_tw, static_cast<const cx<T>*>(a.twz), tid);
+
+  // depth 1: a rolled loop over the groups; deeper rings: fully unrolled,
+  // so that ring slots are fixed registers
+  constexpr int UN = D == 1 ? 1 : NG;
+#pragma unroll 1
+  for (int gb = 0; gb < NG; gb += UN) {
+#pragma unroll
+   for (int u = 0; u < UN; ++u) {
+    const int gi = gb + u;
+    const int r = gi % D;
+#pragma unroll
+    for (int g = 0; g < CG; ++g)
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        if (tid + q * NT < SL) buf[lds[q] + g * W] = ring[r][g][q];
+    const int nx = gi + D;
+    if (nx < NG) {
 #pragma unroll
       for (int g = 0; g < CG; ++g)
 #pragma unroll
         for (int q = 0; q < Q; ++q)
-          nxt[g][q] = ok[q] ? sp[(size_t)(c0 + CG + g) * plane + off[q]] : cx<T>{T(0), T(0)};
+          ring[r][g][q] = ok[q] ? sp[(size_t)(nx * CG + g) * plane + off[q]] : cx<T>{T(0), T(0)};
+    } else if (CG == 1 && nx - NG < HR) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        ring[r][0][q] = (ok[q] && hist_live) ? hp[(size_t)(nx - NG) * plane + off[q]] : cx<T>{T(0), T(0)};
     }
     __syncthreads();
     fft_lines<T, NZ, LW, NT, -1, LD, 9>(buf, s_tw, tid);
@@ -489,8 +561,9 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
     for (int g = 0; g < CG; ++g)
 #pragma unroll
       for (int q = 0; q < Q; ++q)
-        if (tid + q * NT < SL) fold_component<T>(c0 + g, buf[lds[q] + g * W], z[q]);
+        if (tid + q * NT < SL) fold_component<T>(gi * CG + g, buf[lds[q] + g * W], z[q]);
     __syncthreads();
+   }
   }
 
   // equilibrium error partial and traction history
@@ -507,15 +580,17 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
       h0[0] = h0[plane] = h0[2 * plane] = cx<T>{T(0), T(0)};
       continue;
     }
-    cx<T> p0 = {T(0), T(0)}, p1 = {T(0), T(0)}, p2 = {T(0), T(0)};
-    if (!a.first) {
-      p0 = h0[0];
-      p1 = h0[plane];
-      p2 = h0[2 * plane];
+    cx<T> pv[3];
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+      if (h < HR)
+        pv[h] = ring[(NG + h) % D][0][q];  // fetched in the forward loop
+      else
+        pv[h] = hist_live ? h0[(size_t)h * plane] : cx<T>{T(0), T(0)};
     }
-    const double d0x = (double)z[q].a0.x - (double)p0.x, d0y = (double)z[q].a0.y - (double)p0.y;
-    const double d1x = (double)z[q].a1.x - (double)p1.x, d1y = (double)z[q].a1.y - (double)p1.y;
-    const double d2x = (double)z[q].a2.x - (double)p2.x, d2y = (double)z[q].a2.y - (double)p2.y;
+    const double d0x = (double)z[q].a0.x - (double)pv[0].x, d0y = (double)z[q].a0.y - (double)pv[0].y;
+    const double d1x = (double)z[q].a1.x - (double)pv[1].x, d1y = (double)z[q].a1.y - (double)pv[1].y;
+    const double d2x = (double)z[q].a2.x - (double)pv[2].x, d2y = (double)z[q].a2.y - (double)pv[2].y;
     h0[0] = z[q].a0;
     h0[plane] = z[q].a1;
     h0[2 * plane] = z[q].a2;
@@ -614,21 +689,13 @@ __global__ __launch_bounds__(64 * NW) void k_xsweep_wave(SolveArgs a) {
       }
     }
   }
-  T fv[QV];
-  int iv[QV];
+  int mv[QV];
   if (MODE != MODE_EXPORT) {
-    const T* frac = static_cast<const T*>(P.frac);
 #pragma unroll
     for (int q = 0; q < QV; ++q) {
       const int idx = lane + 64 * q;
       const int l = idx / NX, x = idx - l * NX, line = line0 + l;
-      fv[q] = T(0);
-      iv[q] = -1;
-      if (idx < NV && line < nlines) {
-        const size_t v = (size_t)line * NX + x;
-        fv[q] = frac[v];
-        if (P.incl) iv[q] = P.incl[v];
-      }
+      mv[q] = (idx < NV && line < nlines) ? MAT.mid[(size_t)line * NX + x] : -1;
     }
   }
   load_twiddles<T, NX, NT>(s_tw, static_cast<const cx<T>*>(a.twx), tid);
@@ -689,8 +756,7 @@ __global__ __launch_bounds__(64 * NW) void k_xsweep_wave(SolveArgs a) {
     }
     T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     if (line < nlines) {
-      const int y = line % a.ny, z = line / a.ny;
-      voxel_tau<T>(a, MAT, st, fv[q], iv[q], x, y, z, e, tau);
+      voxel_tau<T>(MAT, mv[q], e, tau);
 #pragma unroll
       for (int c = 0; c < 6; ++c) acc[c] += (double)tau[c];
     }
@@ -956,7 +1022,6 @@ __global__ __launch_bounds__(NT) void k_reset_state(SolverState* st, int n_load)
   z.done = 0;
   z.status = ST_RUNNING;
   z.iters = 0;
-  z.flags = 0;
   z.iref = 0;
   z.pad0 = z.pad1 = 0;
   z.err = z.err0 = z.ref = 0.0;
@@ -970,18 +1035,38 @@ using solve_launch_fn = hipError_t (*)(const SolveArgs&, hipStream_t);
 // Candidate schedules of one axis length, timed by the plan's autotuner.
 struct XKern {
   solve_launch_fn first, iter, exp;
-  int lines;  // (y, z) lines per block
+  int lines;         // (y, z) lines per block
+  const char* name;  // iteration-mode instance, name<template arguments>
 };
 struct YKern {
   solve_launch_fn fwd, inv;
   int width;  // kx columns per block
+  const char* fwd_name;
+  const char* inv_name;
 };
 struct ZKern {
   solve_launch_fn run;
   int width;    // kx columns per block
   int threads;  // block size
   int groups;   // components per LDS transform (-1: one wavefront per component)
+  const char* name;
 };
+
+template <typename T> constexpr const char* type_name() { return sizeof(T) == 8 ? "double" : "float"; }
+
+// Instance names in the form profilers print them (spaces dropped), built
+// once per instantiation.
+template <int TAG, typename T, int... A> const char* instance_name(const char* base) {
+  static char buf[64];
+  static const int once = [&] {
+    int o = snprintf(buf, sizeof buf, "%s<%s", base, type_name<T>());
+    for (int v : {A...}) o += snprintf(buf + o, sizeof buf - (size_t)o, ",%d", v);
+    snprintf(buf + o, sizeof buf - (size_t)o, ">");
+    return 0;
+  }();
+  (void)once;
+  return buf;
+}
 constexpr int kMaxVariants = 6;
 struct AxisKernels {
   int n;
@@ -1014,8 +1099,10 @@ template <typename T, int N, int V> struct YTile {
 // frequency slots (2 in FP64, 4 in FP32; half that when radix-7 butterflies
 // are in play) under a 128-register cap.
 // Variant 2 transforms CG = 3 (or 2) components per LDS pass at width
-// 128 B when that fits in 56 KB of LDS.
-// Variant 2 holds one frequency slot per thread (so needs W N <= 1024).
+// 128 B when that fits in 56 KB of LDS; it holds one frequency slot per
+// thread (so needs W N <= 1024).
+// Prefetch depth D: 1, except variant 3 (single precision only), which is
+// variant 0 with depth 2.
 template <typename T, int N, int V> struct ZTile {
   static constexpr int W0 = 128 / (int)sizeof(cx<T>);
   static constexpr int W1 = 256 / (int)sizeof(cx<T>);
@@ -1026,6 +1113,7 @@ template <typename T, int N, int V> struct ZTile {
   static constexpr int CG =
       (V == 2 && W * N <= 1024) ? (lds3 <= 56 * 1024 ? 3 : (lds2 <= 56 * 1024 ? 2 : 1)) : 1;
   static constexpr int NT = clamp_int(round64((W * N + QT - 1) / QT), 64, 1024);
+  static constexpr int D = V == 3 ? 2 : 1;
 };
 
 template <typename T, int NX, int MODE, int V>
@@ -1058,20 +1146,24 @@ hipError_t launch_z_wave(const SolveArgs& a, hipStream_t s) {
 template <typename T, int NZ, int V>
 hipError_t launch_z(const SolveArgs& a, hipStream_t s) {
   using TL = ZTile<T, NZ, V>;
-  hipLaunchKernelGGL((k_zsweep<T, NZ, TL::W, TL::NT, TL::CG>), dim3(a.ntx4, a.ny, a.n_load), dim3(TL::NT), 0, s,
-                     a);
+  hipLaunchKernelGGL((k_zsweep<T, NZ, TL::W, TL::NT, TL::CG, TL::D>), dim3(a.ntx4, a.ny, a.n_load), dim3(TL::NT),
+                     0, s, a);
   return hipGetLastError();
 }
 
 template <typename T, int N, int V> XKern make_x() {
-  return XKern{&launch_x<T, N, MODE_FIRST, V>, &launch_x<T, N, MODE_ITER, V>, &launch_x<T, N, MODE_EXPORT, V>,
-               XTile<T, N, V>::L};
+  using TL = XTile<T, N, V>;
+  return XKern{&launch_x<T, N, MODE_FIRST, V>, &launch_x<T, N, MODE_ITER, V>, &launch_x<T, N, MODE_EXPORT, V>, TL::L,
+               instance_name<0, T, N, TL::L, TL::NT, MODE_ITER, TL::RMAX>("xsweep")};
 }
 template <typename T, int N, int V> YKern make_y() {
-  return YKern{&launch_y<T, N, -1, V>, &launch_y<T, N, +1, V>, YTile<T, N, V>::W};
+  using TL = YTile<T, N, V>;
+  return YKern{&launch_y<T, N, -1, V>, &launch_y<T, N, +1, V>, TL::W,
+               instance_name<1, T, N, TL::W, TL::NT, -1>("ysweep"), instance_name<1, T, N, TL::W, TL::NT, 1>("ysweep")};
 }
 template <typename T, int N, int V> ZKern make_z() {
-  return ZKern{&launch_z<T, N, V>, ZTile<T, N, V>::W, ZTile<T, N, V>::NT, ZTile<T, N, V>::CG};
+  using TL = ZTile<T, N, V>;
+  return ZKern{&launch_z<T, N, V>, TL::W, TL::NT, TL::CG, instance_name<2, T, N, TL::W, TL::NT, TL::CG, TL::D>("zsweep")};
 }
 
 template <typename T, int N>
@@ -1090,21 +1182,24 @@ AxisKernels make_axis_kernels() {
   k.z[0] = make_z<T, N, 0>();
   k.z[1] = make_z<T, N, 1>();
   k.nzv = 2;
-  if (ZTile<T, N, 2>::CG > 1) k.z[k.nzv++] = make_z<T, N, 2>();
+  if constexpr (ZTile<T, N, 2>::CG > 1) k.z[k.nzv++] = make_z<T, N, 2>();
+  if constexpr (sizeof(T) == 4) k.z[k.nzv++] = make_z<T, N, 3>();
   // wavefront x-sweeps: (2 lines per wave, 2 waves) and (1 line per wave, 4 waves)
   if constexpr (2 * N * ((6 | 1)) * (int)sizeof(cx<T>) <= 56 * 1024) {
     k.x[k.nxv++] = XKern{&launch_x_wave<T, N, MODE_FIRST, 2, 2>, &launch_x_wave<T, N, MODE_ITER, 2, 2>,
-                         &launch_x_wave<T, N, MODE_EXPORT, 2, 2>, 4};
+                         &launch_x_wave<T, N, MODE_EXPORT, 2, 2>, 4,
+                         instance_name<3, T, N, 2, 2, MODE_ITER>("xsweep_wave")};
   }
   if constexpr (4 * N * 3 * (int)sizeof(cx<T>) <= 56 * 1024) {
     k.x[k.nxv++] = XKern{&launch_x_wave<T, N, MODE_FIRST, 1, 4>, &launch_x_wave<T, N, MODE_ITER, 1, 4>,
-                         &launch_x_wave<T, N, MODE_EXPORT, 1, 4>, 4};
+                         &launch_x_wave<T, N, MODE_EXPORT, 1, 4>, 4,
+                         instance_name<3, T, N, 1, 4, MODE_ITER>("xsweep_wave")};
   }
   // wavefront z-sweep on 64-byte tiles when its six regions fit in 64 KB
   {
     constexpr int W = 64 / (int)sizeof(cx<T>);
     if constexpr (6 * N * (W | 1) * (int)sizeof(cx<T>) <= 64 * 1024)
-      k.z[k.nzv++] = ZKern{&launch_z_wave<T, N, W>, W, 384, -1};
+      k.z[k.nzv++] = ZKern{&launch_z_wave<T, N, W>, W, 384, -1, instance_name<4, T, N, W>("zsweep_wave")};
   }
   return k;
 }

@@ -13,7 +13,7 @@ import torch
 
 from gpu_helpers import log, oracle_fields_to_comps, oracle_solve, rel
 from oracle import filter as ofilter, gradient as ogradient, solver as osolver
-from workloads import lame, rsa_spheres, small_sphere_case, workload_c1
+from workloads import lame, random_fraction_case, rsa_spheres, small_sphere_case, workload_c1
 
 pytestmark = pytest.mark.gpu
 
@@ -100,6 +100,32 @@ def test_solve_fixed_iterations_3d_anisotropic_grid(hm):
         assert rel(out["sig_mean"][l], sig_ref) < 1e-10
         assert abs(out["reports"][l]["err"] - r["err"]) <= 1e-10 * r["err"] + 1e-13
         assert rel(out["eps"][l].cpu().numpy(), oracle_fields_to_comps(r["eps"])) < 1e-10
+
+
+@pytest.mark.parametrize("rule", ["reuss", "laminate"])
+def test_mostly_fractional_field_grows_the_stiffness_table(hm, rule):
+    # Half of the 45^3 voxels fractional: more rows than the stiffness table
+    # of a fresh plan holds, so it grows and is rebuilt; then a sphere cell
+    # with few fractional voxels reuses the grown table on the same plan.
+    n = (45, 45, 45)
+    w = small_sphere_case(n=n, fraction=0.2, contrast=8.0, rule=rule, radius_vox=1.0, subsamples=4)
+    f = random_fraction_case(23, n).reshape(-1)
+    incl = np.where((f > 0) & (f < 1), 0, -1).astype(np.int32)
+    E = np.array([[0.01, -0.004, 0.002, 0.001, -0.003, 0.005], [0.0, 0.0, 0.0, 0.0, 0.0, 0.01]])
+    hm.release_plans()
+    log("stiffness table growth %s: %d fractional voxels" % (rule, int(np.sum(incl == 0))))
+    cases = [(f, incl)]
+    _, f2, i2, _, _ = _gpu_filter(hm, w)
+    cases.append((f2, i2))
+    for fr, ic in cases:
+        out = hm.hm_solve(w.n, w.dim, w.phases, rule, torch.tensor(fr, device=DEV), torch.tensor(ic, device=DEV),
+                          w.spheres, E, prec="fp64", tol=0.0, max_iter=3, want_eps=True)
+        refs = oracle_solve(w, fr, ic, E, 0.0, 3)
+        for l, r in enumerate(refs):
+            sig_ref = np.array([r["sig_mean"][i, j] for (i, j) in [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]])
+            assert rel(out["sig_mean"][l], sig_ref) < 1e-10
+            assert abs(out["reports"][l]["err"] - r["err"]) <= 1e-10 * r["err"] + 1e-13
+            assert rel(out["eps"][l].cpu().numpy(), oracle_fields_to_comps(r["eps"])) < 1e-10
 
 
 def test_effective_tensor_converged_fp64(hm):
@@ -206,6 +232,10 @@ def test_profiled_solve_matches_and_reports_timing(hm):
     t = hm.last_timing()
     assert t["iterations"] == max(r["iters"] for r in b["reports"]) + 1
     assert all(v > 0 for v in t["ms"].values())
+    # instance names as profilers print them: sweep<double,21,...>
+    for k in ("xsweep", "ysweep_fwd", "zsweep", "ysweep_inv"):
+        assert t["kernels"][k].startswith(k.split("_")[0]) and "<double,21," in t["kernels"][k]
+    assert t["kernels"]["ysweep_fwd"].endswith(",-1>") and t["kernels"]["ysweep_inv"].endswith(",1>")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
