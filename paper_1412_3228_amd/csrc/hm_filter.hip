@@ -14,7 +14,13 @@
 // exact integer.  One thread per voxel: spheres that cannot reach the filter
 // ball are skipped and a sphere that contains the whole ball gives the full
 // count without enumeration (both decisions are conservative by one lattice
-// unit); remaining voxels enumerate the stencil against the candidates.
+// unit).  Remaining voxels count, row by row of the stencil (fixed odd oy,
+// oz), the odd ox inside both the filter ball and some candidate sphere: each
+// is an integer interval (integer square roots), so a row costs a few
+// operations instead of one test per point.  That needs the minimum image of
+// every stencil point to be the voxel's own image shifted by the offset
+// (the ball does not straddle half a period from the sphere); otherwise, or
+// with more candidates than the list holds, the points are tested one by one.
 #include <math.h>
 #include <stdint.h>
 
@@ -31,6 +37,21 @@ __device__ __forceinline__ long long min_image(long long d, long long P) {
 }
 
 constexpr int kMaxCand = 8;
+
+// floor(sqrt(q)) for 0 <= q < 2^53, exact.
+__device__ __forceinline__ long long isqrt(long long q) {
+  long long r = (long long)sqrt((double)q);
+  while (r * r > q) --r;
+  while ((r + 1) * (r + 1) <= q) ++r;
+  return r;
+}
+
+// Number of odd integers in [lo, hi].
+__device__ __forceinline__ long long odd_count(long long lo, long long hi) {
+  if (hi < lo) return 0;
+  auto fdiv2 = [](long long v) { return v >= 0 ? v / 2 : -((1 - v) / 2); };
+  return fdiv2(hi - 1) - fdiv2(lo) + 1;
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_filter(FilterArgs a) {
@@ -76,8 +97,73 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a) {
           overflow = true;
       }
     }
+    // per-candidate minimum-image offset of the voxel centre; the row method
+    // needs every stencil point's image to follow from it (no wrap)
+    long long d0[kMaxCand][3] = {};
+    long long rint[kMaxCand] = {};
+    bool rows_ok = !overflow;
+    if (!full && rows_ok) {
+      for (int q = 0; q < nc; ++q) {
+        const int k = cand[q];
+        for (int ax = 0; ax < 3; ++ax) {
+          const long long h = a.P[ax] / 2;
+          const long long d = ax < axes ? min_image(X[ax] - a.sph[k].c[ax], a.P[ax]) : 0;
+          d0[q][ax] = d;
+          if (ax < axes && (d - a.m < -h || d + a.m >= h)) rows_ok = false;
+        }
+        rint[q] = (long long)floor(a.sph[k].R2);
+      }
+    }
     if (full) {
       cnt = (uint32_t)a.M;
+    } else if (nc > 0 && rows_ok) {
+      const long long rho_i = (long long)floor(a.rho2);
+      const int zlo = axes == 3 ? -a.m : 0;
+      const int zhi = axes == 3 ? a.m : 0;
+      long long total = 0;
+      for (int oz = zlo; oz <= zhi; ++oz) {
+        if (axes == 3 && (oz & 1) == 0) continue;
+        for (int oy = -a.m; oy <= a.m; ++oy) {
+          if ((oy & 1) == 0) continue;
+          const long long rest = rho_i - (long long)oy * oy - (long long)oz * oz;
+          if (rest < 1) continue;
+          const long long al = isqrt(rest);  // |ox| <= al inside the filter ball
+          long long lo[kMaxCand], hi[kMaxCand];
+          int ni = 0;
+          for (int q = 0; q < nc; ++q) {
+            const long long dy = d0[q][1] + oy, dz = d0[q][2] + oz;
+            const long long Q = rint[q] - dy * dy - dz * dz;
+            if (Q < 0) continue;
+            const long long b = isqrt(Q);  // |d0x + ox| <= b inside sphere q
+            const long long l = max(-al, -b - d0[q][0]), u = min(al, b - d0[q][0]);
+            if (l > u) continue;
+            // insert sorted by lower end
+            int j = ni++;
+            while (j > 0 && lo[j - 1] > l) {
+              lo[j] = lo[j - 1];
+              hi[j] = hi[j - 1];
+              --j;
+            }
+            lo[j] = l;
+            hi[j] = u;
+          }
+          // odd integers in the union of the sorted intervals
+          long long cl = 0, ch = -1;
+          bool open = false;
+          for (int j = 0; j < ni; ++j) {
+            if (open && lo[j] <= ch + 1) {
+              ch = max(ch, hi[j]);
+            } else {
+              if (open) total += odd_count(cl, ch);
+              cl = lo[j];
+              ch = hi[j];
+              open = true;
+            }
+          }
+          if (open) total += odd_count(cl, ch);
+        }
+      }
+      cnt = (uint32_t)total;
     } else if (nc > 0) {
       const int zlo = axes == 3 ? -a.m : 0;
       const int zhi = axes == 3 ? a.m : 0;

@@ -42,7 +42,8 @@ def _multi_sphere_case(n=45, k=6, seed=11, rule="laminate", radius=1.0, S=8):
     return w.with_(spheres=sph, name="multi-%d" % n)
 
 
-@pytest.mark.parametrize("case", ["3d-r1-S4", "3d-r0.55-S8-shift", "2d-c1-r1-S16", "2d-c1-none", "multi-45"])
+@pytest.mark.parametrize("case", ["3d-r1-S4", "3d-r0.55-S8-shift", "2d-c1-r1-S16", "2d-c1-none", "multi-45",
+                                  "3d-wide-sphere", "3d-crowded"])
 def test_filter_bit_exact(hm, case):
     log("filter case %s" % case)
     if case == "3d-r1-S4":
@@ -54,6 +55,17 @@ def test_filter_bit_exact(hm, case):
         w = workload_c1("laminate")
     elif case == "2d-c1-none":
         w = workload_c1("none")
+    elif case == "3d-wide-sphere":
+        # the filter ball of surface voxels straddles half a period from the
+        # centre: stencil points take other periodic images
+        w = small_sphere_case(n=(9, 15, 9), radius_vox=1.0, subsamples=4, offset=(0.2, -0.1, 0.3))
+        w = w.with_(spheres=np.array([[4.7, 7.4, 4.8, 4.3]]))
+    elif case == "3d-crowded":
+        # more spheres near a voxel than the candidate list holds
+        rng = np.random.Generator(np.random.PCG64(5))
+        c = 3.0 + rng.random((14, 3)) * 3.0
+        sph = np.concatenate([c, 0.45 + 0.3 * rng.random((14, 1))], axis=1)
+        w = small_sphere_case(n=(9, 9, 9), radius_vox=2.5, subsamples=4).with_(spheres=sph)
     else:
         w = _multi_sphere_case()
     cnt, frac, incl, _, _ = _gpu_filter(hm, w)
