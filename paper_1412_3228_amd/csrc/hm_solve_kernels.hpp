@@ -469,7 +469,7 @@ __device__ __forceinline__ cx<T> strain_component(int c, const Slot<T>& z, cx<T>
 // buffers, so the forward loop is unrolled).  With single-component groups
 // the ring slots that run past the sixth component fetch the traction
 // history, which is then in flight during the last transforms.
-template <typename T, int NZ, int W, int NT, int CG, int D>
+template <typename T, int NZ, int W, int NT, int CG, int D, int PAD>
 __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
   static_assert(6 % CG == 0, "component groups must divide 6");
   static_assert(D >= 1 && D <= 3, "prefetch depth 1..3");
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
   constexpr int SL = W * NZ;
   constexpr int Q = (SL + NT - 1) / NT;
   constexpr int LW = CG * W;      // lines per transform: CG components x W columns
-  constexpr int LD = LW | 1;      // odd row stride
+  constexpr int LD = PAD ? (LW | 1) : LW;  // row stride: odd, or exactly the tile row
   constexpr int HR = CG == 1 ? (D < 3 ? D : 3) : 0;  // history components fetched through the ring
   __shared__ cx<T> buf[NZ * LD];
   __shared__ cx<T> s_tw[NZ];
@@ -1067,7 +1067,7 @@ template <int TAG, typename T, int... A> const char* instance_name(const char* b
   (void)once;
   return buf;
 }
-constexpr int kMaxVariants = 6;
+constexpr int kMaxVariants = 8;
 struct AxisKernels {
   int n;
   int nxv, nyv, nzv;
@@ -1102,7 +1102,8 @@ template <typename T, int N, int V> struct YTile {
 // 128 B when that fits in 56 KB of LDS; it holds one frequency slot per
 // thread (so needs W N <= 1024).
 // Prefetch depth D: 1, except variant 3 (single precision only), which is
-// variant 0 with depth 2.
+// variant 0 with depth 2.  LDS rows are padded to an odd stride, except in
+// variants 4 and 5 (variants 0 and 3 with rows of exactly W values).
 template <typename T, int N, int V> struct ZTile {
   static constexpr int W0 = 128 / (int)sizeof(cx<T>);
   static constexpr int W1 = 256 / (int)sizeof(cx<T>);
@@ -1113,7 +1114,8 @@ template <typename T, int N, int V> struct ZTile {
   static constexpr int CG =
       (V == 2 && W * N <= 1024) ? (lds3 <= 56 * 1024 ? 3 : (lds2 <= 56 * 1024 ? 2 : 1)) : 1;
   static constexpr int NT = clamp_int(round64((W * N + QT - 1) / QT), 64, 1024);
-  static constexpr int D = V == 3 ? 2 : 1;
+  static constexpr int D = (V == 3 || V == 5) ? 2 : 1;
+  static constexpr int PAD = V >= 4 ? 0 : 1;
 };
 
 template <typename T, int NX, int MODE, int V>
@@ -1146,8 +1148,8 @@ hipError_t launch_z_wave(const SolveArgs& a, hipStream_t s) {
 template <typename T, int NZ, int V>
 hipError_t launch_z(const SolveArgs& a, hipStream_t s) {
   using TL = ZTile<T, NZ, V>;
-  hipLaunchKernelGGL((k_zsweep<T, NZ, TL::W, TL::NT, TL::CG, TL::D>), dim3(a.ntx4, a.ny, a.n_load), dim3(TL::NT),
-                     0, s, a);
+  hipLaunchKernelGGL((k_zsweep<T, NZ, TL::W, TL::NT, TL::CG, TL::D, TL::PAD>), dim3(a.ntx4, a.ny, a.n_load),
+                     dim3(TL::NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1163,7 +1165,7 @@ template <typename T, int N, int V> YKern make_y() {
 }
 template <typename T, int N, int V> ZKern make_z() {
   using TL = ZTile<T, N, V>;
-  return ZKern{&launch_z<T, N, V>, TL::W, TL::NT, TL::CG, instance_name<2, T, N, TL::W, TL::NT, TL::CG, TL::D>("zsweep")};
+  return ZKern{&launch_z<T, N, V>, TL::W, TL::NT, TL::CG, instance_name<2, T, N, TL::W, TL::NT, TL::CG, TL::D, TL::PAD>("zsweep")};
 }
 
 template <typename T, int N>
@@ -1184,6 +1186,8 @@ AxisKernels make_axis_kernels() {
   k.nzv = 2;
   if constexpr (ZTile<T, N, 2>::CG > 1) k.z[k.nzv++] = make_z<T, N, 2>();
   if constexpr (sizeof(T) == 4) k.z[k.nzv++] = make_z<T, N, 3>();
+  k.z[k.nzv++] = make_z<T, N, 4>();
+  if constexpr (sizeof(T) == 4) k.z[k.nzv++] = make_z<T, N, 5>();
   // wavefront x-sweeps: (2 lines per wave, 2 waves) and (1 line per wave, 4 waves)
   if constexpr (2 * N * ((6 | 1)) * (int)sizeof(cx<T>) <= 56 * 1024) {
     k.x[k.nxv++] = XKern{&launch_x_wave<T, N, MODE_FIRST, 2, 2>, &launch_x_wave<T, N, MODE_ITER, 2, 2>,
