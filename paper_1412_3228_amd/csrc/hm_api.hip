@@ -573,6 +573,13 @@ int upload_params(Group& g, const std::vector<ProblemIn>& all, const hm_solve_op
     q.rl = opts->c0_alpha * 0.5 * (lmin + lmax);
     q.rm = opts->c0_alpha * 0.5 * (mmin + mmax);
     if (!(q.rm > 0.0) || !(q.rl + 2.0 * q.rm > 0.0)) return fail(HM_E_ARG, "reference medium is not positive");
+    for (int ph = 0; ph < 2; ++ph) {
+      // the rounding of T(lambda) - T(lambda0) and T(2 mu) - T(2 mu0) in T
+      q.pure_f[2 * ph] = (float)q.pl[ph] - (float)q.rl;
+      q.pure_f[2 * ph + 1] = (float)(2.0 * q.pm[ph]) - (float)(2.0 * q.rm);
+      q.pure_d[2 * ph] = q.pl[ph] - q.rl;
+      q.pure_d[2 * ph + 1] = 2.0 * q.pm[ph] - 2.0 * q.rm;
+    }
     q.rule = (int)d.rule;
     q.nsph = d.nsph;
     q.frac = d.frac;

@@ -57,6 +57,11 @@ struct ProblemParams {
   // holds the voxel's filtered stiffness.
   const int* mid;
   const void* coef;
+  // c~ - c0 of the two pure phases as (a1 - lambda0, a2 - 2 mu0) pairs,
+  // matrix then inclusion, rounded the way the working precision computes
+  // them: in single precision from single-precision inputs, or in double
+  float pure_f[4];
+  double pure_d[4];
 };
 
 // One load case: its macroscopic strain (tensor components) and problem.

@@ -125,8 +125,7 @@ __global__ __launch_bounds__(256) void k_material(const SolveParams* prm, int pr
 // values read through the parameter pointer would otherwise be re-read for
 // every voxel).
 template <typename T> struct VoxelMaterial {
-  T pure1[2];  // lambda_phase - lambda0
-  T pure2[2];  // 2 mu_phase - 2 mu0
+  T pure[4];  // (a1 - lambda0, a2 - 2 mu0) of the matrix, then the inclusion
   const T* coef;
   const int* mid;
   bool aniso;  // the rule's table rows use the normal
@@ -134,11 +133,12 @@ template <typename T> struct VoxelMaterial {
 
 template <typename T> __device__ __forceinline__ VoxelMaterial<T> load_material(const ProblemParams& P) {
   VoxelMaterial<T> m;
-  const T rl = T(P.rl), rm2 = T(2.0 * P.rm);
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    m.pure1[i] = T(P.pl[i]) - rl;
-    m.pure2[i] = T(2.0 * P.pm[i]) - rm2;
+  for (int i = 0; i < 4; ++i) {
+    if constexpr (sizeof(T) == 4)
+      m.pure[i] = P.pure_f[i];
+    else
+      m.pure[i] = P.pure_d[i];
   }
   m.coef = static_cast<const T*>(P.coef);
   m.mid = P.mid;
@@ -146,37 +146,45 @@ template <typename T> __device__ __forceinline__ VoxelMaterial<T> load_material(
   return m;
 }
 
+// Load through a pointer known to address device global memory (pointers
+// read from the parameter blob are generic to the compiler, which would
+// otherwise issue flat loads that also wait on the LDS counter).
+template <typename V> __device__ __forceinline__ V load_global(const V* p) {
+  return *(const __attribute__((address_space(1))) V*)(p);
+}
+
 // Eight table entries as two (FP32) or four (FP64) 16-byte loads; rows are
 // 32 or 64 bytes, so every load is aligned.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 template <typename T> __device__ __forceinline__ void load_row8(const T* r, T v[8]) {
   if constexpr (sizeof(T) == 4) {
-    const float4 u0 = reinterpret_cast<const float4*>(r)[0];
-    const float4 u1 = reinterpret_cast<const float4*>(r)[1];
+    const v4f u0 = load_global(reinterpret_cast<const v4f*>(r));
+    const v4f u1 = load_global(reinterpret_cast<const v4f*>(r) + 1);
     v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
     v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w;
   } else {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const double2 u = reinterpret_cast<const double2*>(r)[i];
+      const v2d u = load_global(reinterpret_cast<const v2d*>(r) + i);
       v[2 * i] = u.x;
       v[2 * i + 1] = u.y;
     }
   }
 }
 
-// Polarization at one voxel: tau = (c~ - c0) : e for the voxel's material
-// id mv (a pure phase, or a row of the stiffness table).
-template <typename T>
-__device__ __forceinline__ void voxel_tau(const VoxelMaterial<T>& M, int mv, const T e[6], T tau[6]) {
-  T r[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
-  bool aniso = false;
-  if (mv < 0) {
-    r[0] = mv == -1 ? M.pure1[0] : M.pure1[1];
-    r[1] = mv == -1 ? M.pure2[0] : M.pure2[1];
-  } else {
-    load_row8<T>(M.coef + (size_t)mv * 8, r);
-    aniso = M.aniso;
-  }
+// Stiffness row (a1 - lambda0, a2 - 2 mu0, a3, a4, a5, n) of the voxel with
+// material id mv: a pure phase, or a row of the table (one global gather).
+template <typename T> __device__ __forceinline__ void material_row(const VoxelMaterial<T>& M, int mv, T r[8]) {
+  r[0] = mv == -1 ? M.pure[0] : M.pure[2];
+  r[1] = mv == -1 ? M.pure[1] : M.pure[3];
+#pragma unroll
+  for (int i = 2; i < 8; ++i) r[i] = T(0);
+  if (mv >= 0) load_row8<T>(M.coef + (size_t)mv * 8, r);
+}
+
+// Polarization tau = (c~ - c0) : e from a stiffness row.
+template <typename T> __device__ __forceinline__ void row_tau(bool aniso, const T r[8], const T e[6], T tau[6]) {
   const Coef<T> c = {r[0], r[1], r[2], r[3], r[4], {r[5], r[6], r[7]}, aniso};
   apply_form<T>(c, e, tau);
 }
@@ -245,7 +253,7 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
 #pragma unroll
       for (int m = 0; m < KX; ++m) {
         const int x = lane + 64 * m;
-        mv[i][m] = (rok && x < NX) ? MAT.mid[(size_t)line * NX + x] : -1;
+        mv[i][m] = (rok && x < NX) ? load_global(MAT.mid + (size_t)line * NX + x) : -1;
       }
     }
   }
@@ -290,7 +298,13 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
     return;
   }
 
-  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // all table gathers of the thread's voxels first, then the polarizations
+  T rows[RV][KX][8];
+#pragma unroll
+  for (int i = 0; i < RV; ++i)
+#pragma unroll
+    for (int m = 0; m < KX; ++m) material_row<T>(MAT, mv[i][m], rows[i][m]);
+  T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};  // thread partials, then FP64 block sums
 #pragma unroll
   for (int i = 0; i < RV; ++i) {
     const int l = wv + NW * i;
@@ -314,9 +328,9 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
       }
       T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
       if (line < nlines) {
-        voxel_tau<T>(MAT, mv[i][m], e, tau);
+        row_tau<T>(MAT.aniso && mv[i][m] >= 0, rows[i][m], e, tau);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) acc[c] += (double)tau[c];
+        for (int c = 0; c < 6; ++c) acc[c] += tau[c];
       }
 #pragma unroll
       for (int p = 0; p < 3; ++p) buf[x * LD + p * L + l] = cx<T>{tau[2 * p], tau[2 * p + 1]};
@@ -695,7 +709,7 @@ __global__ __launch_bounds__(64 * NW) void k_xsweep_wave(SolveArgs a) {
     for (int q = 0; q < QV; ++q) {
       const int idx = lane + 64 * q;
       const int l = idx / NX, x = idx - l * NX, line = line0 + l;
-      mv[q] = (idx < NV && line < nlines) ? MAT.mid[(size_t)line * NX + x] : -1;
+      mv[q] = (idx < NV && line < nlines) ? load_global(MAT.mid + (size_t)line * NX + x) : -1;
     }
   }
   load_twiddles<T, NX, NT>(s_tw, static_cast<const cx<T>*>(a.twx), tid);
@@ -736,7 +750,10 @@ __global__ __launch_bounds__(64 * NW) void k_xsweep_wave(SolveArgs a) {
     return;
   }
 
-  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  T rows[QV][8];
+#pragma unroll
+  for (int q = 0; q < QV; ++q) material_row<T>(MAT, mv[q], rows[q]);
+  T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int q = 0; q < QV; ++q) {
     const int idx = lane + 64 * q;
@@ -756,9 +773,9 @@ __global__ __launch_bounds__(64 * NW) void k_xsweep_wave(SolveArgs a) {
     }
     T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     if (line < nlines) {
-      voxel_tau<T>(MAT, mv[q], e, tau);
+      row_tau<T>(MAT.aniso && mv[q] >= 0, rows[q], e, tau);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) acc[c] += (double)tau[c];
+      for (int c = 0; c < 6; ++c) acc[c] += tau[c];
     }
 #pragma unroll
     for (int p = 0; p < 3; ++p) buf[x * LD + p * LW + l] = cx<T>{tau[2 * p], tau[2 * p + 1]};
