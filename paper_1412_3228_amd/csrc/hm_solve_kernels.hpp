@@ -523,12 +523,22 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
     off[q] = (unsigned)(kz * zs + w);
     lds[q] = (unsigned)(kz * LD + w);
     const int az = kz <= (NZ - 1) / 2 ? kz : kz - NZ;
-    const double x0 = twopi * kx, x1 = twopi * ay, x2 = twopi * az;
-    const double q2 = x0 * x0 + x1 * x1 + x2 * x2;
-    const double rinv = q2 > 0.0 ? 1.0 / sqrt(q2) : 0.0;
-    z[q].n0 = T(x0 * rinv);
-    z[q].n1 = T(x1 * rinv);
-    z[q].n2 = T(x2 * rinv);
+    if constexpr (sizeof(T) == 4) {
+      // n = k / |k| from the integer wave vector (the 2 pi cancels); one
+      // hardware reciprocal square root, well inside single precision
+      const int k2 = kx * kx + ay * ay + az * az;
+      const float rinv = k2 > 0 ? rsqrtf((float)k2) : 0.0f;
+      z[q].n0 = (float)kx * rinv;
+      z[q].n1 = (float)ay * rinv;
+      z[q].n2 = (float)az * rinv;
+    } else {
+      const double x0 = twopi * kx, x1 = twopi * ay, x2 = twopi * az;
+      const double q2 = x0 * x0 + x1 * x1 + x2 * x2;
+      const double rinv = q2 > 0.0 ? 1.0 / sqrt(q2) : 0.0;
+      z[q].n0 = T(x0 * rinv);
+      z[q].n1 = T(x1 * rinv);
+      z[q].n2 = T(x2 * rinv);
+    }
     z[q].a0 = z[q].a1 = z[q].a2 = cx<T>{T(0), T(0)};
   }
   // ring[r] holds group r, r + D, ...; then (CG == 1) history components
@@ -602,15 +612,25 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
       else
         pv[h] = hist_live ? h0[(size_t)h * plane] : cx<T>{T(0), T(0)};
     }
-    const double d0x = (double)z[q].a0.x - (double)pv[0].x, d0y = (double)z[q].a0.y - (double)pv[0].y;
-    const double d1x = (double)z[q].a1.x - (double)pv[1].x, d1y = (double)z[q].a1.y - (double)pv[1].y;
-    const double d2x = (double)z[q].a2.x - (double)pv[2].x, d2y = (double)z[q].a2.y - (double)pv[2].y;
     h0[0] = z[q].a0;
     h0[plane] = z[q].a1;
     h0[2 * plane] = z[q].a2;
     const double x0 = twopi * kx, x1 = twopi * ay, x2 = twopi * az;
-    S += (kx == 0 ? 1.0 : 2.0) * (x0 * x0 + x1 * x1 + x2 * x2) *
-         (d0x * d0x + d0y * d0y + d1x * d1x + d1y * d1y + d2x * d2x + d2y * d2y);
+    double dd;
+    if constexpr (sizeof(T) == 4) {
+      // single-precision differences of single-precision values, squared and
+      // summed in single precision; the weighted total stays in FP64
+      const float d0x = z[q].a0.x - pv[0].x, d0y = z[q].a0.y - pv[0].y;
+      const float d1x = z[q].a1.x - pv[1].x, d1y = z[q].a1.y - pv[1].y;
+      const float d2x = z[q].a2.x - pv[2].x, d2y = z[q].a2.y - pv[2].y;
+      dd = (double)(d0x * d0x + d0y * d0y + d1x * d1x + d1y * d1y + d2x * d2x + d2y * d2y);
+    } else {
+      const double d0x = z[q].a0.x - pv[0].x, d0y = z[q].a0.y - pv[0].y;
+      const double d1x = z[q].a1.x - pv[1].x, d1y = z[q].a1.y - pv[1].y;
+      const double d2x = z[q].a2.x - pv[2].x, d2y = z[q].a2.y - pv[2].y;
+      dd = d0x * d0x + d0y * d0y + d1x * d1x + d1y * d1y + d2x * d2x + d2y * d2y;
+    }
+    S += (kx == 0 ? 1.0 : 2.0) * (x0 * x0 + x1 * x1 + x2 * x2) * dd;
   }
 
   // eps^_kh = -[(n_k a_h + n_h a_k) / (2 mu0) - cc (n.a) n_k n_h] / N, eps^(0) = E
@@ -623,8 +643,13 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
   for (int q = 0; q < Q; ++q)
     na[q] = cx<T>{z[q].a0.x * z[q].n0 + z[q].a1.x * z[q].n1 + z[q].a2.x * z[q].n2,
                   z[q].a0.y * z[q].n0 + z[q].a1.y * z[q].n1 + z[q].a2.y * z[q].n2};
+  // inverse transforms: rolled with depth 1, unrolled with deeper rings (the
+  // component index is then a constant in the Gamma0^ contraction)
 #pragma unroll 1
-  for (int c0 = 0; c0 < 6; c0 += CG) {
+  for (int cb = 0; cb < 6; cb += CG * UN) {
+#pragma unroll
+   for (int u = 0; u < UN; ++u) {
+    const int c0 = cb + u * CG;
 #pragma unroll
     for (int g = 0; g < CG; ++g) {
       const T Ec = T(LP.E[c0 + g]);
@@ -644,6 +669,7 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
       for (int q = 0; q < Q; ++q)
         if (tid + q * NT < SL && ok[q]) sp[(size_t)(c0 + g) * plane + off[q]] = buf[lds[q] + g * W];
     __syncthreads();
+   }
   }
   const double tot = block_sum<NT>(S, red);
   if (tid == 0) a.errpart[(size_t)load * ((size_t)ny * a.ntx4) + (size_t)ky * a.ntx4 + tile] = tot;
