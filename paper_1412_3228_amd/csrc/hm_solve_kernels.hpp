@@ -978,45 +978,76 @@ __device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
   s = t;
 }
 
-// Compensated, deterministic sum of v[i * stride] for i < n over the block.
-template <int NT>
-__device__ double block_compensated_sum(const double* v, size_t n, size_t stride, double* ss, double* sc) {
-  const int tid = threadIdx.x;
-  double s = 0.0, c = 0.0;
-  for (size_t i = tid; i < n; i += NT) neumaier_add(s, c, v[i * stride]);
-  ss[tid] = s;
-  sc[tid] = c;
-  __syncthreads();
-  for (int h = NT / 2; h > 0; h >>= 1) {
-    if (tid < h) {
-      double s1 = ss[tid], c1 = sc[tid];
-      neumaier_add(s1, c1, ss[tid + h]);
-      ss[tid] = s1;
-      sc[tid] = c1 + sc[tid + h];
-    }
-    __syncthreads();
-  }
-  const double out = ss[0] + sc[0];
-  __syncthreads();
-  return out;
+// Neumaier combination of two compensated partial sums (s, c) += (s2, c2).
+__device__ __forceinline__ void neumaier_merge(double& s, double& c, double s2, double c2) {
+  neumaier_add(s, c, s2);
+  c += c2;
 }
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_finalize(SolveArgs a) {
-  __shared__ double ss[NT], sc[NT];
+  constexpr int NW = NT / 64;
+  constexpr int K = 7;  // six tau component sums and the error sum
+  __shared__ double ws[NW][K], wc[NW][K];
   const int load = blockIdx.x;
   SolverState* st = a.state + load;
-  if (st->done) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // The block is alone on its compute unit, so its time is a chain of
+  // memory latencies: the first partials, the stop flag and the parameter
+  // chain are all requested before any of them is used.
+  const double* tp = a.taupart + (size_t)load * a.g2 * 6;
+  const size_t ne = (size_t)a.ny * a.ntx4;
+  const double* ep = a.errpart + (size_t)load * ne;
+  double t0[6], e0 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) t0[k] = tid < a.g2 ? tp[(size_t)tid * 6 + k] : 0.0;
+  if ((size_t)tid < ne) e0 = ep[tid];
+  const int done = st->done;
   const SolveParams& S0 = *a.prm;
   const LoadParams& LP = S0.loads[load];
   const ProblemParams& P = S0.probs[LP.prob];
-  double tsum[6];
+  if (done) return;
+  // one pass over the partials: thread-strided compensated sums, then a
+  // fixed shuffle tree per wavefront and the wavefronts in order (the
+  // result does not depend on timing)
+  double s[K], c[K];
 #pragma unroll
-  for (int c = 0; c < 6; ++c)
-    tsum[c] = block_compensated_sum<NT>(a.taupart + (size_t)load * a.g2 * 6 + c, (size_t)a.g2, 6, ss, sc);
-  const size_t ne = (size_t)a.ny * a.ntx4;
-  const double S = block_compensated_sum<NT>(a.errpart + (size_t)load * ne, ne, 1, ss, sc);
-  if (threadIdx.x != 0) return;
+  for (int k = 0; k < 6; ++k) {
+    s[k] = t0[k];
+    c[k] = 0.0;
+  }
+  s[6] = e0;
+  c[6] = 0.0;
+  for (int i = tid + NT; i < a.g2; i += NT)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) neumaier_add(s[k], c[k], tp[(size_t)i * 6 + k]);
+  for (size_t i = (size_t)tid + NT; i < ne; i += NT) neumaier_add(s[6], c[6], ep[i]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double so = __shfl_down(s[k], off, 64), co = __shfl_down(c[k], off, 64);
+      if (lane < off) neumaier_merge(s[k], c[k], so, co);
+    }
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      ws[wv][k] = s[k];
+      wc[wv][k] = c[k];
+    }
+  __syncthreads();
+  if (tid != 0) return;
+  double tsum[6], S;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double sk = ws[0][k], ck = wc[0][k];
+    for (int w = 1; w < NW; ++w) neumaier_merge(sk, ck, ws[w][k], wc[w][k]);
+    if (k < 6)
+      tsum[k] = sk + ck;
+    else
+      S = sk + ck;
+  }
   const double N = (double)a.nx * (double)a.ny * (double)a.nz;
   const double* E = LP.E;
   const double trE = E[0] + E[1] + E[2];
