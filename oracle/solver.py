@@ -182,9 +182,12 @@ def solve(field: StiffnessField, E, c0, tol: float, max_iter: int,
           stall_window: int = 0, eps0=None, dft=None):
     """Basic fixed-point scheme for one macroscopic strain E (3x3 or 6 components).
 
-    Iterate i computes sigma_i = c~ : eps_i and its error e_i; it stops when
-    e_i < tol (converged), when e_i is not finite or exceeds 1e3 e_0
-    (diverged), when with stall_window > 0 the error has not dropped by 1%
+    Iterate i computes sigma_i = c~ : eps_i and its error e_i = r_i / |<sigma_i>|
+    with the equilibrium residual r_i = sqrt(sum_xi |xi . sigma^_i|^2); it
+    stops when e_i < tol (converged), when e_i is not finite or r_i exceeds
+    1e3 r_0 (diverged: the residual, not e_i, because the mean stress of an
+    iterate can pass close to zero at high contrast and make e_i spike while
+    the iteration converges), when with stall_window > 0 the error has not dropped by 1%
     below its last reference value for stall_window iterations (stalled),
     or when i == max_iter (not converged).  Otherwise
     tau_i = sigma_i - c0 : eps_i, eps^_{i+1} = -Gamma0^ : tau^_i (xi != 0),
@@ -209,7 +212,7 @@ def solve(field: StiffnessField, E, c0, tol: float, max_iter: int,
     else:
         eps = np.array(eps0, dtype=np.float64)
     errs = []
-    e0 = None
+    r0 = None
     ref, iref = None, 0
     i = 0
     while True:
@@ -220,12 +223,12 @@ def solve(field: StiffnessField, E, c0, tol: float, max_iter: int,
         den = float(np.sqrt(np.sum(np.abs(sh[0, 0, 0]) ** 2)))
         e = num / den if den > 0 else (0.0 if num == 0.0 else math.inf)
         errs.append(e)
-        if e0 is None:
-            e0 = e
+        if r0 is None:
+            r0 = num
         status = None
         if e < tol:
             status = STATUS_CONVERGED
-        elif not math.isfinite(e) or (e0 > 0 and e > DIVERGENCE_FACTOR * e0):
+        elif not math.isfinite(e) or (r0 > 0 and num > DIVERGENCE_FACTOR * r0):
             status = STATUS_DIVERGED
         else:
             if ref is None or e < STALL_DECREASE * ref:
