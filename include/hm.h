@@ -61,7 +61,8 @@ extern "C" {
 #define HM_OK 0
 #define HM_NOT_CONVERGED 1 /* max_iter reached before e < tol          */
 #define HM_STALLED 2       /* error stopped decreasing (stall window)  */
-#define HM_DIVERGED 3      /* error not finite or above 1e3 * e_0      */
+#define HM_DIVERGED 3      /* error not finite, or equilibrium residual
+                              above 1e3 times that of iterate 0        */
 #define HM_E_ARG (-1)      /* invalid argument                          */
 #define HM_E_SIZE (-2)     /* unsupported grid size                     */
 #define HM_E_NOMEM (-3)    /* device allocation failed                  */

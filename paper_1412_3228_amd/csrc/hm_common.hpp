@@ -38,6 +38,7 @@ struct SolverState {
   int pad0, pad1;
   double err;   // error of the last evaluated (or reported) iterate
   double err0;  // error of iterate 0
+  double res0;  // equilibrium residual sqrt(sum |xi . sigma^|^2) of iterate 0
   double ref;   // error at iref
   double sig[6];  // <sigma> of the last evaluated (or reported) iterate
 };

@@ -1057,14 +1057,21 @@ __global__ __launch_bounds__(NT) void k_finalize(SolveArgs a) {
   const double fro = sqrt(sig[0] * sig[0] + sig[1] * sig[1] + sig[2] * sig[2] +
                           2.0 * (sig[3] * sig[3] + sig[4] * sig[4] + sig[5] * sig[5]));
   const double den = N * fro;
-  const double e = den > 0.0 ? sqrt(S) / den : (S == 0.0 ? 0.0 : INFINITY);
+  const double res = sqrt(S);
+  const double e = den > 0.0 ? res / den : (S == 0.0 ? 0.0 : INFINITY);
   const int i = st->iter;
   if (i < a.hist_cap) a.errhist[(size_t)load * a.hist_cap + i] = e;
-  if (i == 0) st->err0 = e;
+  if (i == 0) {
+    st->err0 = e;
+    st->res0 = res;
+  }
+  // divergence is judged on the residual: the mean stress in the
+  // denominator of e can pass near zero while the iteration converges
+  const double r0 = i == 0 ? res : st->res0;
   int status = ST_RUNNING;
   if (e < S0.tol) {
     status = ST_CONVERGED;
-  } else if (!isfinite(e) || (st->err0 > 0.0 && e > kDivergenceFactor * st->err0)) {
+  } else if (!isfinite(e) || (r0 > 0.0 && res > kDivergenceFactor * r0)) {
     status = ST_DIVERGED;
   } else {
     if (i == 0 || e < kStallDecrease * st->ref) {
@@ -1098,7 +1105,7 @@ __global__ __launch_bounds__(NT) void k_reset_state(SolverState* st, int n_load)
   z.iters = 0;
   z.iref = 0;
   z.pad0 = z.pad1 = 0;
-  z.err = z.err0 = z.ref = 0.0;
+  z.err = z.err0 = z.res0 = z.ref = 0.0;
   for (int c = 0; c < 6; ++c) z.sig[c] = 0.0;
   st[l] = z;
 }

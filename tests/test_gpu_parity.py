@@ -13,7 +13,7 @@ import torch
 
 from gpu_helpers import log, oracle_fields_to_comps, oracle_solve, rel
 from oracle import filter as ofilter, gradient as ogradient, solver as osolver
-from workloads import lame, random_fraction_case, rsa_spheres, small_sphere_case, workload_c1
+from workloads import fig1_disk_case, lame, random_fraction_case, rsa_spheres, small_sphere_case, workload_c1
 
 pytestmark = pytest.mark.gpu
 
@@ -210,6 +210,24 @@ def test_status_codes(hm):
     with pytest.raises(HmError) as ei:
         hm.hm_solve(w.n, w.dim, w.phases, "none", frac, incl, w.spheres, E, tol=1e-6, max_iter=5)
     assert ei.value.code == -5
+
+
+def test_high_contrast_mean_stress_swing_is_not_divergence(hm):
+    # contrast 1e3, shear load: e_i spikes far above e_0 while the residual
+    # falls; GPU and oracle both run to convergence in the same iterations
+    w = fig1_disk_case(7, 1e3, "none")
+    log("mean stress swing")
+    _, _, _, frac, incl = _gpu_filter(hm, w)
+    ref_f = ofilter.filter_field(w)
+    E = np.array([[0.0, 0.0, 0.0, 0.0, 0.0, 0.01]])
+    out = hm.hm_solve(w.n, w.dim, w.phases, "none", frac, incl, w.spheres, E, prec="fp64", tol=1e-4,
+                      max_iter=5000, check_every=1)
+    r = oracle_solve(w, ref_f["frac"], ref_f["incl"], E, 1e-4, 5000)[0]
+    assert r["status"] == 0 and max(r["errs"]) > 1e3 * r["errs"][0]
+    assert out["reports"][0]["status"] == 0
+    assert out["reports"][0]["iters"] == r["iters"]
+    sig_ref = np.array([r["sig_mean"][i, j] for (i, j) in [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]])
+    assert rel(out["sig_mean"][0], sig_ref) < 1e-10
 
 
 def test_adjoint_matches_oracle_gradient(hm):

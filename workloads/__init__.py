@@ -19,4 +19,7 @@ from .microstructures import (  # noqa: F401
     small_sphere_case,
     target_perturbation,
     random_fraction_case,
+    fig1_disk_case,
+    FIG1_RESOLUTIONS,
+    FIG1_DISK_RADIUS,
 )

@@ -319,3 +319,33 @@ def random_fraction_case(seed: int, n=(9, 7, 5)) -> np.ndarray:
     f[u < 0.25] = 0.0
     f[u > 0.75] = 1.0
     return f
+
+
+# Resolutions of the resolution study: the odd sizes with prime factors 3,
+# 5 and 7 between 7 and 125 (the paper sweeps every size from 6 to 128).
+FIG1_RESOLUTIONS = (7, 9, 15, 21, 25, 27, 35, 45, 49, 63, 75, 81, 105, 125)
+FIG1_DISK_RADIUS = math.pi / 15.0  # cell lengths (Section 2 numerical setup)
+
+
+def fig1_disk_case(n: int, contrast: float, rule: str = "none", radius_vox: float = 0.55,
+                   subsamples: int = 16) -> Workload:
+    """The 2D cell of the resolution study: a disk of radius pi/15 centred in
+    the unit square, n x n pixels, E_inclusion / E_matrix = contrast with
+    nu = 0.3 in both phases, loaded by a uniaxial mean strain of 1 %."""
+    r = FIG1_DISK_RADIUS * n
+    sph = np.array([[n / 2.0, n / 2.0, 0.5, r]])
+    loads = np.zeros((1, 6))
+    loads[0, 0] = 0.01
+    return Workload(
+        name="fig1-%d-c%g-%s-r%g" % (n, contrast, rule, radius_vox),
+        dim=2,
+        n=(n, n, 1),
+        spheres=sph,
+        phases=(lame(1.0, 0.3), lame(contrast, 0.3)),
+        radius_vox=radius_vox,
+        subsamples=subsamples,
+        rule=rule,
+        loads=loads,
+        tol=1e-4,
+        meta={"contrast": contrast},
+    )
