@@ -250,6 +250,78 @@ def solve(field: StiffnessField, E, c0, tol: float, max_iter: int,
         i += 1
 
 
+def project_compatible(t: np.ndarray, xi: np.ndarray) -> np.ndarray:
+    """G t: orthogonal projection (sum over voxels of u : v) of a real
+    symmetric tensor field onto compatible strain fields of zero mean.  It
+    is Gamma0 of the reference medium lambda0 = 0, mu0 = 1/2 (c0 = identity
+    on symmetric tensors), applied at every nonzero frequency (eq. 2)."""
+    th = np.fft.fftn(t, axes=(0, 1, 2))
+    return np.real(np.fft.ifftn(-_apply_gamma(th, xi, 0.0, 0.5), axes=(0, 1, 2)))
+
+
+def field_dot(u: np.ndarray, v: np.ndarray) -> float:
+    """sum over voxels of u : v for (nz, ny, nx, 3, 3) fields."""
+    return float(np.sum(u * v))
+
+
+def solve_cg(field: StiffnessField, E, tol: float, max_iter: int, keep_residuals: bool = False):
+    """Conjugate gradients on the same Lippmann-Schwinger operator (the Krylov
+    alternative named in Section 5).
+
+    With c0 = identity, the strain eps = E + x whose stress is in
+    equilibrium satisfies G(c~ : x) = -G(c~ : E) with x compatible and of
+    zero mean, where G is project_compatible; G c~ G is symmetric positive
+    definite for sum_v u : v on that space, so plain CG applies:
+    x_0 = 0, r_0 = p_0 = -G(c~ : E); q = G(c~ : p), alpha = (r.r)/(p.q),
+    x += alpha p, r -= alpha q, beta = (r.r)_new/(r.r), p = r + beta p.
+    Iterate k (k operator applications after the start) has the error
+    e_k = sqrt(<r_k : r_k>) / |<sigma_k>| (r = -G sigma_k, the compatible part
+    of the stress, vanishes at equilibrium; <.> voxel mean, Frobenius norm);
+    the solve stops when e_k < tol or k == max_iter.
+
+    Returns dict(iters=k, err=e_k, status, sig_mean=<sigma_k> (3x3),
+    errs=[e_0..e_k], eps=E + x_k) and, with keep_residuals, the r_k fields.
+    """
+    E = np.asarray(E, dtype=np.float64)
+    if E.shape != (3, 3):
+        E = strain_tensor(E)
+    nx, ny, nz = field.n
+    N = nx * ny * nz
+    xi = frequency_grid(field.n)
+    Eb = np.broadcast_to(E, (nz, ny, nx, 3, 3))
+    x = np.zeros((nz, ny, nx, 3, 3))
+    r = -project_compatible(field.apply(Eb), xi)
+    p = r.copy()
+    rr = field_dot(r, r)
+    errs, rs = [], []
+    k = 0
+    while True:
+        if keep_residuals:
+            rs.append(r.copy())
+        sig_mean = np.mean(field.apply(Eb + x).reshape(-1, 3, 3), axis=0)
+        fro = float(np.sqrt(np.sum(sig_mean * sig_mean)))
+        e = math.sqrt(rr / N) / fro if fro > 0 else (0.0 if rr == 0.0 else math.inf)
+        errs.append(e)
+        status = None
+        if e < tol:
+            status = STATUS_CONVERGED
+        elif k >= max_iter:
+            status = STATUS_NOT_CONVERGED
+        if status is not None:
+            out = {"iters": k, "err": e, "status": status, "sig_mean": sig_mean, "errs": errs, "eps": Eb + x}
+            if keep_residuals:
+                out["residuals"] = rs
+            return out
+        q = project_compatible(field.apply(p), xi)
+        alpha = rr / field_dot(p, q)
+        x = x + alpha * p
+        r = r - alpha * q
+        rr_new = field_dot(r, r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        k += 1
+
+
 def unit_mandel_strains(dim: int):
     """Unit Mandel strains as 3x3 tensors: 6 in 3D, the 3 in-plane ones (11, 22, 12) in 2D."""
     s = 1.0 / math.sqrt(2.0)
