@@ -96,6 +96,8 @@ typedef struct {
   double r;
 } hm_sphere;
 
+typedef enum { HM_FIXED_POINT = 0, HM_CONJUGATE_GRADIENT = 1 } hm_method;
+
 typedef struct {
   hm_prec prec;     /* HM_FP64 or HM_MIXED                                   */
   double tol;       /* stop when the equilibrium error e_i < tol (0: never)   */
@@ -111,6 +113,14 @@ typedef struct {
   int schedule;     /* with autotune == 0: -1 for the first compiled schedule,
                        else xv | yv << 4 | zv << 8 selecting the variants
                        counted by hm_schedule_count (for tests)             */
+  int method;       /* HM_FIXED_POINT (the basic scheme of Section 2) or
+                       HM_CONJUGATE_GRADIENT (Krylov alternative named in
+                       Section 5: CG on the same operator with c0 = identity;
+                       c0_alpha, stall_window and profile do not apply; the
+                       error is sqrt(<r:r>)/|<sigma>| of the residual r =
+                       -G(c~:eps), G the projection on compatible fields; the
+                       returned strain is the reported iterate itself).  Not
+                       available in hm_effective_tensor_batch.               */
 } hm_solve_opts;
 
 /* Average device duration per launch of each kernel of the iteration, over

@@ -18,6 +18,7 @@ HM_E_DATA = -5
 
 RULES = {"none": 0, "voigt": 1, "reuss": 2, "laminate": 3}
 PRECS = {"fp64": 0, "mixed": 1}
+METHODS = {"fixed_point": 0, "cg": 1}
 
 # Every symbol include/hm.h declares.
 EXPORTS = ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_effective_tensor_batch", "hm_solve_adjoint",
@@ -41,7 +42,8 @@ class HmSolveOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("c0_alpha", ctypes.c_double), ("check_every", ctypes.c_int),
                 ("stall_window", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("profile", ctypes.c_int), ("autotune", ctypes.c_int), ("schedule", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("autotune", ctypes.c_int), ("schedule", ctypes.c_int),
+                ("method", ctypes.c_int)]
 
 
 class HmTiming(ctypes.Structure):

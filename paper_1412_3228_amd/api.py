@@ -65,7 +65,7 @@ def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
 
 
 def _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile=False,
-          autotune=True, schedule=None) -> L.HmSolveOpts:
+          autotune=True, schedule=None, method="fixed_point") -> L.HmSolveOpts:
     o = L.HmSolveOpts()
     o.prec = L.PRECS[prec]
     o.tol = float(tol)
@@ -77,6 +77,7 @@ def _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, p
     o.profile = 1 if profile else 0
     o.autotune = 1 if (autotune and schedule is None) else 0
     o.schedule = -1 if schedule is None else int(schedule[0]) | int(schedule[1]) << 4 | int(schedule[2]) << 8
+    o.method = L.METHODS[method]
     return o
 
 
@@ -111,8 +112,8 @@ def hm_filter(n, dim, spheres, radius_vox: float, subsamples: int, rule: str, pr
 def hm_solve(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres, E,
              prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
              check_every: int = 1, stall_window: int = 0, use_graph: bool = False, want_eps: bool = False,
-             profile: bool = False, autotune: bool = True):
-    """Fixed-point solve for the rows of E (n_load x 6 tensor components)."""
+             profile: bool = False, autotune: bool = True, method: str = "fixed_point"):
+    """Solve for the rows of E (n_load x 6 tensor components); method "fixed_point" or "cg"."""
     dev = frac.device
     N = int(n[0] * n[1] * n[2])
     _check_field(frac, N, _DT[prec], dev, "frac")
@@ -124,7 +125,7 @@ def hm_solve(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch
     eps = torch.empty((nl, 6, N), dtype=_DT[prec], device=dev) if want_eps else None
     g = _grid(n, dim)
     sph, ns = _spheres(spheres)
-    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, autotune)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, autotune, None, method)
     rc = _lib().hm_solve(ctypes.byref(g), _phases(phases), L.RULES[rule], _ptr(frac), _ptr(incl), sph, ns,
                          Ea.ctypes.data_as(L._dp), nl, ctypes.byref(o), _ptr(eps),
                          sig.ctypes.data_as(L._dp), rep, _stream(dev))
@@ -136,7 +137,7 @@ def hm_effective_tensor(n, dim, phases, rule: str, frac: torch.Tensor, incl: Opt
                         prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
                         check_every: int = 1, stall_window: int = 0, use_graph: bool = False,
                         want_eps: bool = False, profile: bool = False, autotune: bool = True,
-                        schedule=None):
+                        schedule=None, method: str = "fixed_point"):
     """Effective Mandel tensor from the unit-strain solves (6 in 3D, 3 in 2D)."""
     dev = frac.device
     N = int(n[0] * n[1] * n[2])
@@ -148,7 +149,8 @@ def hm_effective_tensor(n, dim, phases, rule: str, frac: torch.Tensor, incl: Opt
     eps = torch.empty((k, 6, N), dtype=_DT[prec], device=dev) if want_eps else None
     g = _grid(n, dim)
     sph, ns = _spheres(spheres)
-    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, autotune, schedule)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, autotune, schedule,
+              method)
     rc = _lib().hm_effective_tensor(ctypes.byref(g), _phases(phases), L.RULES[rule], _ptr(frac), _ptr(incl),
                                     sph, ns, ctypes.byref(o), C.ctypes.data_as(L._dp), _ptr(eps), rep,
                                     _stream(dev))

@@ -139,6 +139,9 @@ int check_opts(const hm_solve_opts* o) {
   if (!(o->c0_alpha > 0.0) || !isfinite(o->c0_alpha)) return fail(HM_E_ARG, "c0_alpha must be > 0");
   if (o->check_every < 1) return fail(HM_E_ARG, "check_every must be >= 1");
   if (o->stall_window < 0) return fail(HM_E_ARG, "stall_window must be >= 0");
+  if (o->method != HM_FIXED_POINT && o->method != HM_CONJUGATE_GRADIENT) return fail(HM_E_ARG, "unknown method");
+  if (o->method == HM_CONJUGATE_GRADIENT && o->profile)
+    return fail(HM_E_ARG, "profiling times the fixed-point iteration only");
   return HM_OK;
 }
 
@@ -186,6 +189,12 @@ struct Plan {
   size_t coef_cap = 0;       // rows
   int* mcount = nullptr;     // [2]: rows handed out, data flags
   int* mcount_host = nullptr;
+  void* cgv[3] = {nullptr, nullptr, nullptr};  // CG iterate x, residual r, direction p
+  CgState* cgs = nullptr;
+  double* cgpart = nullptr;
+  int cg_blocks = 0;
+  hipGraphExec_t cg_graph = nullptr;
+  int cg_graph_k = 0;
   void* tw[3] = {nullptr, nullptr, nullptr};
   SolveArgs args;
   hipStream_t cap_stream = nullptr;
@@ -198,6 +207,10 @@ std::map<std::tuple<int, bool, int, int, int, int>, Plan*> g_plans;
 
 void free_plan(Plan* p) {
   if (p->graph) (void)hipGraphExecDestroy(p->graph);
+  if (p->cg_graph) (void)hipGraphExecDestroy(p->cg_graph);
+  for (int v = 0; v < 3; ++v) (void)hipFree(p->cgv[v]);
+  (void)hipFree(p->cgs);
+  (void)hipFree(p->cgpart);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   (void)hipFree(p->spec);
   (void)hipFree(p->hist);
@@ -214,6 +227,14 @@ void free_plan(Plan* p) {
   if (p->state_host) (void)hipHostFree(p->state_host);
   if (p->prm_host) (void)hipHostFree(p->prm_host);
   delete p;
+}
+
+// Captured graphs bake in the launch arguments: drop them when those change.
+void drop_graphs(Plan* p) {
+  if (p->graph) (void)hipGraphExecDestroy(p->graph);
+  if (p->cg_graph) (void)hipGraphExecDestroy(p->cg_graph);
+  p->graph = nullptr;
+  p->cg_graph = nullptr;
 }
 
 int device_alloc(void** ptr, size_t bytes, const char* what) {
@@ -292,6 +313,7 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, Plan** out) {
   SolveArgs& a = p->args;
   memset(&a, 0, sizeof a);
   a.spec = p->spec;
+  a.spec_in = p->spec;
   a.hist = p->hist;
   a.taupart = p->taupart;
   a.errpart = p->errpart;
@@ -320,10 +342,7 @@ void set_schedule(Plan* p, const XKern* X, const YKern* Y, const ZKern* Z) {
   a.g2 = (a.ny * a.nz + X->lines - 1) / X->lines;
   a.ntx3 = (a.H + Y->width - 1) / Y->width;
   a.ntx4 = (a.H + Z->width - 1) / Z->width;
-  if (p->graph) {
-    (void)hipGraphExecDestroy(p->graph);
-    p->graph = nullptr;
-  }
+  drop_graphs(p);
 }
 
 int ensure_hist(Plan* p, int cap) {
@@ -336,10 +355,7 @@ int ensure_hist(Plan* p, int cap) {
   p->hist_cap = cap;
   p->args.errhist = p->errhist;
   p->args.hist_cap = cap;
-  if (p->graph) {
-    (void)hipGraphExecDestroy(p->graph);
-    p->graph = nullptr;
-  }
+  drop_graphs(p);
   return HM_OK;
 }
 
@@ -526,10 +542,7 @@ int upload_params(Group& g, const std::vector<ProblemIn>& all, const hm_solve_op
     if (hipHostMalloc((void**)&p->prm_host, cap, 0) != hipSuccess) return fail(HM_E_NOMEM, "pinned parameters");
     p->prm_cap = cap;
     p->args.prm = reinterpret_cast<const SolveParams*>(p->prm);
-    if (p->graph) {
-      (void)hipGraphExecDestroy(p->graph);
-      p->graph = nullptr;
-    }
+    drop_graphs(p);
   }
   size_t nmid = 0;
   for (int q : g.probs) nmid += (size_t)all[q].grid.n[0] * all[q].grid.n[1] * all[q].grid.n[2];
@@ -572,6 +585,11 @@ int upload_params(Group& g, const std::vector<ProblemIn>& all, const hm_solve_op
     const double mmin = fmin(q.pm[0], q.pm[1]), mmax = fmax(q.pm[0], q.pm[1]);
     q.rl = opts->c0_alpha * 0.5 * (lmin + lmax);
     q.rm = opts->c0_alpha * 0.5 * (mmin + mmax);
+    if (opts->method == HM_CONJUGATE_GRADIENT) {
+      // c0 = identity on symmetric tensors: Gamma0 becomes the projection G
+      q.rl = 0.0;
+      q.rm = 0.5;
+    }
     if (!(q.rm > 0.0) || !(q.rl + 2.0 * q.rm > 0.0)) return fail(HM_E_ARG, "reference medium is not positive");
     for (int ph = 0; ph < 2; ++ph) {
       // the rounding of T(lambda) - T(lambda0) and T(2 mu) - T(2 mu0) in T
@@ -726,6 +744,161 @@ int profiled_loop(Plan* p, const hm_solve_opts* opts, hipStream_t s) {
   return HM_OK;
 }
 
+// ---------------------------------------------------- conjugate gradients
+// Vectors x, r, p, per-load scalars and block partials, allocated on a
+// plan's first CG solve.
+int ensure_cg(Plan* p) {
+  if (p->cgs) return HM_OK;
+  const size_t cplx = p->fp64 ? 16 : 8;
+  const size_t total = 6 * (size_t)p->n[2] * p->n[1] * p->args.Hp;
+  const int blocks = (int)std::min<size_t>(1024, (total + kCgThreads * 8 - 1) / (kCgThreads * 8));
+  void* v[3] = {nullptr, nullptr, nullptr};
+  double* part = nullptr;
+  CgState* cs = nullptr;
+  int rc = HM_OK;
+  for (int i = 0; i < 3 && !rc; ++i) rc = device_alloc(&v[i], (size_t)p->n_load * total * cplx, "CG vectors");
+  if (!rc) rc = device_alloc((void**)&part, (size_t)p->n_load * blocks * sizeof(double), "CG partials");
+  if (!rc) rc = device_alloc((void**)&cs, (size_t)p->n_load * sizeof(CgState), "CG state");
+  if (rc) {
+    for (int i = 0; i < 3; ++i) (void)hipFree(v[i]);
+    (void)hipFree(part);
+    return rc;
+  }
+  for (int i = 0; i < 3; ++i) p->cgv[i] = v[i];
+  p->cgpart = part;
+  p->cgs = cs;
+  p->cg_blocks = blocks;
+  SolveArgs& a = p->args;
+  a.cgx = v[0];
+  a.cgr = v[1];
+  a.cgp = v[2];
+  a.cgs = cs;
+  a.cgpart = part;
+  a.cg_blocks = blocks;
+  drop_graphs(p);
+  return HM_OK;
+}
+
+template <typename T> hipError_t cg_vec(int op, const SolveArgs& a, hipStream_t s) {
+  const dim3 grid(a.cg_blocks, a.n_load), block(kCgThreads);
+  switch (op) {
+    case CG_INIT:
+      hipLaunchKernelGGL((k_cg_vec<T, CG_INIT>), grid, block, 0, s, a);
+      break;
+    case CG_DOT:
+      hipLaunchKernelGGL((k_cg_vec<T, CG_DOT>), grid, block, 0, s, a);
+      break;
+    case CG_UPDATE:
+      hipLaunchKernelGGL((k_cg_vec<T, CG_UPDATE>), grid, block, 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_cg_vec<T, CG_DIR>), grid, block, 0, s, a);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t cg_vector(const Plan* p, int op, const SolveArgs& a, hipStream_t s) {
+  return p->fp64 ? cg_vec<double>(op, a, s) : cg_vec<float>(op, a, s);
+}
+
+hipError_t cg_scalar(int step, const SolveArgs& a, hipStream_t s) {
+  const dim3 grid(a.n_load), block(kFinalizeThreads);
+  if (step == CGS_INIT)
+    hipLaunchKernelGGL((k_cg_scalar<kFinalizeThreads, CGS_INIT>), grid, block, 0, s, a);
+  else if (step == CGS_ALPHA)
+    hipLaunchKernelGGL((k_cg_scalar<kFinalizeThreads, CGS_ALPHA>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_cg_scalar<kFinalizeThreads, CGS_BETA>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+// Iterate 0: the sweeps turn E into r_0 = -G((c~ - I) : E); x = 0, p = r_0.
+hipError_t launch_cg_start(Plan* p, hipStream_t s) {
+  SolveArgs a = p->args;
+  a.first = 1;
+  a.cg = 1;
+  hipError_t e;
+  if ((e = p->X->first(a, s)) != hipSuccess) return e;
+  if ((e = p->Y->fwd(a, s)) != hipSuccess) return e;
+  if ((e = p->Z->run(a, s)) != hipSuccess) return e;
+  if ((e = p->Y->inv(a, s)) != hipSuccess) return e;
+  if ((e = cg_vector(p, CG_INIT, a, s)) != hipSuccess) return e;
+  return cg_scalar(CGS_INIT, a, s);
+}
+
+// One CG iteration: w = sweeps(p), q = p - w, alpha, x and r, beta, p.
+hipError_t launch_cg_iteration(Plan* p, hipStream_t s) {
+  SolveArgs a = p->args;
+  a.first = 0;
+  a.cg = 1;
+  a.spec_in = p->cgv[2];
+  hipError_t e;
+  if ((e = p->X->iter(a, s)) != hipSuccess) return e;
+  if ((e = p->Y->fwd(a, s)) != hipSuccess) return e;
+  if ((e = p->Z->run(a, s)) != hipSuccess) return e;
+  if ((e = p->Y->inv(a, s)) != hipSuccess) return e;
+  if ((e = cg_vector(p, CG_DOT, a, s)) != hipSuccess) return e;
+  if ((e = cg_scalar(CGS_ALPHA, a, s)) != hipSuccess) return e;
+  if ((e = cg_vector(p, CG_UPDATE, a, s)) != hipSuccess) return e;
+  if ((e = cg_scalar(CGS_BETA, a, s)) != hipSuccess) return e;
+  return cg_vector(p, CG_DIR, a, s);
+}
+
+int build_cg_graph(Plan* p, int k) {
+  if (p->cg_graph && p->cg_graph_k == k) return HM_OK;
+  if (p->cg_graph) (void)hipGraphExecDestroy(p->cg_graph);
+  p->cg_graph = nullptr;
+  if (!p->cap_stream) HM_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  HM_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  for (int i = 0; i < k && le == hipSuccess; ++i) le = launch_cg_iteration(p, p->cap_stream);
+  hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
+  if (le != hipSuccess || ce != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(HM_E_DEVICE, "CG graph capture failed: %s", hipGetErrorString(le != hipSuccess ? le : ce));
+  }
+  hipError_t ie = hipGraphInstantiate(&p->cg_graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    p->cg_graph = nullptr;
+    return fail(HM_E_DEVICE, "CG graph instantiation failed: %s", hipGetErrorString(ie));
+  }
+  p->cg_graph_k = k;
+  return HM_OK;
+}
+
+// CG solve of one grid group to its stop; exports eps = E + x when asked.
+int run_cg(Group& g, const hm_solve_opts* opts, hipStream_t s) {
+  Plan* p = g.p;
+  int rc;
+  if ((rc = ensure_cg(p))) return rc;
+  HM_HIP(launch_cg_start(p, s));
+  bool done = false;
+  if ((rc = poll_done(p, s, &done))) return rc;
+  const int k = opts->check_every;
+  int it = 1;
+  while (!done && it <= opts->max_iter) {
+    if (opts->use_graph) {
+      if ((rc = build_cg_graph(p, k))) return rc;
+      HM_HIP(hipGraphLaunch(p->cg_graph, s));
+      it += k;
+    } else {
+      for (int b = 0; b < k && it <= opts->max_iter; ++b, ++it) HM_HIP(launch_cg_iteration(p, s));
+    }
+    if ((rc = poll_done(p, s, &done))) return rc;
+  }
+  if (g.eps_out) {
+    SolveArgs a = p->args;
+    a.cg = 1;
+    a.spec_in = p->cgv[0];
+    a.eps_out = g.eps_out;
+    HM_HIP(p->X->exp(a, s));
+  }
+  return poll_done(p, s, &done);
+}
+
 // Solves every group to its stop (or max_iter): iterate 0 directly, then
 // blocks of check_every iterations (one captured graph over all active
 // groups, or direct launches), polling the device-side stop flags between
@@ -752,6 +925,10 @@ int run_groups(std::vector<Group>& G, const std::vector<ProblemIn>& all, const h
                        g.p->n_load);
     HM_HIP(hipGetLastError());
     g.active = true;
+  }
+  if (opts->method == HM_CONJUGATE_GRADIENT) {
+    if (G.size() != 1) return fail(HM_E_ARG, "conjugate gradients solve one grid group");
+    return run_cg(G[0], opts, s);
   }
   if (opts->profile) {
     if (G.size() != 1) return fail(HM_E_ARG, "profiling times a single grid group");
@@ -1080,6 +1257,7 @@ int hm_effective_tensor_batch(const hm_problem* problems, int n_problems, const 
   if (!C_mandel) return fail(HM_E_ARG, "C_mandel is NULL");
   if ((rc = check_opts(opts))) return rc;
   if (opts->profile) return fail(HM_E_ARG, "profiling is not available for batches");
+  if (opts->method != HM_FIXED_POINT) return fail(HM_E_ARG, "batches use the fixed-point method");
   std::vector<ProblemIn> all((size_t)n_problems);
   for (int q = 0; q < n_problems; ++q) {
     const hm_problem& h = problems[q];

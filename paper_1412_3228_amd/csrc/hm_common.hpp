@@ -86,8 +86,19 @@ struct SolveParams {
 };
 
 // Plan-stable launch arguments.
+// Conjugate-gradient scalars of one load case (FP64).
+struct CgState {
+  double rr;     // (r . r) of the current residual, Parseval-weighted sum
+  double alpha;  // step of the current iteration
+  double beta;   // direction update of the current iteration
+  double pad;
+  double sE[6];  // <c~ : E>
+  double sx[6];  // <c~ : x> of the current iterate's fluctuation
+};
+
 struct SolveArgs {
   void* spec;       // cx<T>[n_load][6][nz][ny][Hp]  x-spectrum / full spectrum
+  const void* spec_in;  // x-sweep input (spec itself, or the CG direction)
   void* hist;       // cx<T>[n_load][3][nz][ny][Hp]  previous projected traction
   double* taupart;  // [n_load][g2][6]  per-block sums of tau
   double* errpart;  // [n_load][ny * ntx4]  per-block equilibrium sums
@@ -103,6 +114,15 @@ struct SolveArgs {
   int g2, ntx3, ntx4;
   int hist_cap;
   int first;  // 1 on iterate 0 (uniform strain, empty traction history)
+  // conjugate gradients (cg = 1): the sweeps apply -G to (c~ - I) : p with a
+  // zero mean, no traction history; vectors x, r, p share spec's layout
+  int cg;
+  int cg_blocks;     // blocks per load of the CG vector kernels
+  void* cgx;
+  void* cgr;
+  void* cgp;
+  CgState* cgs;      // [n_load]
+  double* cgpart;    // [n_load][cg_blocks]
 };
 
 }  // namespace hm

@@ -222,6 +222,7 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
   const int Hp = a.Hp;
   const size_t cs = (size_t)nlines * Hp;
   cx<T>* spec = static_cast<cx<T>*>(a.spec) + (size_t)load * 6 * cs;
+  const cx<T>* src = static_cast<const cx<T>*>(a.spec_in) + (size_t)load * 6 * cs;
 
   // row r = p * L + l: component pair p of line l (wave-uniform)
   cx<T> pa[RP][KH], pb[RP][KH];
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
       const int p = r / L, l = r - (r / L) * L;
       const int line = line0 + l;
       const bool rok = r < LL && line < nlines;
-      const cx<T>* ra = spec + (size_t)(2 * p) * cs + (size_t)line * Hp;
+      const cx<T>* ra = src + (size_t)(2 * p) * cs + (size_t)line * Hp;
       const cx<T>* rb = ra + cs;
 #pragma unroll
       for (int m = 0; m < KH; ++m) {
@@ -289,9 +290,10 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
       for (int x = lane; x < NX; x += 64) {
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
+          // a CG iterate is stored as its zero-mean fluctuation
           const cx<T> Z = buf[x * LD + p * L + l];
-          out[(size_t)(2 * p) * N + (size_t)line * NX + x] = Z.x;
-          out[(size_t)(2 * p + 1) * N + (size_t)line * NX + x] = Z.y;
+          out[(size_t)(2 * p) * N + (size_t)line * NX + x] = Z.x + (a.cg ? T(LP.E[2 * p]) : T(0));
+          out[(size_t)(2 * p + 1) * N + (size_t)line * NX + x] = Z.y + (a.cg ? T(LP.E[2 * p + 1]) : T(0));
         }
       }
     }
@@ -543,7 +545,7 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
   }
   // ring[r] holds group r, r + D, ...; then (CG == 1) history components
   cx<T> ring[D][CG][Q];
-  const bool hist_live = !a.first;
+  const bool hist_live = !a.first && !a.cg;
 #pragma unroll
   for (int r = 0; r < D; ++r)
 #pragma unroll
@@ -590,11 +592,11 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
    }
   }
 
-  // equilibrium error partial and traction history
+  // equilibrium error partial and traction history (not in CG mode)
   double S = 0.0;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    if (!ok[q]) continue;
+    if (!ok[q] || a.cg) continue;
     const int s = tid + q * NT;
     const int kz = s / W, w = s - kz * W;
     const int az = kz <= (NZ - 1) / 2 ? kz : kz - NZ;
@@ -652,7 +654,7 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
     const int c0 = cb + u * CG;
 #pragma unroll
     for (int g = 0; g < CG; ++g) {
-      const T Ec = T(LP.E[c0 + g]);
+      const T Ec = a.cg ? T(0) : T(LP.E[c0 + g]);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         if (tid + q * NT < SL) {
@@ -707,6 +709,7 @@ __global__ __launch_bounds__(64 * NW) void k_xsweep_wave(SolveArgs a) {
   const int Hp = a.Hp;
   const size_t cs = (size_t)nlines * Hp;
   cx<T>* spec = static_cast<cx<T>*>(a.spec) + (size_t)load * 6 * cs;
+  const cx<T>* src = static_cast<const cx<T>*>(a.spec_in) + (size_t)load * 6 * cs;
   cx<T>* buf = bufs[wv];
 
   cx<T> pa[QL], pb[QL];
@@ -723,8 +726,8 @@ __global__ __launch_bounds__(64 * NW) void k_xsweep_wave(SolveArgs a) {
         const int k = rem - l * H;
         const int line = line0 + l;
         if (line < nlines) {
-          pa[q] = spec[(size_t)(2 * p) * cs + (size_t)line * Hp + k];
-          pb[q] = spec[(size_t)(2 * p + 1) * cs + (size_t)line * Hp + k];
+          pa[q] = src[(size_t)(2 * p) * cs + (size_t)line * Hp + k];
+          pb[q] = src[(size_t)(2 * p + 1) * cs + (size_t)line * Hp + k];
         }
       }
     }
@@ -768,8 +771,8 @@ __global__ __launch_bounds__(64 * NW) void k_xsweep_wave(SolveArgs a) {
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
           const cx<T> Z = buf[x * LD + p * LW + l];
-          out[(size_t)(2 * p) * N + (size_t)line * NX + x] = Z.x;
-          out[(size_t)(2 * p + 1) * N + (size_t)line * NX + x] = Z.y;
+          out[(size_t)(2 * p) * N + (size_t)line * NX + x] = Z.x + (a.cg ? T(LP.E[2 * p]) : T(0));
+          out[(size_t)(2 * p + 1) * N + (size_t)line * NX + x] = Z.y + (a.cg ? T(LP.E[2 * p + 1]) : T(0));
         }
       }
     }
@@ -895,7 +898,7 @@ __global__ __launch_bounds__(384) void k_zsweep_wave(SolveArgs a) {
   for (int q = 0; q < QS; ++q) {
     const int s = tid + NT * q;
     const int kz = s / W, w = s - (s / W) * W;
-    const bool ok = s < SL && kx0 + w < H && !a.first;
+    const bool ok = s < SL && kx0 + w < H && !a.first && !a.cg;
 #pragma unroll
     for (int d = 0; d < 3; ++d)
       h[q][d] = ok ? hp[(size_t)d * plane + (size_t)kz * zs + w] : cx<T>{T(0), T(0)};
@@ -927,9 +930,10 @@ __global__ __launch_bounds__(384) void k_zsweep_wave(SolveArgs a) {
     const size_t go = (size_t)kz * zs + w;
     if (kx == 0 && ay == 0 && az == 0) {
 #pragma unroll
-      for (int d = 0; d < 6; ++d) rg[d * RS + o] = cx<T>{T(LP.E[d]), T(0)};
+      for (int d = 0; d < 6; ++d) rg[d * RS + o] = cx<T>{a.cg ? T(0) : T(LP.E[d]), T(0)};
+      if (!a.cg)
 #pragma unroll
-      for (int d = 0; d < 3; ++d) hp[(size_t)d * plane + go] = cx<T>{T(0), T(0)};
+        for (int d = 0; d < 3; ++d) hp[(size_t)d * plane + go] = cx<T>{T(0), T(0)};
       continue;
     }
     const double x0 = twopi * kx, x1 = twopi * ay, x2 = twopi * az;
@@ -945,10 +949,12 @@ __global__ __launch_bounds__(384) void k_zsweep_wave(SolveArgs a) {
     const double d0x = (double)a0.x - (double)h[q][0].x, d0y = (double)a0.y - (double)h[q][0].y;
     const double d1x = (double)a1.x - (double)h[q][1].x, d1y = (double)a1.y - (double)h[q][1].y;
     const double d2x = (double)a2.x - (double)h[q][2].x, d2y = (double)a2.y - (double)h[q][2].y;
-    S += (kx == 0 ? 1.0 : 2.0) * q2 * (d0x * d0x + d0y * d0y + d1x * d1x + d1y * d1y + d2x * d2x + d2y * d2y);
-    hp[go] = a0;
-    hp[plane + go] = a1;
-    hp[2 * plane + go] = a2;
+    if (!a.cg) {
+      S += (kx == 0 ? 1.0 : 2.0) * q2 * (d0x * d0x + d0y * d0y + d1x * d1x + d1y * d1y + d2x * d2x + d2y * d2y);
+      hp[go] = a0;
+      hp[plane + go] = a1;
+      hp[2 * plane + go] = a2;
+    }
     rg[o] = gamma_entry<T>(n0, n0, a0, a0, na, inv2mu, cc, m);
     rg[RS + o] = gamma_entry<T>(n1, n1, a1, a1, na, inv2mu, cc, m);
     rg[2 * RS + o] = gamma_entry<T>(n2, n2, a2, a2, na, inv2mu, cc, m);
@@ -1108,6 +1114,168 @@ __global__ __launch_bounds__(NT) void k_reset_state(SolverState* st, int n_load)
   z.err = z.err0 = z.res0 = z.ref = 0.0;
   for (int c = 0; c < 6; ++c) z.sig[c] = 0.0;
   st[l] = z;
+}
+
+// ---------------------------------------------------- conjugate gradients --
+// CG on the Galerkin form of the same operator (the Krylov alternative of
+// Section 5), with the reference medium c0 = identity: the four sweeps then
+// turn a direction p into w = -G((c~ - I) : p) (G the projection onto
+// compatible zero-mean fields), so q = G(c~ : p) = p - w.  Vectors x, r, p
+// and w live in the x-half-spectrum layout of the iterate (x-DFTs divided
+// by nx); a sum over voxels of u : v is, by Parseval along x, nx times the
+// sum over stored entries of w_c h_kx Re(u conj v) (w_c = 2 for shear
+// components, h_kx = 2 for kx > 0).  Every vector kernel writes one FP64
+// partial per block.
+
+enum : int { CG_INIT = 0, CG_DOT = 1, CG_UPDATE = 2, CG_DIR = 3 };
+enum : int { CGS_INIT = 0, CGS_ALPHA = 1, CGS_BETA = 2 };
+constexpr int kCgThreads = 256;
+
+template <typename T, int OP>
+__global__ __launch_bounds__(kCgThreads) void k_cg_vec(SolveArgs a) {
+  __shared__ double red[kCgThreads / 64];
+  const int load = blockIdx.y;
+  if (a.state[load].done) return;
+  const unsigned plane = (unsigned)a.nz * (unsigned)a.ny * (unsigned)a.Hp;
+  const unsigned total = 6u * plane;
+  const size_t off = (size_t)load * total;
+  cx<T>* W = static_cast<cx<T>*>(a.spec) + off;
+  cx<T>* X = static_cast<cx<T>*>(a.cgx) + off;
+  cx<T>* R = static_cast<cx<T>*>(a.cgr) + off;
+  cx<T>* P = static_cast<cx<T>*>(a.cgp) + off;
+  const T al = OP == CG_UPDATE ? T(a.cgs[load].alpha) : T(0);
+  const T be = OP == CG_DIR ? T(a.cgs[load].beta) : T(0);
+  double acc = 0.0;
+  for (unsigned e = blockIdx.x * kCgThreads + threadIdx.x; e < total; e += gridDim.x * kCgThreads) {
+    const unsigned kx = e % (unsigned)a.Hp;
+    if (kx >= (unsigned)a.H) continue;
+    const double wgt = (e / plane < 3u ? 1.0 : 2.0) * (kx == 0 ? 1.0 : 2.0);
+    if (OP == CG_INIT) {
+      const cx<T> w = W[e];
+      X[e] = cx<T>{T(0), T(0)};
+      R[e] = w;
+      P[e] = w;
+      acc += wgt * ((double)w.x * w.x + (double)w.y * w.y);
+    } else if (OP == CG_DOT) {
+      const cx<T> pv = P[e], w = W[e];
+      const cx<T> q = {pv.x - w.x, pv.y - w.y};
+      acc += wgt * ((double)pv.x * q.x + (double)pv.y * q.y);
+    } else if (OP == CG_UPDATE) {
+      const cx<T> pv = P[e], w = W[e], xv = X[e], rv = R[e];
+      const cx<T> q = {pv.x - w.x, pv.y - w.y};
+      const cx<T> rn = {rv.x - al * q.x, rv.y - al * q.y};
+      X[e] = cx<T>{xv.x + al * pv.x, xv.y + al * pv.y};
+      R[e] = rn;
+      acc += wgt * ((double)rn.x * rn.x + (double)rn.y * rn.y);
+    } else {
+      const cx<T> rv = R[e], pv = P[e];
+      P[e] = cx<T>{rv.x + be * pv.x, rv.y + be * pv.y};
+    }
+  }
+  if (OP == CG_DIR) return;
+  const double tot = block_sum<kCgThreads>(acc, red);
+  if (threadIdx.x == 0) a.cgpart[(size_t)load * a.cg_blocks + blockIdx.x] = tot;
+}
+
+// One block per load case: reduces the partials of the preceding vector
+// kernel (and, for INIT and ALPHA, the tau sums of the preceding x-sweep),
+// then takes the CG step (alpha), the direction update (beta), the error
+// e_k = sqrt(<r : r>) / |<sigma_k>| and the stop decision.
+template <int NT, int STEP>
+__global__ __launch_bounds__(NT) void k_cg_scalar(SolveArgs a) {
+  constexpr int NW = NT / 64;
+  constexpr int K = 7;
+  __shared__ double ws[NW][K], wc[NW][K];
+  const int load = blockIdx.x;
+  SolverState* st = a.state + load;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const double* pp = a.cgpart + (size_t)load * a.cg_blocks;
+  const double* tp = a.taupart + (size_t)load * a.g2 * 6;
+  const bool taus = STEP != CGS_BETA;
+  double s[K], c[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) s[k] = c[k] = 0.0;
+  if (st->done) return;
+  for (int i = tid; i < a.cg_blocks; i += NT) neumaier_add(s[6], c[6], pp[i]);
+  if (taus)
+    for (int i = tid; i < a.g2; i += NT)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) neumaier_add(s[k], c[k], tp[(size_t)i * 6 + k]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double so = __shfl_down(s[k], off, 64), co = __shfl_down(c[k], off, 64);
+      if (lane < off) neumaier_merge(s[k], c[k], so, co);
+    }
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      ws[wv][k] = s[k];
+      wc[wv][k] = c[k];
+    }
+  __syncthreads();
+  if (tid != 0) return;
+  double tot[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double sk = ws[0][k], ck = wc[0][k];
+    for (int w = 1; w < NW; ++w) neumaier_merge(sk, ck, ws[w][k], wc[w][k]);
+    tot[k] = sk + ck;
+  }
+  const SolveParams& S0 = *a.prm;
+  const LoadParams& LP = S0.loads[load];
+  CgState& cg = a.cgs[load];
+  const double N = (double)a.nx * (double)a.ny * (double)a.nz;
+  if (STEP == CGS_ALPHA) {
+    // <c~ : p> = <tau> + <p>, and p has zero mean
+    cg.alpha = cg.rr / tot[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) cg.sx[k] += cg.alpha * (tot[k] / N);
+    return;
+  }
+  const double rr = tot[6];
+  if (STEP == CGS_INIT) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      cg.sE[k] = tot[k] / N + LP.E[k];  // <c~ : E> = <tau_E> + I : E
+      cg.sx[k] = 0.0;
+    }
+    cg.beta = 0.0;
+  } else {
+    cg.beta = rr / cg.rr;
+  }
+  cg.rr = rr;
+  double sig[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sig[k] = cg.sE[k] + cg.sx[k];
+  const double fro = sqrt(sig[0] * sig[0] + sig[1] * sig[1] + sig[2] * sig[2] +
+                          2.0 * (sig[3] * sig[3] + sig[4] * sig[4] + sig[5] * sig[5]));
+  const double rms = sqrt(fmax(rr, 0.0) * (double)a.nx / N);
+  const double e = fro > 0.0 ? rms / fro : (rr == 0.0 ? 0.0 : INFINITY);
+  const int i = STEP == CGS_INIT ? 0 : st->iter;
+  if (i < a.hist_cap) a.errhist[(size_t)load * a.hist_cap + i] = e;
+  if (i == 0) {
+    st->err0 = e;
+    st->res0 = rms;
+  }
+  int status = ST_RUNNING;
+  if (e < S0.tol)
+    status = ST_CONVERGED;
+  else if (!isfinite(e))
+    status = ST_DIVERGED;
+  else if (i >= S0.max_iter)
+    status = ST_NOT_CONVERGED;
+  st->err = e;
+  st->iters = i;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) st->sig[k] = sig[k];
+  if (status != ST_RUNNING) {
+    st->status = status;
+    st->done = 1;
+  }
+  st->iter = i + 1;
 }
 
 // ------------------------------------------------------------ registry --
