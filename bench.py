@@ -203,6 +203,35 @@ def roofline(timings, n, prec, reports, n_frac=0):
             "ms_per_kernel": {k: v / its for k, v in tot.items()}}
 
 
+def time_to_solution(hm, works, ref, dev):
+    """Untimed context beside the metric: wall time of the mixed-precision
+    six-load solve alone (filter done, graph replay) with the fixed-point
+    scheme (tol 1e-4, stall window 20) and with conjugate gradients on the
+    same operator (tol 1e-5 on its residual criterion), with each one's
+    C_eff error against the tightly converged FP64 tensor."""
+    out = {}
+    for c, w in works.items():
+        _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "mixed", dev)
+        row = {}
+        for name, kw in (("fixed_point", dict(tol=w.tol, stall_window=20, check_every=16)),
+                         ("cg", dict(tol=1e-5, method="cg", check_every=8))):
+            hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, prec="mixed",
+                                   max_iter=5000, use_graph=True, **kw)  # plan, tuning and graph warm
+            _sync()
+            t0 = time.perf_counter()
+            o = hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, prec="mixed",
+                                       max_iter=5000, use_graph=True, **kw)
+            _sync()
+            row[name] = {"seconds": time.perf_counter() - t0,
+                         "iters": max(r["iters"] for r in o["reports"]),
+                         "ceff_rel_err_vs_fp64_tol1e-9": float(np.linalg.norm(o["C"] - ref[c]) /
+                                                               np.linalg.norm(ref[c]))}
+        row["speedup_cg"] = row["fixed_point"]["seconds"] / row["cg"]["seconds"]
+        out[str(c)] = row
+        del frac, incl
+    return out
+
+
 def cpu_baseline(iters=1):
     """The oracle timed on this host's cores on a bounded sample of the workload."""
     from oracle import filter as ofilter, solver as osolver
@@ -351,6 +380,7 @@ def main():
         "roofline": mixed["roofline"],
         "cpu_baseline": None,
     }
+    line["time_to_solution"] = time_to_solution(hm, works, ref, dev)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
