@@ -1338,10 +1338,11 @@ template <typename T, int N, int V> struct XTile {
   static constexpr int L = clamp_int(want < cap ? want : cap, 1, 8);
   static constexpr int NT = 256;
 };
-// ysweep variant v: width 128 B or 256 B of kx per row.
+// ysweep variant v: width 128 B (v = 0), 256 B (v = 1, 3) or 512 B (v = 2)
+// of kx per row; 256 threads, or 512 for v = 2 and 3.
 template <typename T, int N, int V> struct YTile {
-  static constexpr int W = (V == 0 ? 128 : 256) / (int)sizeof(cx<T>);
-  static constexpr int NT = 256;
+  static constexpr int W = (V == 0 ? 128 : (V == 2 ? 512 : 256)) / (int)sizeof(cx<T>);
+  static constexpr int NT = V >= 2 ? 512 : 256;
 };
 // zsweep variant v: width 128 B (v = 0) or 256 B (v = 1, 64 B when that
 // would need more than 1024 threads); threads so that each holds at most QT
@@ -1429,7 +1430,9 @@ AxisKernels make_axis_kernels() {
     k.x[k.nxv++] = make_x<T, N, 3>();
   k.y[0] = make_y<T, N, 0>();
   k.y[1] = make_y<T, N, 1>();
-  k.nyv = 2;
+  k.y[2] = make_y<T, N, 2>();
+  k.y[3] = make_y<T, N, 3>();
+  k.nyv = 4;
   k.z[0] = make_z<T, N, 0>();
   k.z[1] = make_z<T, N, 1>();
   k.nzv = 2;
