@@ -85,12 +85,12 @@ def summarize(trace_dir, fetch_dir, write_dir, out):
     sf = calib / 1024.0 / (sum(cal_f) / len(cal_f))
     sw = calib / 1024.0 / (sum(cal_w) / len(cal_w))
     lines = ["# rocprofv3 summary: solver sweeps, centred-sphere 125^3 cell, 6 load cases",
-             "# commands (run from /tmp with TMPDIR=/tmp, repository at $R):",
-             "#   rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof/trace -o kp -- "
+             "# commands (run from /tmp with TMPDIR=/tmp, repository at $R, output under $OUT):",
+             "#   rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/trace -o kp -- "
              "python3 -u $R/bench.py --kernel-pass",
-             "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/prof/fetch -o kp -- "
+             "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/fetch -o kp -- "
              "python3 -u $R/bench.py --kernel-pass",
-             "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/prof/write -o kp -- "
+             "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/write -o kp -- "
              "python3 -u $R/bench.py --kernel-pass",
              "#   python3 bench.py --summarize <trace> <fetch> <write> --out <this file>",
              "# calibration: a %d-byte device copy reads FETCH_SIZE x %.4f and WRITE_SIZE x %.4f of its bytes;"
@@ -277,7 +277,7 @@ def main():
         summarize(*args.summarize, args.out)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the solver has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1412_3228_amd as hm

@@ -8,7 +8,7 @@ setup of Section 2 fixes the filter radius in pixel units (0.5 being the
 circle inscribed in a pixel) and the interface normal as the unit vector
 from the inclusion centre to x_a.
 
-Integer lattice (reading of the refined grid, documented in the design doc):
+Integer lattice (this reading of the refined grid):
 lengths are measured in units u = h / (2 S) where h is the voxel size and S
 the number of sub-samples per voxel and axis (S even).  Voxel a has its
 centre at (2 a + 1) S; the refined grid is the global lattice of spacing

@@ -7,7 +7,7 @@ and eps^(0) = E (eq. 2); on an odd grid the frequencies are the integer
 set J = prod_d {-(N_d-1)/2 .. (N_d-1)/2}.  The polarization is evaluated at
 the grid points with the filtered stiffness c~ in place of c.
 
-Readings (documented in DESIGN.md):
+Readings taken where the paper is silent:
 * grid points are voxel centres, the cell is [0,1)^d, frequencies
   xi = 2 pi a for a in J; 2D is plane strain (a 3D cell one voxel thick);
 * the reference medium is the mean of the phases' smallest and largest
