@@ -226,6 +226,58 @@ int hm_effective_tensor(const hm_grid* grid, const hm_iso phases[2], hm_rule rul
                         const hm_solve_opts* opts, double* C_mandel,
                         void* d_eps, hm_report* rep, void* stream);
 
+/*
+ * hm_conduct_solve - the same filtered fixed-point scheme for a scalar
+ * conductivity (thermal or electrical), for n_load mean gradients at once.
+ *
+ * Section 2's scheme applied to conduction, the other physical context in
+ * which the abstract expects the filters to help: the unknown is the gradient
+ * field g with mean G, the flux q = k~ g, tau = (k~ - k0) g, and
+ * g^(xi) = -n (n . tau^(xi)) / k0 for xi != 0 (n = xi / |xi|), g^(0) = G,
+ * the conduction form of eqs. 1-a, 1-b and 2.  k~ per voxel: k[p] I where
+ * f is exactly 0 or 1, else the rule at f: HM_RULE_VOIGT <k> I (eq. 3),
+ * HM_RULE_REUSS <1/k>^-1 I (eq. 4), HM_RULE_LAMINATE <k> (I - n n) +
+ * <1/k>^-1 n n (eq. 5: layers along the interface in parallel, across it in
+ * series; n from the centre of sphere d_incl[v] to the voxel centre, e_1
+ * when d_incl[v] < 0).  k0 = c0_alpha times the mean of the smallest and
+ * largest conductivity.  Error of iterate i:
+ * e_i = sqrt(sum_xi |xi . q^_i(xi)|^2) / |q^_i(0)| (flux equilibrium, same
+ * stop rules as hm_solve).
+ *
+ * Inputs:  k (host, 2 doubles > 0: matrix, inclusion), d_frac, d_incl,
+ *          spheres as hm_solve, G (host, 3 * n_load doubles: the x, y, z
+ *          components of each mean gradient; in 2D the z component is
+ *          carried unchanged).  opts as hm_solve, except that only
+ *          HM_FIXED_POINT is accepted, autotune is ignored and schedule
+ *          must be -1 or 0 (one compiled schedule).
+ * Outputs: flux_mean (host, 3 * n_load doubles, <q_i> of the reported
+ *          iterate), rep (host, n_load entries, nullable), d_grad
+ *          (nullable, device, 3 * N * n_load reals of the solve precision,
+ *          [load][component][z][y][x]: the gradient field produced by the
+ *          update from the reported iterate).
+ * Returns the largest status over load cases, or a negative error
+ * (HM_E_DATA as hm_solve).  n_load is at most 4096.
+ */
+int hm_conduct_solve(const hm_grid* grid, const double k[2], hm_rule rule,
+                     const void* d_frac, const int32_t* d_incl,
+                     const hm_sphere* spheres, int n_spheres,
+                     const double* G, int n_load, const hm_solve_opts* opts,
+                     void* d_grad, double* flux_mean, hm_report* rep, void* stream);
+
+/*
+ * hm_effective_conductivity - effective conductivity tensor from the mean
+ * fluxes under the unit gradients e_1..e_dim, solved in one batched launch.
+ * Column J of K is <q> under G = e_J.  Inputs as hm_conduct_solve.
+ * Outputs: K (host, 9 doubles in 3D, 4 in 2D, row-major), rep (host, 3 or 2
+ * entries, nullable), d_grad (nullable, device gradient fields of the 3 or
+ * 2 solves, as hm_conduct_solve).
+ */
+int hm_effective_conductivity(const hm_grid* grid, const double k[2], hm_rule rule,
+                              const void* d_frac, const int32_t* d_incl,
+                              const hm_sphere* spheres, int n_spheres,
+                              const hm_solve_opts* opts, double* K,
+                              void* d_grad, hm_report* rep, void* stream);
+
 /* One cell of a batch: grid, phases, rule and its device fraction / normal
  * fields and host sphere table, with the meanings of hm_solve. */
 typedef struct {

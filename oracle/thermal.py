@@ -1,9 +1,8 @@
 """Scalar conductivity (thermal / electrical) counterpart of the filtered
 Lippmann-Schwinger fixed point (oracle; test infrastructure only).
 
-The paper's FFT scheme and filters apply to any linear property (its
-introduction names the wider range of physical properties FFT solvers
-cover).  For conduction the unknown is the gradient field g = grad T with
+The paper's study is elastic, but its abstract expects the filters to
+help in the same way for thermal or electrical conduction.  For conduction the unknown is the gradient field g = grad T with
 mean G, the flux is q = k~ g, equilibrium is div q = 0, the polarization is
 tau = (k~ - k0) g with a scalar reference k0, and the Green operator is
 Gamma0^(xi) = n (x) n / k0 (n = xi / |xi|):  g^(xi) = -Gamma0^ tau^ for

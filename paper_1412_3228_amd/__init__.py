@@ -8,6 +8,8 @@ package is its thin Python binding.
 from .api import (  # noqa: F401
     EffectiveTensor,
     device_ok,
+    hm_conduct_solve,
+    hm_effective_conductivity,
     hm_effective_tensor,
     hm_effective_tensor_batch,
     hm_filter,

@@ -158,6 +158,60 @@ def hm_effective_tensor(n, dim, phases, rule: str, frac: torch.Tensor, incl: Opt
     return {"status": rc, "C": C, "reports": _reports(rep, k), "eps": eps}
 
 
+def _conductivities(k) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(k, dtype=np.float64).reshape(2))
+    return a
+
+
+def hm_conduct_solve(n, dim, k, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres, G,
+                     prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
+                     check_every: int = 1, stall_window: int = 0, use_graph: bool = False,
+                     want_grad: bool = False, profile: bool = False):
+    """Conduction solve for the rows of G (n_load x 3 mean-gradient components); k = (matrix, inclusion)."""
+    dev = frac.device
+    N = int(n[0] * n[1] * n[2])
+    _check_field(frac, N, _DT[prec], dev, "frac")
+    _check_field(incl, N, torch.int32, dev, "incl")
+    Ga = np.ascontiguousarray(np.asarray(G, dtype=np.float64).reshape(-1, 3))
+    nl = Ga.shape[0]
+    q = np.zeros((nl, 3))
+    rep = (L.HmReport * nl)()
+    grad = torch.empty((nl, 3, N), dtype=_DT[prec], device=dev) if want_grad else None
+    g = _grid(n, dim)
+    sph, ns = _spheres(spheres)
+    kk = _conductivities(k)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, False, None)
+    rc = _lib().hm_conduct_solve(ctypes.byref(g), kk.ctypes.data_as(L._dp), L.RULES[rule], _ptr(frac), _ptr(incl),
+                                 sph, ns, Ga.ctypes.data_as(L._dp), nl, ctypes.byref(o), _ptr(grad),
+                                 q.ctypes.data_as(L._dp), rep, _stream(dev))
+    L.check(rc)
+    return {"status": rc, "flux_mean": q, "reports": _reports(rep, nl), "grad": grad}
+
+
+def hm_effective_conductivity(n, dim, k, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres,
+                              prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
+                              check_every: int = 1, stall_window: int = 0, use_graph: bool = False,
+                              want_grad: bool = False, profile: bool = False):
+    """Effective conductivity tensor (dim x dim) from the unit-gradient solves."""
+    dev = frac.device
+    N = int(n[0] * n[1] * n[2])
+    _check_field(frac, N, _DT[prec], dev, "frac")
+    _check_field(incl, N, torch.int32, dev, "incl")
+    nd = 2 if dim == 2 else 3
+    K = np.zeros((nd, nd))
+    rep = (L.HmReport * nd)()
+    grad = torch.empty((nd, 3, N), dtype=_DT[prec], device=dev) if want_grad else None
+    g = _grid(n, dim)
+    sph, ns = _spheres(spheres)
+    kk = _conductivities(k)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, False, None)
+    rc = _lib().hm_effective_conductivity(ctypes.byref(g), kk.ctypes.data_as(L._dp), L.RULES[rule], _ptr(frac),
+                                          _ptr(incl), sph, ns, ctypes.byref(o), K.ctypes.data_as(L._dp),
+                                          _ptr(grad), rep, _stream(dev))
+    L.check(rc)
+    return {"status": rc, "K": K, "reports": _reports(rep, nd), "grad": grad}
+
+
 def hm_effective_tensor_batch(problems, prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000,
                               c0_alpha: float = 1.0, check_every: int = 16, stall_window: int = 0,
                               use_graph: bool = True, autotune: bool = True):

@@ -25,6 +25,7 @@
 #include "hm_common.hpp"
 #include "hm_adjoint.hpp"
 #include "hm_filter.hpp"
+#include "hm_conduct_kernels.hpp"
 #include "hm_solve_kernels.hpp"
 
 namespace hm {
@@ -54,6 +55,16 @@ const AxisKernels* axis_kernels(bool fp64, int n) {
   return k;
 }
 
+const CondKernels* cond_kernels_f64_g0(int n);
+const CondKernels* cond_kernels_f64_g1(int n);
+const CondKernels* cond_kernels_f32_g0(int n);
+const CondKernels* cond_kernels_f32_g1(int n);
+
+const CondKernels* cond_kernels(bool fp64, int n) {
+  const CondKernels* k = fp64 ? cond_kernels_f64_g0(n) : cond_kernels_f32_g0(n);
+  if (!k) k = fp64 ? cond_kernels_f64_g1(n) : cond_kernels_f32_g1(n);
+  return k;
+}
 
 }  // namespace hm
 
@@ -162,12 +173,14 @@ void set_schedule(Plan* p, const XKern* X, const YKern* Y, const ZKern* Z);
 
 struct Plan {
   bool fp64 = true;
+  bool cond = false;  // conduction plan: 3 gradient components, conduction kernels
   int n[3] = {0, 0, 0};
   int n_load = 0;
   int device = 0;
   const AxisKernels* kx = nullptr;
   const AxisKernels* ky = nullptr;
   const AxisKernels* kz = nullptr;
+  const CondKernels* ck[3] = {nullptr, nullptr, nullptr};  // conduction plans
   const XKern* X = nullptr;  // chosen schedules
   const YKern* Y = nullptr;
   const ZKern* Z = nullptr;
@@ -203,7 +216,7 @@ struct Plan {
 };
 
 std::mutex g_mutex;
-std::map<std::tuple<int, bool, int, int, int, int>, Plan*> g_plans;
+std::map<std::tuple<int, bool, bool, int, int, int, int>, Plan*> g_plans;
 
 void free_plan(Plan* p) {
   if (p->graph) (void)hipGraphExecDestroy(p->graph);
@@ -262,11 +275,11 @@ int upload_twiddles(Plan* p, int axis, int n) {
   return HM_OK;
 }
 
-int get_plan(bool fp64, const int n[3], int dim, int n_load, Plan** out) {
+int get_plan(bool fp64, const int n[3], int dim, int n_load, bool cond, Plan** out) {
   int dev = 0;
   HM_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lock(g_mutex);
-  auto key = std::make_tuple(dev, fp64, n[0], n[1], n[2], n_load);
+  auto key = std::make_tuple(dev, fp64, cond, n[0], n[1], n[2], n_load);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) {
     *out = it->second;
@@ -277,13 +290,22 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, Plan** out) {
   p->device = dev;
   for (int d = 0; d < 3; ++d) p->n[d] = n[d];
   p->n_load = n_load;
-  p->kx = axis_kernels(fp64, n[0]);
-  p->ky = axis_kernels(fp64, n[1]);
-  p->kz = axis_kernels(fp64, n[2]);
-  if (!p->kx || !p->ky || !p->kz) {
+  p->cond = cond;
+  bool have = true;
+  if (cond) {
+    for (int d = 0; d < 3; ++d) have = have && (p->ck[d] = cond_kernels(fp64, n[d])) != nullptr;
+  } else {
+    p->kx = axis_kernels(fp64, n[0]);
+    p->ky = axis_kernels(fp64, n[1]);
+    p->kz = axis_kernels(fp64, n[2]);
+    have = p->kx && p->ky && p->kz;
+  }
+  if (!have) {
     delete p;
     return fail(HM_E_SIZE, "no kernels compiled for grid %dx%dx%d", n[0], n[1], n[2]);
   }
+  const int nc = cond ? 3 : 6;     // field components per load
+  const int nh = cond ? 1 : 3;     // traction-history components per load
   const int H = (n[0] + 1) / 2;
   const size_t cplx = fp64 ? 16 : 8;
   const int row = (int)(128 / cplx);  // complex values per 128-byte line
@@ -291,13 +313,18 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, Plan** out) {
   const size_t plane = (size_t)n[2] * n[1] * Hp;
   // partial-sum buffers sized for the finest schedule of each kernel
   int min_lines = 1 << 30, min_zw = 1 << 30;
-  for (int v = 0; v < p->kx->nxv; ++v) min_lines = std::min(min_lines, p->kx->x[v].lines);
-  for (int v = 0; v < p->kz->nzv; ++v) min_zw = std::min(min_zw, p->kz->z[v].width);
+  if (cond) {
+    min_lines = p->ck[0]->x.lines;
+    min_zw = p->ck[2]->z.width;
+  } else {
+    for (int v = 0; v < p->kx->nxv; ++v) min_lines = std::min(min_lines, p->kx->x[v].lines);
+    for (int v = 0; v < p->kz->nzv; ++v) min_zw = std::min(min_zw, p->kz->z[v].width);
+  }
   const int g2 = (n[1] * n[2] + min_lines - 1) / min_lines;
   const int ntx4 = (H + min_zw - 1) / min_zw;
   int rc = HM_OK;
-  if (!rc) rc = device_alloc(&p->spec, (size_t)n_load * 6 * plane * cplx, "spectrum");
-  if (!rc) rc = device_alloc(&p->hist, (size_t)n_load * 3 * plane * cplx, "traction history");
+  if (!rc) rc = device_alloc(&p->spec, (size_t)n_load * nc * plane * cplx, "spectrum");
+  if (!rc) rc = device_alloc(&p->hist, (size_t)n_load * nh * plane * cplx, "traction history");
   if (!rc) rc = device_alloc((void**)&p->taupart, (size_t)n_load * g2 * 6 * sizeof(double), "tau partials");
   if (!rc) rc = device_alloc((void**)&p->errpart, (size_t)n_load * n[1] * ntx4 * sizeof(double), "error partials");
   if (!rc) rc = device_alloc((void**)&p->state, (size_t)n_load * sizeof(SolverState), "state");
@@ -328,7 +355,11 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, Plan** out) {
   a.Hp = Hp;
   a.dim = dim;
   a.n_load = n_load;
-  set_schedule(p, &p->kx->x[0], &p->ky->y[0], &p->kz->z[0]);
+  a.cond = cond ? 1 : 0;
+  if (cond)
+    set_schedule(p, &p->ck[0]->x, &p->ck[1]->y, &p->ck[2]->z);
+  else
+    set_schedule(p, &p->kx->x[0], &p->ky->y[0], &p->kz->z[0]);
   g_plans[key] = p;
   *out = p;
   return HM_OK;
@@ -490,6 +521,8 @@ int tune_plan(Plan* p, hipStream_t s) {
 struct ProblemIn {
   hm_grid grid;
   hm_iso phases[2];
+  int cond;      // conduction problem: phase conductivities in k, phases unused
+  double k[2];
   hm_rule rule;
   const void* frac;
   const int32_t* incl;
@@ -509,7 +542,12 @@ struct Group {
 int check_problem(const ProblemIn& d) {
   int rc;
   if ((rc = check_grid(&d.grid))) return rc;
-  if ((rc = check_phases(d.phases))) return rc;
+  if (d.cond) {
+    for (int p = 0; p < 2; ++p)
+      if (!(d.k[p] > 0.0) || !isfinite(d.k[p])) return fail(HM_E_ARG, "conductivity %d must be finite and > 0", p);
+  } else if ((rc = check_phases(d.phases))) {
+    return rc;
+  }
   if ((rc = check_spheres(&d.grid, d.sph, d.nsph))) return rc;
   if (d.rule < HM_RULE_NONE || d.rule > HM_RULE_LAMINATE) return fail(HM_E_ARG, "unknown rule %d", (int)d.rule);
   if (!d.frac) return fail(HM_E_ARG, "d_frac is NULL");
@@ -577,26 +615,37 @@ int upload_params(Group& g, const std::vector<ProblemIn>& all, const hm_solve_op
   for (int j = 0; j < np; ++j) {
     const ProblemIn& d = all[g.probs[j]];
     ProblemParams& q = PP[j];
-    for (int ph = 0; ph < 2; ++ph) {
-      q.pl[ph] = d.phases[ph].lambda;
-      q.pm[ph] = d.phases[ph].mu;
-    }
-    const double lmin = fmin(q.pl[0], q.pl[1]), lmax = fmax(q.pl[0], q.pl[1]);
-    const double mmin = fmin(q.pm[0], q.pm[1]), mmax = fmax(q.pm[0], q.pm[1]);
-    q.rl = opts->c0_alpha * 0.5 * (lmin + lmax);
-    q.rm = opts->c0_alpha * 0.5 * (mmin + mmax);
-    if (opts->method == HM_CONJUGATE_GRADIENT) {
-      // c0 = identity on symmetric tensors: Gamma0 becomes the projection G
-      q.rl = 0.0;
-      q.rm = 0.5;
-    }
-    if (!(q.rm > 0.0) || !(q.rl + 2.0 * q.rm > 0.0)) return fail(HM_E_ARG, "reference medium is not positive");
-    for (int ph = 0; ph < 2; ++ph) {
-      // the rounding of T(lambda) - T(lambda0) and T(2 mu) - T(2 mu0) in T
-      q.pure_f[2 * ph] = (float)q.pl[ph] - (float)q.rl;
-      q.pure_f[2 * ph + 1] = (float)(2.0 * q.pm[ph]) - (float)(2.0 * q.rm);
-      q.pure_d[2 * ph] = q.pl[ph] - q.rl;
-      q.pure_d[2 * ph + 1] = 2.0 * q.pm[ph] - 2.0 * q.rm;
+    if (d.cond) {
+      // conductivities in pl, k0 = alpha * mean of the smallest and largest
+      q.pl[0] = d.k[0];
+      q.pl[1] = d.k[1];
+      q.rl = opts->c0_alpha * 0.5 * (fmin(d.k[0], d.k[1]) + fmax(d.k[0], d.k[1]));
+      for (int ph = 0; ph < 2; ++ph) {
+        q.pure_f[2 * ph] = (float)d.k[ph] - (float)q.rl;
+        q.pure_d[2 * ph] = d.k[ph] - q.rl;
+      }
+    } else {
+      for (int ph = 0; ph < 2; ++ph) {
+        q.pl[ph] = d.phases[ph].lambda;
+        q.pm[ph] = d.phases[ph].mu;
+      }
+      const double lmin = fmin(q.pl[0], q.pl[1]), lmax = fmax(q.pl[0], q.pl[1]);
+      const double mmin = fmin(q.pm[0], q.pm[1]), mmax = fmax(q.pm[0], q.pm[1]);
+      q.rl = opts->c0_alpha * 0.5 * (lmin + lmax);
+      q.rm = opts->c0_alpha * 0.5 * (mmin + mmax);
+      if (opts->method == HM_CONJUGATE_GRADIENT) {
+        // c0 = identity on symmetric tensors: Gamma0 becomes the projection G
+        q.rl = 0.0;
+        q.rm = 0.5;
+      }
+      if (!(q.rm > 0.0) || !(q.rl + 2.0 * q.rm > 0.0)) return fail(HM_E_ARG, "reference medium is not positive");
+      for (int ph = 0; ph < 2; ++ph) {
+        // the rounding of T(lambda) - T(lambda0) and T(2 mu) - T(2 mu0) in T
+        q.pure_f[2 * ph] = (float)q.pl[ph] - (float)q.rl;
+        q.pure_f[2 * ph + 1] = (float)(2.0 * q.pm[ph]) - (float)(2.0 * q.rm);
+        q.pure_d[2 * ph] = q.pl[ph] - q.rl;
+        q.pure_d[2 * ph + 1] = 2.0 * q.pm[ph] - 2.0 * q.rm;
+      }
     }
     q.rule = (int)d.rule;
     q.nsph = d.nsph;
@@ -643,12 +692,19 @@ int prepare_material(Group& g, const std::vector<ProblemIn>& all, const hm_solve
       const int N = gr.n[0] * gr.n[1] * gr.n[2];
       const SolveParams* prm = reinterpret_cast<const SolveParams*>(p->prm);
       const int cap = (int)std::min<size_t>(p->coef_cap, (size_t)1 << 30);
-      if (p->fp64)
-        hipLaunchKernelGGL((k_material<double>), dim3((N + 255) / 256), dim3(256), 0, s, prm, j, gr.n[0], gr.n[1],
-                           gr.n[2], gr.dim, p->mid + mo, static_cast<double*>(p->coef), cap, p->mcount);
+      const dim3 grid((N + 255) / 256), blk(256);
+      if (p->fp64 && p->cond)
+        hipLaunchKernelGGL((k_material<double, true>), grid, blk, 0, s, prm, j, gr.n[0], gr.n[1], gr.n[2], gr.dim,
+                           p->mid + mo, static_cast<double*>(p->coef), cap, p->mcount);
+      else if (p->fp64)
+        hipLaunchKernelGGL((k_material<double>), grid, blk, 0, s, prm, j, gr.n[0], gr.n[1], gr.n[2], gr.dim,
+                           p->mid + mo, static_cast<double*>(p->coef), cap, p->mcount);
+      else if (p->cond)
+        hipLaunchKernelGGL((k_material<float, true>), grid, blk, 0, s, prm, j, gr.n[0], gr.n[1], gr.n[2], gr.dim,
+                           p->mid + mo, static_cast<float*>(p->coef), cap, p->mcount);
       else
-        hipLaunchKernelGGL((k_material<float>), dim3((N + 255) / 256), dim3(256), 0, s, prm, j, gr.n[0], gr.n[1],
-                           gr.n[2], gr.dim, p->mid + mo, static_cast<float*>(p->coef), cap, p->mcount);
+        hipLaunchKernelGGL((k_material<float>), grid, blk, 0, s, prm, j, gr.n[0], gr.n[1], gr.n[2], gr.dim,
+                           p->mid + mo, static_cast<float*>(p->coef), cap, p->mcount);
       HM_HIP(hipGetLastError());
       mo += (size_t)N;
     }
@@ -909,7 +965,10 @@ int run_groups(std::vector<Group>& G, const std::vector<ProblemIn>& all, const h
     if ((rc = ensure_hist(g.p, opts->max_iter + 1))) return rc;
     if ((rc = upload_params(g, all, opts, s))) return rc;
     if ((rc = prepare_material(g, all, opts, s))) return rc;
-    if (opts->autotune) {
+    if (g.p->cond) {
+      // conduction plans have one compiled schedule
+      if (opts->schedule >= 0 && opts->schedule != 0) return fail(HM_E_ARG, "conduction solves have one schedule");
+    } else if (opts->autotune) {
       if (!g.p->tuned && (rc = tune_plan(g.p, s))) return rc;
     } else if (opts->schedule >= 0) {
       const int xv = opts->schedule & 15, yv = (opts->schedule >> 4) & 15, zv = (opts->schedule >> 8) & 15;
@@ -1052,7 +1111,7 @@ int solve_one(const ProblemIn& d, const double* E, int n_load, const hm_solve_op
     if (!isfinite(E[i])) return fail(HM_E_ARG, "E has a non-finite entry");
   std::vector<ProblemIn> all{d};
   std::vector<Group> G(1);
-  if ((rc = get_plan(opts->prec == HM_FP64, d.grid.n, d.grid.dim, n_load, &G[0].p))) return rc;
+  if ((rc = get_plan(opts->prec == HM_FP64, d.grid.n, d.grid.dim, n_load, d.cond != 0, &G[0].p))) return rc;
   G[0].probs = {0};
   G[0].loads.resize(n_load);
   for (int l = 0; l < n_load; ++l) {
@@ -1063,6 +1122,34 @@ int solve_one(const ProblemIn& d, const double* E, int n_load, const hm_solve_op
   G[0].eps_out = d_eps;
   if ((rc = run_groups(G, all, opts, s))) return rc;
   *plan_out = G[0].p;
+  return HM_OK;
+}
+
+// The conduction solve shared by hm_conduct_solve and hm_effective_conductivity:
+// G holds 3 mean-gradient components per load case.
+int solve_cond(const ProblemIn& d, const double* G, int n_load, const hm_solve_opts* opts, void* d_grad,
+               hipStream_t s, Plan** plan_out) {
+  int rc;
+  if ((rc = check_problem(d))) return rc;
+  if ((rc = check_opts(opts))) return rc;
+  if (opts->method != HM_FIXED_POINT) return fail(HM_E_ARG, "conduction solves use the fixed-point method");
+  if (n_load < 1 || n_load > kMaxLoads) return fail(HM_E_ARG, "n_load must be in 1..%d", kMaxLoads);
+  for (int i = 0; i < 3 * n_load; ++i)
+    if (!isfinite(G[i])) return fail(HM_E_ARG, "G has a non-finite entry");
+  std::vector<ProblemIn> all{d};
+  std::vector<Group> grp(1);
+  if ((rc = get_plan(opts->prec == HM_FP64, d.grid.n, d.grid.dim, n_load, true, &grp[0].p))) return rc;
+  grp[0].probs = {0};
+  grp[0].loads.resize(n_load);
+  for (int l = 0; l < n_load; ++l) {
+    LoadParams& L = grp[0].loads[l];
+    for (int c = 0; c < 6; ++c) L.E[c] = c < 3 ? G[3 * l + c] : 0.0;
+    L.prob = 0;
+    L.pad = 0;
+  }
+  grp[0].eps_out = d_grad;
+  if ((rc = run_groups(grp, all, opts, s))) return rc;
+  *plan_out = grp[0].p;
   return HM_OK;
 }
 
@@ -1249,6 +1336,61 @@ int hm_effective_tensor(const hm_grid* grid, const hm_iso phases[2], hm_rule rul
   return worst;
 }
 
+int hm_conduct_solve(const hm_grid* grid, const double k[2], hm_rule rule, const void* d_frac,
+                     const int32_t* d_incl, const hm_sphere* spheres, int n_spheres, const double* G, int n_load,
+                     const hm_solve_opts* opts, void* d_grad, double* flux_mean, hm_report* rep, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!k) return fail(HM_E_ARG, "k is NULL");
+  if (!G || !flux_mean) return fail(HM_E_ARG, "G and flux_mean must not be NULL");
+  ProblemIn d = make_problem(grid, nullptr, rule, d_frac, d_incl, spheres, n_spheres);
+  d.cond = 1;
+  d.k[0] = k[0];
+  d.k[1] = k[1];
+  Plan* p = nullptr;
+  int rc = solve_cond(d, G, n_load, opts, d_grad, (hipStream_t)stream, &p);
+  if (rc) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = HM_OK;
+  for (int l = 0; l < n_load; ++l) {
+    const SolverState& st = p->state_host[l];
+    for (int c = 0; c < 3; ++c) flux_mean[3 * l + c] = st.sig[c];
+    const int status = load_status(st);
+    if (rep) rep[l] = hm_report{st.iters, status, st.err, st.err0, secs};
+    worst = std::max(worst, status);
+  }
+  return worst;
+}
+
+int hm_effective_conductivity(const hm_grid* grid, const double k[2], hm_rule rule, const void* d_frac,
+                              const int32_t* d_incl, const hm_sphere* spheres, int n_spheres,
+                              const hm_solve_opts* opts, double* K, void* d_grad, hm_report* rep, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  int rc;
+  if ((rc = check_grid(grid))) return rc;
+  if (!k) return fail(HM_E_ARG, "k is NULL");
+  if (!K) return fail(HM_E_ARG, "K is NULL");
+  const int nd = grid->dim == 2 ? 2 : 3;
+  double G[9] = {0.0};
+  for (int J = 0; J < nd; ++J) G[3 * J + J] = 1.0;
+  ProblemIn d = make_problem(grid, nullptr, rule, d_frac, d_incl, spheres, n_spheres);
+  d.cond = 1;
+  d.k[0] = k[0];
+  d.k[1] = k[1];
+  Plan* p = nullptr;
+  rc = solve_cond(d, G, nd, opts, d_grad, (hipStream_t)stream, &p);
+  if (rc) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = HM_OK;
+  for (int J = 0; J < nd; ++J) {
+    const SolverState& st = p->state_host[J];
+    for (int I = 0; I < nd; ++I) K[I * nd + J] = st.sig[I];
+    const int status = load_status(st);
+    if (rep) rep[J] = hm_report{st.iters, status, st.err, st.err0, secs};
+    worst = std::max(worst, status);
+  }
+  return worst;
+}
+
 int hm_effective_tensor_batch(const hm_problem* problems, int n_problems, const hm_solve_opts* opts,
                               double* C_mandel, hm_report* rep, void* stream) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -1290,7 +1432,7 @@ int hm_effective_tensor_batch(const hm_problem* problems, int n_problems, const 
     const int k = unit_loads(d0.grid.dim, E, &idx);
     const int nl = k * (int)g.probs.size();
     if (nl > kMaxLoads) return fail(HM_E_ARG, "more than %d load cases on one grid", kMaxLoads);
-    if ((rc = get_plan(opts->prec == HM_FP64, d0.grid.n, d0.grid.dim, nl, &g.p))) return rc;
+    if ((rc = get_plan(opts->prec == HM_FP64, d0.grid.n, d0.grid.dim, nl, false, &g.p))) return rc;
     g.loads.resize(nl);
     for (int j = 0; j < (int)g.probs.size(); ++j)
       for (int J = 0; J < k; ++J) {

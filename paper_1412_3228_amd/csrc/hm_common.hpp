@@ -43,7 +43,10 @@ struct SolverState {
   double sig[6];  // <sigma> of the last evaluated (or reported) iterate
 };
 
-// Material of one problem (cell) of a solve.
+// Material of one problem (cell) of a solve.  A conduction solve keeps the
+// phase conductivities in pl (pm unused) and the reference conductivity k0
+// in rl (rm = 0); its table rows are (a - k0, b, 0, 0, 0, n0, n1, n2) for
+// the filtered tensor k~ = a I + b n (x) n.
 struct ProblemParams {
   double pl[2], pm[2];  // phase Lame parameters (0: matrix, 1: inclusion)
   double rl, rm;        // reference medium
@@ -58,14 +61,16 @@ struct ProblemParams {
   // holds the voxel's filtered stiffness.
   const int* mid;
   const void* coef;
-  // c~ - c0 of the two pure phases as (a1 - lambda0, a2 - 2 mu0) pairs,
+  // c~ - c0 of the two pure phases as (a1 - lambda0, a2 - 2 mu0) pairs
+  // (conduction: (k - k0, 0)),
   // matrix then inclusion, rounded the way the working precision computes
   // them: in single precision from single-precision inputs, or in double
   float pure_f[4];
   double pure_d[4];
 };
 
-// One load case: its macroscopic strain (tensor components) and problem.
+// One load case: its macroscopic strain (tensor components) and problem;
+// a conduction load keeps its mean gradient G in E[0..2] (E[3..5] = 0).
 struct LoadParams {
   double E[6];
   int prob;
@@ -97,6 +102,8 @@ struct CgState {
 };
 
 struct SolveArgs {
+  // elastic solves hold six components per load, conduction solves three
+  // (the gradient), and one traction-history component instead of three
   void* spec;       // cx<T>[n_load][6][nz][ny][Hp]  x-spectrum / full spectrum
   const void* spec_in;  // x-sweep input (spec itself, or the CG direction)
   void* hist;       // cx<T>[n_load][3][nz][ny][Hp]  previous projected traction
@@ -123,6 +130,7 @@ struct SolveArgs {
   void* cgp;
   CgState* cgs;      // [n_load]
   double* cgpart;    // [n_load][cg_blocks]
+  int cond;          // 1: conduction (3 gradient components), 0: elasticity
 };
 
 }  // namespace hm

@@ -61,7 +61,11 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // wavefront through one atomic counter (count[0]); the row order does not
 // affect any result.  count[1] collects the data flags.  Rows at or beyond
 // `cap` are not written; the caller re-runs with a larger table.
-template <typename T>
+// COND: conduction rows (a - k0, b, 0, 0, 0, n) of k~ = a I + b n (x) n,
+// from the phase conductivities in pl: Voigt a = <k>, b = 0; Reuss
+// a = <1/k>^-1, b = 0; 2-layer a = <k>, b = <1/k>^-1 - <k> (layers in
+// parallel along the interface, in series across it).
+template <typename T, bool COND = false>
 __global__ __launch_bounds__(256) void k_material(const SolveParams* prm, int prob, int nx, int ny, int nz, int dim,
                                                   int* mid, T* coef, int cap, int* count) {
   const ProblemParams& P = prm->probs[prob];
@@ -94,7 +98,17 @@ __global__ __launch_bounds__(256) void k_material(const SolveParams* prm, int pr
   }
   Coef<T> c;
   c.n[0] = c.n[1] = c.n[2] = T(0);
-  rule_coefficients<T>(rule, f, pl, pm, c);
+  if constexpr (COND) {
+    const T g = T(1) - f;
+    const T arith = g * pl[0] + f * pl[1];
+    const T harm = T(1) / (g / pl[0] + f / pl[1]);
+    c.a1 = rule == RULE_REUSS ? harm : arith;
+    c.a2 = rule == RULE_LAMINATE ? harm - arith : T(0);
+    c.a3 = c.a4 = c.a5 = T(0);
+    c.aniso = rule == RULE_LAMINATE;
+  } else {
+    rule_coefficients<T>(rule, f, pl, pm, c);
+  }
   if (c.aniso) {
     const int k = P.incl ? P.incl[v] : -1;
     if (k >= P.nsph) atomicOr(&count[1], FLAG_BAD_INCL);
@@ -110,7 +124,7 @@ __global__ __launch_bounds__(256) void k_material(const SolveParams* prm, int pr
   if (row < cap) {
     T* r = coef + (size_t)row * 8;
     r[0] = c.a1 - T(P.rl);
-    r[1] = c.a2 - T(2.0 * P.rm);
+    r[1] = COND ? c.a2 : c.a2 - T(2.0 * P.rm);
     r[2] = c.a3;
     r[3] = c.a4;
     r[4] = c.a5;
@@ -380,8 +394,9 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
 }
 
 // ---------------------------------------------------------------- ysweep --
-// A block owns W adjacent kx columns of one (load, component, z) plane.
-template <typename T, int NY, int W, int NT, int SIGN>
+// A block owns W adjacent kx columns of one (load, component, z) plane;
+// NC components per load (6 strain, or 3 gradient components).
+template <typename T, int NY, int W, int NT, int SIGN, int NC = 6>
 __global__ __launch_bounds__(NT) void k_ysweep(SolveArgs a) {
   constexpr int SL = NY * W;
   constexpr int Q = (SL + NT - 1) / NT;
@@ -389,11 +404,11 @@ __global__ __launch_bounds__(NT) void k_ysweep(SolveArgs a) {
   __shared__ cx<T> s_tw[NY];
   const int tid = threadIdx.x;
   const int z = blockIdx.y;
-  const int load = blockIdx.z / 6, comp = blockIdx.z - 6 * (blockIdx.z / 6);
+  const int load = blockIdx.z / NC, comp = blockIdx.z - NC * (blockIdx.z / NC);
   if (a.state[load].done) return;
   const int H = a.H, Hp = a.Hp;
   const int kx0 = blockIdx.x * W;
-  cx<T>* base = static_cast<cx<T>*>(a.spec) + ((size_t)(load * 6 + comp) * a.nz + z) * (size_t)NY * Hp + kx0;
+  cx<T>* base = static_cast<cx<T>*>(a.spec) + ((size_t)(load * NC + comp) * a.nz + z) * (size_t)NY * Hp + kx0;
   cx<T> r[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -1058,8 +1073,14 @@ __global__ __launch_bounds__(NT) void k_finalize(SolveArgs a) {
   const double* E = LP.E;
   const double trE = E[0] + E[1] + E[2];
   double sig[6];
+  if (a.cond) {
+    // mean flux <q> = k0 G + <tau>; shear slots stay zero
 #pragma unroll
-  for (int c = 0; c < 6; ++c) sig[c] = tsum[c] / N + (c < 3 ? P.rl * trE : 0.0) + 2.0 * P.rm * E[c];
+    for (int c = 0; c < 6; ++c) sig[c] = c < 3 ? tsum[c] / N + P.rl * E[c] : 0.0;
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sig[c] = tsum[c] / N + (c < 3 ? P.rl * trE : 0.0) + 2.0 * P.rm * E[c];
+  }
   const double fro = sqrt(sig[0] * sig[0] + sig[1] * sig[1] + sig[2] * sig[2] +
                           2.0 * (sig[3] * sig[3] + sig[4] * sig[4] + sig[5] * sig[5]));
   const double den = N * fro;

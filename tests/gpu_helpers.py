@@ -33,3 +33,21 @@ def rel(a, b):
 
 def log(msg):
     print(msg, flush=True)
+
+
+def band_oracle_filter(w, margin=2.0):
+    """Oracle counts on the voxels near the single sphere's surface; pure elsewhere."""
+    vox = ofilter.all_voxels(w.n)
+    c = w.spheres[0, :3]
+    R = w.spheres[0, 3]
+    d = np.linalg.norm(vox + 0.5 - c, axis=1)
+    near = np.abs(d - R) <= w.radius_vox + margin
+    cnt = np.where(d < R, 1, 0).astype(np.int64)
+    M = ofilter.stencil_offsets(w.radius_vox, w.subsamples, w.dim).shape[0]
+    cnt *= M
+    cb, M2 = ofilter.counts_at(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, vox[near])
+    assert M2 == M
+    cnt[near] = cb
+    frac = cnt.astype(np.float64) / np.float64(M)
+    incl = np.where((cnt > 0) & (cnt < M), 0, -1)
+    return cnt, frac, incl, M

@@ -19,7 +19,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import log, oracle_fields_to_comps, rel
+from gpu_helpers import band_oracle_filter, log, oracle_fields_to_comps, rel
 from oracle import filter as ofilter, rules as orules, solver as osolver
 from workloads import target_perturbation, workload_c2, workload_c3, workload_c5
 
@@ -34,28 +34,10 @@ def hm():
     return hm_mod
 
 
-def _band_oracle_filter(w, margin=2.0):
-    """Oracle counts on the voxels near the single sphere's surface; pure elsewhere."""
-    vox = ofilter.all_voxels(w.n)
-    c = w.spheres[0, :3]
-    R = w.spheres[0, 3]
-    d = np.linalg.norm(vox + 0.5 - c, axis=1)
-    near = np.abs(d - R) <= w.radius_vox + margin
-    cnt = np.where(d < R, 1, 0).astype(np.int64)
-    M = ofilter.stencil_offsets(w.radius_vox, w.subsamples, w.dim).shape[0]
-    cnt *= M
-    cb, M2 = ofilter.counts_at(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, vox[near])
-    assert M2 == M
-    cnt[near] = cb
-    frac = cnt.astype(np.float64) / np.float64(M)
-    incl = np.where((cnt > 0) & (cnt < M), 0, -1)
-    return cnt, frac, incl, M
-
-
 def test_c2_full_size_filter_and_iteration(hm):
     w = workload_c2(100.0)
     log("c2 full size: oracle band filter")
-    cnt_o, frac_o, incl_o, M = _band_oracle_filter(w)
+    cnt_o, frac_o, incl_o, M = band_oracle_filter(w)
     cnt, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", DEV)
     assert np.array_equal(cnt.cpu().numpy(), cnt_o)
     assert np.array_equal(frac.cpu().numpy(), frac_o)
