@@ -43,7 +43,8 @@ METRIC = "voxel-iterations/s of LS fixed point, mixed vs FP64 at equal C_eff err
 CONTRASTS = (100.0, 0.01)
 
 
-KERNEL_SOURCES = ("hm_solve_kernels.hpp", "hm_fft.hpp", "hm_material.hpp", "hm_common.hpp")
+KERNEL_SOURCES = ("hm_solve_kernels.hpp", "hm_conduct_kernels.hpp", "hm_fft.hpp", "hm_material.hpp",
+                  "hm_common.hpp")
 PROFILE_GLOB = os.path.join(ROOT, "profiles", "hbm_traffic_*.txt")
 
 
@@ -84,7 +85,8 @@ def summarize(trace_dir, fetch_dir, write_dir, out):
     cal_w = [v for k, vs in wk.items() if "copyBuffer" in k for v in vs if v > 1e5]
     sf = calib / 1024.0 / (sum(cal_f) / len(cal_f))
     sw = calib / 1024.0 / (sum(cal_w) / len(cal_w))
-    lines = ["# rocprofv3 summary: solver sweeps, centred-sphere 125^3 cell, 6 load cases",
+    lines = ["# rocprofv3 summary: solver sweeps, centred-sphere 125^3 cell (elastic: 6 load cases; "
+             "conduction: 3 load cases)",
              "# commands (run from /tmp with TMPDIR=/tmp, repository at $R, output under $OUT):",
              "#   rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/trace -o kp -- "
              "python3 -u $R/bench.py --kernel-pass",
@@ -133,27 +135,28 @@ def _sync():
     torch.cuda.synchronize()
 
 
-def kernel_bytes(n, prec, kernel, n_frac=0):
+def kernel_bytes(n, prec, kernel, n_frac=0, nc=6, nh=3):
     """Algorithmic HBM bytes of one launch of `kernel` for ONE load case.
 
-    The stored state is the x-half-spectrum: 6 components x nz x ny x H
-    complex values (H = (nx + 1) / 2).  xsweep reads and writes it and reads
-    the material: a 4-byte id per voxel and, for each of the n_frac
-    fractional voxels, its 8-real row of the stiffness table; each ysweep
-    reads and writes the spectrum; zsweep also reads and writes the
-    3-component traction history.
+    The stored state is the x-half-spectrum: nc components (6 strain, or 3
+    gradient components for conduction) x nz x ny x H complex values
+    (H = (nx + 1) / 2).  xsweep reads and writes it and reads the material:
+    a 4-byte id per voxel and, for each of the n_frac fractional voxels, its
+    8-real row of the material table; each ysweep reads and writes the
+    spectrum; zsweep also reads and writes the nh-component history
+    (3 traction components, or 1 for conduction).
     """
     nx, ny, nz = n
     H = (nx + 1) // 2
     cb = 16 if prec == "fp64" else 8
     plane = nz * ny * H
-    spec = 2 * 6 * plane * cb
+    spec = 2 * nc * plane * cb
     if kernel == "xsweep":
         return spec + nx * ny * nz * 4 + n_frac * 8 * (cb // 2)
     if kernel in ("ysweep_fwd", "ysweep_inv"):
         return spec
     if kernel == "zsweep":
-        return spec + 2 * 3 * plane * cb
+        return spec + 2 * nh * plane * cb
     return 0
 
 
@@ -179,7 +182,7 @@ def run_path(hm, w, prec, contrast, dev, profile=True, C_target=None, max_iter=5
             "dLdphase": dph}
 
 
-def roofline(timings, n, prec, reports, n_frac=0):
+def roofline(timings, n, prec, reports, n_frac=0, nc=6, nh=3, n_load=6):
     """Dominant kernel of the profiled solves, its algorithmic bandwidth vs peak."""
     tot = {}
     for t in timings:
@@ -190,12 +193,12 @@ def roofline(timings, n, prec, reports, n_frac=0):
     its = sum(t["iterations"] for t in timings)
     active = sum(sum(r["iters"] + 1 for r in rep) for rep in reports) / max(1, its)
     ms = tot[dom] / its
-    bytes_launch = kernel_bytes(n, prec, dom, n_frac) * active
+    bytes_launch = kernel_bytes(n, prec, dom, n_frac, nc, nh) * active
     achieved = bytes_launch / (ms * 1e-3) / 1e9
     key = timings[-1]["kernels"][dom]
     tr = measured_traffic(key)
     # the counters were taken with all load cases active: scale to the average active count
-    traffic = None if tr is None else tr["bytes"] * active / 6.0
+    traffic = None if tr is None else tr["bytes"] * active / n_load
     return {"kernel": dom, "instance": key, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_source": None if tr is None else tr["file"], "ms_per_launch": ms,
@@ -230,6 +233,66 @@ def time_to_solution(hm, works, ref, dev):
         out[str(c)] = row
         del frac, incl
     return out
+
+
+def conduction(hm, works, dev, n_frac):
+    """The conduction form of the solve on the same cells (phase
+    conductivities 1 and the contrast, same 2-layer filter, the 3 unit
+    gradients batched, tol 1e-4): profiled solves per path, voxel-iterations
+    per second and the roofline of the dominant sweep.  Untimed context
+    beside the metric."""
+    out = {}
+    for prec in ("fp64", "mixed"):
+        vit, secs, timings, reps, K = 0, 0.0, [], [], {}
+        for c, w in works.items():
+            k = (1.0, c)
+            _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, prec, dev)
+            kw = dict(prec=prec, tol=w.tol, max_iter=5000, check_every=16, stall_window=(20 if prec == "mixed" else 0))
+            hm.hm_effective_conductivity(w.n, w.dim, k, w.rule, frac, incl, w.spheres, **kw)  # plan warm
+            _sync()
+            t0 = time.perf_counter()
+            o = hm.hm_effective_conductivity(w.n, w.dim, k, w.rule, frac, incl, w.spheres, profile=True, **kw)
+            _sync()
+            secs += time.perf_counter() - t0
+            vit += sum(r["iters"] + 1 for r in o["reports"]) * w.nvox
+            timings.append(hm.last_timing())
+            reps.append(o["reports"])
+            K[str(c)] = {"K_diag": [float(v) for v in np.diag(o["K"])],
+                         "iters": [r["iters"] for r in o["reports"]],
+                         "status": [r["status"] for r in o["reports"]]}
+            del frac, incl
+        n = next(iter(works.values())).n
+        out[prec] = {"value": vit / secs, "unit": "voxel-iterations/s", "seconds": secs, "solves": K,
+                     "roofline": roofline(timings, n, prec, reps, n_frac, nc=3, nh=1, n_load=3)}
+    return out
+
+
+def conduction_cpu_baseline(iters=1):
+    """The conduction oracle timed on a bounded sample: iterations of one
+    unit gradient on the full 125^3 cell, FP64."""
+    from oracle import filter as ofilter, thermal as othermal
+    from workloads import workload_c2
+    w = workload_c2(CONTRASTS[0])
+    vox = ofilter.all_voxels(w.n)
+    d = np.linalg.norm(vox + 0.5 - w.spheres[0, :3], axis=1)
+    R = w.spheres[0, 3]
+    band = np.abs(d - R) <= w.radius_vox + 2.0
+    frac = (d < R).astype(np.float64)
+    cnt, M = ofilter.counts_at(w.n, 3, w.spheres, w.radius_vox, w.subsamples, vox[band])
+    frac[band] = cnt / M
+    incl = np.where((frac > 0) & (frac < 1), 0, -1)
+    nrm = ofilter.interface_normals(w.n, 3, w.spheres, incl, vox)
+    k = (1.0, CONTRASTS[0])
+    fld = othermal.ConductivityField(w.n, 3, k, w.rule, frac, nrm)
+    w0, c0t = time.perf_counter(), time.process_time()
+    r = othermal.solve(fld, [1.0, 0.0, 0.0], othermal.reference_conductivity(k), 0.0, iters)
+    wall = time.perf_counter() - w0
+    cpu = time.process_time() - c0t
+    evals = r["iters"] + 1
+    return {"value": evals * w.nvox / wall, "unit": "voxel-iterations/s", "cores": max(1, int(round(cpu / wall))),
+            "kind": "oracle",
+            "sample": "%d conduction fixed-point iterations of one unit gradient (contrast 100) on the full 125^3 "
+                      "grid, FP64; %.1f s wall" % (evals, wall)}
 
 
 def cpu_baseline(iters=1):
@@ -296,6 +359,10 @@ def main():
                                    max_iter=9, check_every=10, profile=True)
             t = hm.last_timing()
             print(json.dumps({"kernel_pass": prec, "timing": t}), flush=True)
+            hm.hm_effective_conductivity(w.n, w.dim, (1.0, CONTRASTS[0]), w.rule, frac, incl, w.spheres, prec=prec,
+                                         tol=0.0, max_iter=9, check_every=10, profile=True)
+            t = hm.last_timing()
+            print(json.dumps({"kernel_pass": "conduction " + prec, "timing": t}), flush=True)
         # calibration copy of a known size for the rocprofv3 byte counters
         x = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
         y = torch.empty_like(x)
@@ -381,8 +448,10 @@ def main():
         "cpu_baseline": None,
     }
     line["time_to_solution"] = time_to_solution(hm, works, ref, dev)
+    line["conduction"] = conduction(hm, works, dev, n_frac)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
+        line["conduction"]["cpu_baseline"] = conduction_cpu_baseline(iters=8)
     print(json.dumps(line), flush=True)
 
 
