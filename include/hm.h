@@ -331,6 +331,45 @@ int hm_solve_adjoint(const hm_grid* grid, const hm_iso phases[2], hm_rule rule,
                      const double* dLdC, const void* d_eps, int n_load,
                      double* dLdphase, void* d_dLdfrac, void* stream);
 
+/*
+ * hm_fourier_series - the truncated Fourier series of a grid field,
+ * evaluated on a finer grid (the extrapolated material properties of
+ * Figure 4, Section 6).
+ *
+ * With the grid points at the voxel centres (a + 1/2) / n[d] of the unit
+ * cell and the odd frequency set J of Section 2, the series
+ * F(y) = sum_{a in J} c^(a) exp(2 pi i a . y), with c^ the normalised DFT
+ * coefficients of the field, is real and equals the field at the grid
+ * points; it is evaluated at the voxel centres (b + 1/2) / m[d] of an
+ * m[0] x m[1] x m[2] grid (any m; odd multiples of n contain the grid
+ * points).  Computed as three axis contractions with Dirichlet-kernel
+ * matrices D_n(t) = sin(pi n t) / (n sin(pi t)), which is the same sum.
+ *
+ * Inputs:  grid (n[d] odd, 1..243, any odd value; n[2] = 1 in 2D),
+ *          m (host, 3 ints in 1..4096, m[2] = 1 in 2D, at most 2^32
+ *          points), d_field (device, n[0]*n[1]*n[2] reals [z][y][x],
+ *          double for HM_FP64, float for HM_MIXED).
+ * Output:  d_out (device, m[0]*m[1]*m[2] reals of the same type,
+ *          [z][y][x]).  The call allocates its own temporaries and
+ *          returns after the result is written.
+ */
+int hm_fourier_series(const hm_grid* grid, const int m[3], hm_prec prec,
+                      const void* d_field, void* d_out, void* stream);
+
+/*
+ * hm_stiffness_component - Mandel entry (I, J) of the filtered stiffness
+ * c~(x_a) at every voxel (Section 2, eqs. 3-5 as in hm_solve: the phase
+ * tensor where f is 0 or 1, else the rule at f with the interface normal
+ * of d_incl), evaluated in double and stored in the precision of `prec`:
+ * the per-voxel property field that Figure 4 extrapolates.
+ * Inputs as hm_solve; I, J in 0..5 (Mandel order 11, 22, 33, 23, 13, 12).
+ * Output: d_out (device, N reals [z][y][x]).  HM_E_DATA as hm_solve.
+ */
+int hm_stiffness_component(const hm_grid* grid, const hm_iso phases[2], hm_rule rule,
+                           const void* d_frac, const int32_t* d_incl,
+                           const hm_sphere* spheres, int n_spheres, hm_prec prec,
+                           int I, int J, void* d_out, void* stream);
+
 /* Timing of the calling thread's last solve run with opts->profile set.
  * Returns HM_E_ARG when there is none. */
 int hm_last_timing(hm_timing* out);

@@ -13,8 +13,10 @@ from .api import (  # noqa: F401
     hm_effective_tensor,
     hm_effective_tensor_batch,
     hm_filter,
+    hm_fourier_series,
     hm_solve,
     hm_solve_adjoint,
+    hm_stiffness_component,
     last_timing,
     release_plans,
     schedule_count,

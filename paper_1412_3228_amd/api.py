@@ -212,6 +212,35 @@ def hm_effective_conductivity(n, dim, k, rule: str, frac: torch.Tensor, incl: Op
     return {"status": rc, "K": K, "reports": _reports(rep, nd), "grad": grad}
 
 
+def hm_fourier_series(n, dim, field: torch.Tensor, m, prec: str = "fp64"):
+    """Truncated Fourier series of a grid field on the voxel centres of an m grid, (m_z, m_y, m_x)."""
+    dev = field.device
+    N = int(n[0] * n[1] * n[2])
+    _check_field(field, N, _DT[prec], dev, "field")
+    mm = (ctypes.c_int * 3)(*(int(v) for v in m))
+    out = torch.empty((int(m[2]), int(m[1]), int(m[0])), dtype=_DT[prec], device=dev)
+    g = _grid(n, dim)
+    rc = _lib().hm_fourier_series(ctypes.byref(g), mm, L.PRECS[prec], _ptr(field), _ptr(out), _stream(dev))
+    L.check(rc)
+    return out
+
+
+def hm_stiffness_component(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres,
+                           I: int, J: int, prec: str = "fp64"):
+    """Mandel entry (I, J) of the filtered stiffness at every voxel (N reals)."""
+    dev = frac.device
+    N = int(n[0] * n[1] * n[2])
+    _check_field(frac, N, _DT[prec], dev, "frac")
+    _check_field(incl, N, torch.int32, dev, "incl")
+    out = torch.empty(N, dtype=_DT[prec], device=dev)
+    g = _grid(n, dim)
+    sph, ns = _spheres(spheres)
+    rc = _lib().hm_stiffness_component(ctypes.byref(g), _phases(phases), L.RULES[rule], _ptr(frac), _ptr(incl),
+                                       sph, ns, L.PRECS[prec], int(I), int(J), _ptr(out), _stream(dev))
+    L.check(rc)
+    return out
+
+
 def hm_effective_tensor_batch(problems, prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000,
                               c0_alpha: float = 1.0, check_every: int = 16, stall_window: int = 0,
                               use_graph: bool = True, autotune: bool = True):

@@ -26,6 +26,7 @@
 #include "hm_adjoint.hpp"
 #include "hm_filter.hpp"
 #include "hm_conduct_kernels.hpp"
+#include "hm_extrapolate.hpp"
 #include "hm_solve_kernels.hpp"
 
 namespace hm {
@@ -1170,9 +1171,155 @@ ProblemIn make_problem(const hm_grid* grid, const hm_iso phases[2], hm_rule rule
   return d;
 }
 
+// Dirichlet kernel matrix K[b][a] = D_n((b + 1/2)/m - (a + 1/2)/n) with
+// D_n(t) = sin(pi n t) / (n sin(pi t)) (1 at integer t): with
+// p = (2b + 1) n - (2a + 1) m, t = p / (2 m n), so both sines take
+// rational multiples of pi whose arguments are reduced exactly in integers
+// before a long double evaluation; entries are exactly 1 or 0 where the
+// fine point meets a grid point.
+std::vector<double> dirichlet_matrix(int n, int m) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  std::vector<double> K((size_t)m * n);
+  const long long q1 = 2LL * m, q2 = 2LL * m * n;
+  for (int b = 0; b < m; ++b)
+    for (int a = 0; a < n; ++a) {
+      const long long p = (2LL * b + 1) * n - (2LL * a + 1) * m;
+      double v;
+      if (p % q2 == 0) {
+        v = 1.0;
+      } else if (p % q1 == 0) {
+        v = 0.0;
+      } else {
+        const long long r1 = ((p % (2 * q1)) + 2 * q1) % (2 * q1);
+        const long long r2 = ((p % (2 * q2)) + 2 * q2) % (2 * q2);
+        v = (double)(sinl(pi * (long double)r1 / (long double)q1) /
+                     ((long double)n * sinl(pi * (long double)r2 / (long double)q2)));
+      }
+      K[(size_t)b * n + a] = v;
+    }
+  return K;
+}
+
+// Uploads a matrix (row-major, or transposed) in the working precision.
+int upload_matrix(const std::vector<double>& K, int rows, int cols, bool transpose, bool fp64, void** out) {
+  const size_t cnt = (size_t)rows * cols;
+  int rc = device_alloc(out, cnt * (fp64 ? 8 : 4), "series matrix");
+  if (rc) return rc;
+  std::vector<double> d(cnt);
+  for (int r = 0; r < rows; ++r)
+    for (int c = 0; c < cols; ++c) d[transpose ? (size_t)c * rows + r : (size_t)r * cols + c] = K[(size_t)r * cols + c];
+  hipError_t e;
+  if (fp64) {
+    e = hipMemcpy(*out, d.data(), cnt * 8, hipMemcpyHostToDevice);
+  } else {
+    std::vector<float> f(cnt);
+    for (size_t i = 0; i < cnt; ++i) f[i] = (float)d[i];
+    e = hipMemcpy(*out, f.data(), cnt * 4, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return fail(HM_E_DEVICE, "series matrix upload: %s", hipGetErrorString(e));
+  return HM_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int hm_fourier_series(const hm_grid* grid, const int m[3], hm_prec prec, const void* d_field, void* d_out,
+                      void* stream) {
+  if (!grid || !m) return fail(HM_E_ARG, "grid and m must not be NULL");
+  if (grid->dim != 2 && grid->dim != 3) return fail(HM_E_ARG, "dim must be 2 or 3 (got %d)", grid->dim);
+  if (prec != HM_FP64 && prec != HM_MIXED) return fail(HM_E_ARG, "unknown precision");
+  long long M = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (grid->n[d] < 1 || grid->n[d] > 243 || grid->n[d] % 2 == 0)
+      return fail(HM_E_SIZE, "n[%d] = %d must be odd and <= 243", d, grid->n[d]);
+    if (m[d] < 1 || m[d] > 4096) return fail(HM_E_SIZE, "m[%d] = %d must be in 1..4096", d, m[d]);
+    M *= m[d];
+  }
+  if (grid->dim == 2 && (grid->n[2] != 1 || m[2] != 1)) return fail(HM_E_ARG, "2D grids need n[2] == m[2] == 1");
+  if (M > (1LL << 32)) return fail(HM_E_SIZE, "output of %lld points is too large", M);
+  if (!d_field || !d_out) return fail(HM_E_ARG, "d_field and d_out must not be NULL");
+  const bool fp64 = prec == HM_FP64;
+  const size_t rb = fp64 ? 8 : 4;
+  const int nx = grid->n[0], ny = grid->n[1], nz = grid->n[2];
+  hipStream_t s = (hipStream_t)stream;
+  void *kx = nullptr, *ky = nullptr, *kz = nullptr, *t1 = nullptr, *t2 = nullptr;
+  int rc = upload_matrix(dirichlet_matrix(nx, m[0]), m[0], nx, true, fp64, &kx);
+  if (!rc) rc = upload_matrix(dirichlet_matrix(ny, m[1]), m[1], ny, false, fp64, &ky);
+  if (!rc) rc = upload_matrix(dirichlet_matrix(nz, m[2]), m[2], nz, false, fp64, &kz);
+  const bool zpass = !(nz == 1 && m[2] == 1);
+  if (!rc) rc = device_alloc(&t1, (size_t)nz * ny * m[0] * rb, "series x pass");
+  if (!rc && zpass) rc = device_alloc(&t2, (size_t)nz * m[1] * m[0] * rb, "series y pass");
+  hipError_t e = hipSuccess;
+  if (!rc) {
+    // x: contiguous lines; y: stride mx; z: stride mx * my
+    AxisPass px{d_field, t1, kx, 1, (long long)ny * nz, nx, m[0]};
+    AxisPass py{t1, zpass ? t2 : d_out, ky, (long long)m[0], (long long)nz, ny, m[1]};
+    AxisPass pz{t2, d_out, kz, (long long)m[0] * m[1], 1, nz, m[2]};
+    e = launch_series_pass(px, fp64, s);
+    if (e == hipSuccess) e = launch_series_pass(py, fp64, s);
+    if (e == hipSuccess && zpass) e = launch_series_pass(pz, fp64, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  for (void* q : {kx, ky, kz, t1, t2}) (void)hipFree(q);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(HM_E_DEVICE, "Fourier series: %s", hipGetErrorString(e));
+  return HM_OK;
+}
+
+int hm_stiffness_component(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,
+                           const int32_t* d_incl, const hm_sphere* spheres, int n_spheres, hm_prec prec, int I,
+                           int J, void* d_out, void* stream) {
+  ProblemIn d = make_problem(grid, phases, rule, d_frac, d_incl, spheres, n_spheres);
+  int rc;
+  if ((rc = check_problem(d))) return rc;
+  if (prec != HM_FP64 && prec != HM_MIXED) return fail(HM_E_ARG, "unknown precision");
+  if (I < 0 || I > 5 || J < 0 || J > 5) return fail(HM_E_ARG, "Mandel indices must be in 0..5");
+  if (!d_out) return fail(HM_E_ARG, "d_out is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  double* dsph = nullptr;
+  int* dflags = nullptr;
+  const size_t sb = (size_t)(n_spheres > 0 ? n_spheres : 1) * 4 * sizeof(double);
+  if ((rc = device_alloc((void**)&dsph, sb, "sphere table"))) return rc;
+  if ((rc = device_alloc((void**)&dflags, sizeof(int), "flags"))) {
+    (void)hipFree(dsph);
+    return rc;
+  }
+  std::vector<double> tab(sb / sizeof(double), 0.0);
+  for (int k = 0; k < n_spheres; ++k) {
+    for (int c = 0; c < 3; ++c) tab[4 * k + c] = spheres[k].c[c];
+    tab[4 * k + 3] = spheres[k].r;
+  }
+  StiffnessArgs a;
+  memset(&a, 0, sizeof a);
+  a.frac = d_frac;
+  a.incl = d_incl;
+  a.sph = dsph;
+  a.nsph = n_spheres;
+  for (int k = 0; k < 3; ++k) a.n[k] = grid->n[k];
+  a.dim = grid->dim;
+  for (int p = 0; p < 2; ++p) {
+    a.pl[p] = phases[p].lambda;
+    a.pm[p] = phases[p].mu;
+  }
+  a.rule = (int)rule;
+  a.I = I;
+  a.J = J;
+  a.out = d_out;
+  a.flags = dflags;
+  int flags = 0;
+  hipError_t e = hipMemcpyAsync(dsph, tab.data(), sb, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(dflags, 0, sizeof(int), s);
+  if (e == hipSuccess) e = launch_stiffness_component(a, prec == HM_FP64, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&flags, dflags, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(dsph);
+  (void)hipFree(dflags);
+  if (e != hipSuccess) return fail(HM_E_DEVICE, "stiffness component: %s", hipGetErrorString(e));
+  if (flags & 1) return fail(HM_E_DATA, "fractional voxel with HM_RULE_NONE");
+  if (flags & 2) return fail(HM_E_DATA, "d_incl holds a sphere index >= n_spheres");
+  return HM_OK;
+}
 
 const char* hm_last_error(void) { return g_last_error.c_str(); }
 

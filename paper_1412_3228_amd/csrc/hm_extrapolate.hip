@@ -1,0 +1,161 @@
+// Post-processing kernels.
+//
+// Truncated Fourier series (Figure 4): on an odd grid the series with the
+// FFT coefficients of a field, evaluated at a point y, is a sum of the grid
+// values weighted by the Dirichlet kernel, separable over the axes:
+//   F(y) = sum_x c(x) prod_d D_(n_d)(y_d - x_d),
+//   D_n(t) = (1/n) sum_{a in J} exp(2 pi i a t) = sin(pi n t) / (n sin(pi t)).
+// On a finer grid of m_d points per axis this is three dense contractions
+// with (m_d x n_d) matrices, one axis at a time: no transform length
+// restrictions on n or m.  The host fills the matrices; each pass here is
+// a blocked matrix product on the vector ALUs (FP64 matrix cores run at
+// the vector rate on this chip, and FP32 ones need no more than the
+// contraction's 2 flops per loaded operand).
+//
+// Stiffness component: the filtered stiffness of Section 2 (eqs. 3-5) at
+// each voxel applied to a unit Mandel strain, one Mandel entry kept.
+#include <math.h>
+
+#include "hm_common.hpp"
+#include "hm_extrapolate.hpp"
+#include "hm_material.hpp"
+
+namespace hm {
+
+constexpr int kPassThreads = 256;
+constexpr int kLinePass = 8;    // lines per block of the contiguous pass
+constexpr int kStridedOut = 16; // outputs per thread of the strided pass
+
+// Contiguous lines (I == 1): a block stages kLinePass input lines in LDS and
+// its threads run along the outputs j'; the matrix is read transposed
+// (Kt[j][j'], so consecutive threads read consecutive entries) and each
+// entry serves all staged lines.
+template <typename T>
+__global__ __launch_bounds__(kPassThreads) void k_series_lines(const T* in, T* out, const T* Kt, long long O,
+                                                               int n, int mj) {
+  extern __shared__ unsigned char smem[];
+  T* rows = reinterpret_cast<T*>(smem);  // [kLinePass][n]
+  const long long o0 = (long long)blockIdx.y * kLinePass;
+  const int jp = blockIdx.x * kPassThreads + threadIdx.x;
+  for (int e = threadIdx.x; e < kLinePass * n; e += kPassThreads) {
+    const int l = e / n, j = e - (e / n) * n;
+    rows[e] = o0 + l < O ? in[(o0 + l) * n + j] : T(0);
+  }
+  __syncthreads();
+  if (jp >= mj) return;
+  T acc[kLinePass];
+#pragma unroll
+  for (int l = 0; l < kLinePass; ++l) acc[l] = T(0);
+  for (int j = 0; j < n; ++j) {
+    const T k = Kt[(size_t)j * mj + jp];
+#pragma unroll
+    for (int l = 0; l < kLinePass; ++l) acc[l] += rows[l * n + j] * k;
+  }
+#pragma unroll
+  for (int l = 0; l < kLinePass; ++l)
+    if (o0 + l < O) out[(o0 + l) * mj + jp] = acc[l];
+}
+
+// Strided axis (I > 1): threads run along i (coalesced), each computes
+// kStridedOut consecutive outputs j' from the block's rows of K in LDS.
+template <typename T>
+__global__ __launch_bounds__(kPassThreads) void k_series_strided(const T* in, T* out, const T* K, long long I,
+                                                                 int n, int mj) {
+  extern __shared__ unsigned char smem[];
+  T* ks = reinterpret_cast<T*>(smem);  // [kStridedOut][n]
+  const long long i = (long long)blockIdx.x * kPassThreads + threadIdx.x;
+  const int j0 = blockIdx.y * kStridedOut;
+  const long long o = blockIdx.z;
+  for (int e = threadIdx.x; e < kStridedOut * n; e += kPassThreads) {
+    const int t = e / n, j = e - (e / n) * n;
+    ks[e] = j0 + t < mj ? K[(size_t)(j0 + t) * n + j] : T(0);
+  }
+  __syncthreads();
+  if (i >= I) return;
+  T acc[kStridedOut];
+#pragma unroll
+  for (int t = 0; t < kStridedOut; ++t) acc[t] = T(0);
+  const T* src = in + (size_t)o * n * I + i;
+  for (int j = 0; j < n; ++j) {
+    const T v = src[(size_t)j * I];
+#pragma unroll
+    for (int t = 0; t < kStridedOut; ++t) acc[t] += ks[t * n + j] * v;
+  }
+  T* dst = out + (size_t)o * mj * I + i;
+#pragma unroll
+  for (int t = 0; t < kStridedOut; ++t)
+    if (j0 + t < mj) dst[(size_t)(j0 + t) * I] = acc[t];
+}
+
+template <typename T> hipError_t series_pass(const AxisPass& p, hipStream_t s) {
+  const T* in = static_cast<const T*>(p.in);
+  T* out = static_cast<T*>(p.out);
+  const T* K = static_cast<const T*>(p.K);
+  if (p.I == 1) {
+    const dim3 grid((unsigned)((p.mj + kPassThreads - 1) / kPassThreads), (unsigned)((p.O + kLinePass - 1) / kLinePass));
+    hipLaunchKernelGGL((k_series_lines<T>), grid, dim3(kPassThreads), (size_t)kLinePass * p.n * sizeof(T), s, in, out,
+                       K, p.O, p.n, p.mj);
+  } else {
+    const dim3 grid((unsigned)((p.I + kPassThreads - 1) / kPassThreads), (unsigned)((p.mj + kStridedOut - 1) / kStridedOut),
+                    (unsigned)p.O);
+    hipLaunchKernelGGL((k_series_strided<T>), grid, dim3(kPassThreads), (size_t)kStridedOut * p.n * sizeof(T), s, in,
+                       out, K, p.I, p.n, p.mj);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_series_pass(const AxisPass& p, bool fp64, hipStream_t s) {
+  return fp64 ? series_pass<double>(p, s) : series_pass<float>(p, s);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_stiffness_component(StiffnessArgs a) {
+  const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (v >= N) return;
+  const double f = (double)static_cast<const T*>(a.frac)[v];
+  Coef<double> c;
+  c.n[0] = c.n[1] = c.n[2] = 0.0;
+  c.a3 = c.a4 = c.a5 = 0.0;
+  c.aniso = false;
+  if (f == 0.0 || f == 1.0) {
+    const int p = f == 0.0 ? 0 : 1;
+    c.a1 = a.pl[p];
+    c.a2 = 2.0 * a.pm[p];
+  } else {
+    int rule = a.rule;
+    if (rule == RULE_NONE) {
+      atomicOr(a.flags, 1);
+      rule = RULE_VOIGT;
+    }
+    rule_coefficients<double>(rule, f, a.pl, a.pm, c);
+    if (c.aniso) {
+      const int k = a.incl ? a.incl[v] : -1;
+      if (k >= a.nsph) atomicOr(a.flags, 2);
+      if (k >= 0 && k < a.nsph) {
+        const int x = (int)(v % a.n[0]), y = (int)((v / a.n[0]) % a.n[1]), z = (int)(v / ((long long)a.n[0] * a.n[1]));
+        interface_normal<double>(a.sph, k, x, y, z, a.n[0], a.n[1], a.n[2], a.dim, c.n);
+      } else {
+        c.n[0] = 1.0;
+      }
+    }
+  }
+  // unit Mandel strain J as tensor components, Mandel entry I of the stress
+  const double r2 = 1.4142135623730950488;
+  double e[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, s6[6];
+  e[a.J] = a.J < 3 ? 1.0 : 1.0 / r2;
+  apply_form<double>(c, e, s6);
+  static_cast<T*>(a.out)[v] = (T)(a.I < 3 ? s6[a.I] : r2 * s6[a.I]);
+}
+
+hipError_t launch_stiffness_component(const StiffnessArgs& a, bool fp64, hipStream_t s) {
+  const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
+  const dim3 grid((unsigned)((N + 255) / 256));
+  if (fp64)
+    hipLaunchKernelGGL((k_stiffness_component<double>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_stiffness_component<float>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace hm

@@ -1,0 +1,42 @@
+// Launch interface of the post-processing kernels: the truncated Fourier
+// series of a grid field on a finer grid (Figure 4) and a Mandel entry of
+// the filtered stiffness per voxel (the field that figure extrapolates).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hm {
+
+// One separable pass of the series: out[o][j'][i] = sum_j K[j'][j] in[o][j][i]
+// (i contiguous, extent I; j contracted, extent n; j' extent mj; o extent O).
+// K is row-major (mj x n).  When I == 1 the pass runs along contiguous lines.
+struct AxisPass {
+  const void* in;
+  void* out;
+  const void* K;
+  long long I, O;
+  int n, mj;
+};
+
+hipError_t launch_series_pass(const AxisPass& p, bool fp64, hipStream_t s);
+
+// Mandel entry (I, J) of c~ at every voxel (rule of eqs. 3-5, pure phases
+// where f is 0 or 1); flags[0] gets 1 for a fractional voxel under the
+// no-filter rule, 2 for an interface sphere index out of range.
+struct StiffnessArgs {
+  const void* frac;
+  const int* incl;
+  const double* sph;  // [nsph][4]
+  int nsph;
+  int n[3];
+  int dim;
+  double pl[2], pm[2];
+  int rule;
+  int I, J;
+  void* out;
+  int* flags;
+};
+
+hipError_t launch_stiffness_component(const StiffnessArgs& a, bool fp64, hipStream_t s);
+
+}  // namespace hm
