@@ -39,6 +39,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFS = 78.6
 METRIC = "voxel-iterations/s of LS fixed point, mixed vs FP64 at equal C_eff error; %HBM peak"
 CONTRASTS = (100.0, 0.01)
 
@@ -267,6 +268,42 @@ def conduction(hm, works, dev, n_frac):
     return out
 
 
+def series_flops(n, m):
+    """Multiply-adds x 2 of the three axis contractions of hm_fourier_series."""
+    nx, ny, nz = n
+    mx, my, mz = m
+    return 2.0 * (ny * nz * nx * mx + nz * mx * ny * my + mx * my * nz * mz)
+
+
+def series(hm, w, dev, m=(375, 375, 375)):
+    """Figure 4's extrapolation on the benchmark cell: the 2-layer-filtered
+    C_11 field (125^3, FP64) as a truncated Fourier series on a 3x finer
+    grid.  Device time of the call from events on its stream; the bound is
+    the FP64 vector ALU (the contractions do 2 flops per loaded operand
+    from LDS or L2, far above the HBM balance point)."""
+    import torch
+    _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", dev)
+    c11 = hm.hm_stiffness_component(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, 0, 0)
+    out = hm.hm_fourier_series(w.n, 3, c11, m)  # warm
+    del out
+    ms = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = hm.hm_fourier_series(w.n, 3, c11, m)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+        del out
+    t = min(ms)
+    fl = series_flops(w.n, m)
+    achieved = fl / (t * 1e-3) / 1e12
+    return {"grid": list(w.n), "fine_grid": list(m), "ms_per_call": t, "flops": fl,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFS, "unit": "TFLOP/s",
+                         "frac": achieved / FP64_VALU_PEAK_TFS, "traffic": None,
+                         "note": "whole call (three passes and three matrix uploads of <400 KB each)"}}
+
+
 def conduction_cpu_baseline(iters=1):
     """The conduction oracle timed on a bounded sample: iterations of one
     unit gradient on the full 125^3 cell, FP64."""
@@ -363,6 +400,12 @@ def main():
                                          tol=0.0, max_iter=9, check_every=10, profile=True)
             t = hm.last_timing()
             print(json.dumps({"kernel_pass": "conduction " + prec, "timing": t}), flush=True)
+        w = works[CONTRASTS[0]]
+        _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", dev)
+        c11 = hm.hm_stiffness_component(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, 0, 0)
+        for _ in range(3):
+            hm.hm_fourier_series(w.n, 3, c11, (375, 375, 375))
+        print(json.dumps({"kernel_pass": "fourier series 125^3 -> 375^3"}), flush=True)
         # calibration copy of a known size for the rocprofv3 byte counters
         x = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
         y = torch.empty_like(x)
@@ -449,6 +492,7 @@ def main():
     }
     line["time_to_solution"] = time_to_solution(hm, works, ref, dev)
     line["conduction"] = conduction(hm, works, dev, n_frac)
+    line["fourier_series"] = series(hm, works[CONTRASTS[0]], dev)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
         line["conduction"]["cpu_baseline"] = conduction_cpu_baseline(iters=8)

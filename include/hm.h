@@ -350,8 +350,10 @@ int hm_solve_adjoint(const hm_grid* grid, const hm_iso phases[2], hm_rule rule,
  *          points), d_field (device, n[0]*n[1]*n[2] reals [z][y][x],
  *          double for HM_FP64, float for HM_MIXED).
  * Output:  d_out (device, m[0]*m[1]*m[2] reals of the same type,
- *          [z][y][x]).  The call allocates its own temporaries and
- *          returns after the result is written.
+ *          [z][y][x]).  The call returns once the work is queued on
+ *          `stream`; the Dirichlet matrices and two temporaries of each
+ *          (n, m, precision) are kept until hm_release_plans, so calls with
+ *          the same sizes on one stream must not overlap.
  */
 int hm_fourier_series(const hm_grid* grid, const int m[3], hm_prec prec,
                       const void* d_field, void* d_out, void* stream);

@@ -1200,6 +1200,20 @@ std::vector<double> dirichlet_matrix(int n, int m) {
   return K;
 }
 
+// Matrices and temporaries of one (device, precision, n, m) series, kept
+// until hm_release_plans.
+struct SeriesPlan {
+  void* k[3] = {nullptr, nullptr, nullptr};  // x transposed, y, z
+  void* t1 = nullptr;                        // after the x pass
+  void* t2 = nullptr;                        // after the y pass (3D)
+};
+std::map<std::tuple<int, bool, int, int, int, int, int, int>, SeriesPlan*> g_series;
+
+void free_series(SeriesPlan* q) {
+  for (void* v : {q->k[0], q->k[1], q->k[2], q->t1, q->t2}) (void)hipFree(v);
+  delete q;
+}
+
 // Uploads a matrix (row-major, or transposed) in the working precision.
 int upload_matrix(const std::vector<double>& K, int rows, int cols, bool transpose, bool fp64, void** out) {
   const size_t cnt = (size_t)rows * cols;
@@ -1242,27 +1256,38 @@ int hm_fourier_series(const hm_grid* grid, const int m[3], hm_prec prec, const v
   const bool fp64 = prec == HM_FP64;
   const size_t rb = fp64 ? 8 : 4;
   const int nx = grid->n[0], ny = grid->n[1], nz = grid->n[2];
-  hipStream_t s = (hipStream_t)stream;
-  void *kx = nullptr, *ky = nullptr, *kz = nullptr, *t1 = nullptr, *t2 = nullptr;
-  int rc = upload_matrix(dirichlet_matrix(nx, m[0]), m[0], nx, true, fp64, &kx);
-  if (!rc) rc = upload_matrix(dirichlet_matrix(ny, m[1]), m[1], ny, false, fp64, &ky);
-  if (!rc) rc = upload_matrix(dirichlet_matrix(nz, m[2]), m[2], nz, false, fp64, &kz);
   const bool zpass = !(nz == 1 && m[2] == 1);
-  if (!rc) rc = device_alloc(&t1, (size_t)nz * ny * m[0] * rb, "series x pass");
-  if (!rc && zpass) rc = device_alloc(&t2, (size_t)nz * m[1] * m[0] * rb, "series y pass");
-  hipError_t e = hipSuccess;
-  if (!rc) {
-    // x: contiguous lines; y: stride mx; z: stride mx * my
-    AxisPass px{d_field, t1, kx, 1, (long long)ny * nz, nx, m[0]};
-    AxisPass py{t1, zpass ? t2 : d_out, ky, (long long)m[0], (long long)nz, ny, m[1]};
-    AxisPass pz{t2, d_out, kz, (long long)m[0] * m[1], 1, nz, m[2]};
-    e = launch_series_pass(px, fp64, s);
-    if (e == hipSuccess) e = launch_series_pass(py, fp64, s);
-    if (e == hipSuccess && zpass) e = launch_series_pass(pz, fp64, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  HM_HIP(hipGetDevice(&dev));
+  SeriesPlan* q = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    const auto key = std::make_tuple(dev, fp64, nx, ny, nz, m[0], m[1], m[2]);
+    auto it = g_series.find(key);
+    if (it != g_series.end()) {
+      q = it->second;
+    } else {
+      q = new SeriesPlan();
+      int rc = upload_matrix(dirichlet_matrix(nx, m[0]), m[0], nx, true, fp64, &q->k[0]);
+      if (!rc) rc = upload_matrix(dirichlet_matrix(ny, m[1]), m[1], ny, false, fp64, &q->k[1]);
+      if (!rc) rc = upload_matrix(dirichlet_matrix(nz, m[2]), m[2], nz, false, fp64, &q->k[2]);
+      if (!rc) rc = device_alloc(&q->t1, (size_t)nz * ny * m[0] * rb, "series x pass");
+      if (!rc && zpass) rc = device_alloc(&q->t2, (size_t)nz * m[1] * m[0] * rb, "series y pass");
+      if (rc) {
+        free_series(q);
+        return rc;
+      }
+      g_series[key] = q;
+    }
   }
-  for (void* q : {kx, ky, kz, t1, t2}) (void)hipFree(q);
-  if (rc) return rc;
+  // x: contiguous lines; y: stride mx; z: stride mx * my
+  AxisPass px{d_field, q->t1, q->k[0], 1, (long long)ny * nz, nx, m[0]};
+  AxisPass py{q->t1, zpass ? q->t2 : d_out, q->k[1], (long long)m[0], (long long)nz, ny, m[1]};
+  AxisPass pz{q->t2, d_out, q->k[2], (long long)m[0] * m[1], 1, nz, m[2]};
+  hipError_t e = launch_series_pass(px, fp64, s);
+  if (e == hipSuccess) e = launch_series_pass(py, fp64, s);
+  if (e == hipSuccess && zpass) e = launch_series_pass(pz, fp64, s);
   if (e != hipSuccess) return fail(HM_E_DEVICE, "Fourier series: %s", hipGetErrorString(e));
   return HM_OK;
 }
@@ -1362,6 +1387,8 @@ void hm_release_plans(void) {
   std::lock_guard<std::mutex> lock(g_mutex);
   for (auto& kv : g_plans) free_plan(kv.second);
   g_plans.clear();
+  for (auto& kv : g_series) free_series(kv.second);
+  g_series.clear();
 }
 
 int hm_filter(const hm_grid* grid, const hm_sphere* spheres, int n_spheres, double radius_vox, int subsamples,

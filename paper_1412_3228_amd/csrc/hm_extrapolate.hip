@@ -24,7 +24,7 @@ namespace hm {
 
 constexpr int kPassThreads = 256;
 constexpr int kLinePass = 8;    // lines per block of the contiguous pass
-constexpr int kStridedOut = 16; // outputs per thread of the strided pass
+constexpr int kStridedOut = 32; // outputs per thread of the strided pass
 
 // Contiguous lines (I == 1): a block stages kLinePass input lines in LDS and
 // its threads run along the outputs j'; the matrix is read transposed
@@ -57,29 +57,30 @@ __global__ __launch_bounds__(kPassThreads) void k_series_lines(const T* in, T* o
 }
 
 // Strided axis (I > 1): threads run along i (coalesced), each computes
-// kStridedOut consecutive outputs j' from the block's rows of K in LDS.
+// kStridedOut consecutive outputs j'.  The matrix entries are the same for
+// every thread of the block, so they are read through the scalar cache
+// (read-only, no aliasing) and each loaded input value feeds kStridedOut
+// multiply-adds; the input is re-read once per block of outputs.
 template <typename T>
-__global__ __launch_bounds__(kPassThreads) void k_series_strided(const T* in, T* out, const T* K, long long I,
-                                                                 int n, int mj) {
-  extern __shared__ unsigned char smem[];
-  T* ks = reinterpret_cast<T*>(smem);  // [kStridedOut][n]
+__global__ __launch_bounds__(kPassThreads) void k_series_strided(const T* __restrict__ in, T* __restrict__ out,
+                                                                 const T* __restrict__ K, long long I, int n,
+                                                                 int mj) {
   const long long i = (long long)blockIdx.x * kPassThreads + threadIdx.x;
   const int j0 = blockIdx.y * kStridedOut;
   const long long o = blockIdx.z;
-  for (int e = threadIdx.x; e < kStridedOut * n; e += kPassThreads) {
-    const int t = e / n, j = e - (e / n) * n;
-    ks[e] = j0 + t < mj ? K[(size_t)(j0 + t) * n + j] : T(0);
-  }
-  __syncthreads();
   if (i >= I) return;
   T acc[kStridedOut];
 #pragma unroll
   for (int t = 0; t < kStridedOut; ++t) acc[t] = T(0);
   const T* src = in + (size_t)o * n * I + i;
+  // rows past mj repeat the last row (their results are not stored)
+  const T* kr = K + (size_t)j0 * n;
+  const int tmax = mj - 1 - j0;
+#pragma unroll 2
   for (int j = 0; j < n; ++j) {
     const T v = src[(size_t)j * I];
 #pragma unroll
-    for (int t = 0; t < kStridedOut; ++t) acc[t] += ks[t * n + j] * v;
+    for (int t = 0; t < kStridedOut; ++t) acc[t] += kr[(size_t)(t < tmax ? t : tmax) * n + j] * v;
   }
   T* dst = out + (size_t)o * mj * I + i;
 #pragma unroll
@@ -98,8 +99,7 @@ template <typename T> hipError_t series_pass(const AxisPass& p, hipStream_t s) {
   } else {
     const dim3 grid((unsigned)((p.I + kPassThreads - 1) / kPassThreads), (unsigned)((p.mj + kStridedOut - 1) / kStridedOut),
                     (unsigned)p.O);
-    hipLaunchKernelGGL((k_series_strided<T>), grid, dim3(kPassThreads), (size_t)kStridedOut * p.n * sizeof(T), s, in,
-                       out, K, p.I, p.n, p.mj);
+    hipLaunchKernelGGL((k_series_strided<T>), grid, dim3(kPassThreads), 0, s, in, out, K, p.I, p.n, p.mj);
   }
   return hipGetLastError();
 }
