@@ -332,6 +332,50 @@ int hm_solve_adjoint(const hm_grid* grid, const hm_iso phases[2], hm_rule rule,
                      double* dLdphase, void* d_dLdfrac, void* stream);
 
 /*
+ * Cells of more than two phases (Section 2: the Voigt rule of eq. 3 and the
+ * Reuss rule of eq. 4 are written for Nphase phases).  Phase 0 is the
+ * matrix; every inclusion carries a phase label in 1..n_phases-1
+ * (n_phases in 2..8).
+ *
+ * hm_filter_phases - per-phase fractions: for each label p the refined
+ * points of the filter inside the spheres of label p, counted exactly as
+ * hm_filter counts the inclusion set (same lattice, stencil and rule ==
+ * HM_RULE_NONE meaning).  Spheres of different labels must not overlap
+ * (HM_E_ARG otherwise: a refined point would belong to two phases).
+ * Inputs:  labels (host, n_spheres int32 in 1..n_phases-1), others as
+ *          hm_filter.
+ * Outputs: d_count (device, uint32 [n_phases-1][N]), d_frac (device,
+ *          [n_phases-1][N] reals of the precision, count / M).
+ */
+int hm_filter_phases(const hm_grid* grid, const hm_sphere* spheres, const int32_t* labels,
+                     int n_spheres, int n_phases, double radius_vox, int subsamples,
+                     hm_rule rule, hm_prec prec, uint32_t* d_count, void* d_frac,
+                     void* stream);
+
+/*
+ * hm_solve_phases / hm_effective_tensor_phases - hm_solve and
+ * hm_effective_tensor for a multi-phase cell.  c~ per voxel: phase 0 where
+ * all fractions are 0, phase p where f_p is exactly 1, else HM_RULE_VOIGT
+ * (sum_i f_i c_i, eq. 3) or HM_RULE_REUSS ((sum_i f_i c_i^-1)^-1, eq. 4)
+ * with f_0 = 1 - (f_1 + ... + f_(P-1)) summed in phase order; the 2-layer
+ * rule (eq. 5, two phases) is refused.  c0 = c0_alpha times the mean of the
+ * smallest and largest Lame parameters over all phases.
+ * Inputs:  phases (host, n_phases isotropic phases, [0] the matrix),
+ *          d_frac (device, [n_phases-1][N] as written by hm_filter_phases),
+ *          E, n_load, opts as hm_solve (hm_solve_phases).
+ * Outputs as hm_solve / hm_effective_tensor.  HM_E_DATA: a fractional voxel
+ * with HM_RULE_NONE.  With n_phases == 2 the results equal hm_solve's on
+ * the same fractions up to rounding.
+ */
+int hm_solve_phases(const hm_grid* grid, const hm_iso* phases, int n_phases, hm_rule rule,
+                    const void* d_frac, const double* E, int n_load,
+                    const hm_solve_opts* opts, void* d_eps, double* sig_mean,
+                    hm_report* rep, void* stream);
+int hm_effective_tensor_phases(const hm_grid* grid, const hm_iso* phases, int n_phases,
+                               hm_rule rule, const void* d_frac, const hm_solve_opts* opts,
+                               double* C_mandel, void* d_eps, hm_report* rep, void* stream);
+
+/*
  * hm_fourier_series - the truncated Fourier series of a grid field,
  * evaluated on a finer grid (the extrapolated material properties of
  * Figure 4, Section 6).

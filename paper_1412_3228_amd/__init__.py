@@ -12,10 +12,13 @@ from .api import (  # noqa: F401
     hm_effective_conductivity,
     hm_effective_tensor,
     hm_effective_tensor_batch,
+    hm_effective_tensor_phases,
     hm_filter,
+    hm_filter_phases,
     hm_fourier_series,
     hm_solve,
     hm_solve_adjoint,
+    hm_solve_phases,
     hm_stiffness_component,
     last_timing,
     release_plans,

@@ -212,6 +212,71 @@ def hm_effective_conductivity(n, dim, k, rule: str, frac: torch.Tensor, incl: Op
     return {"status": rc, "K": K, "reports": _reports(rep, nd), "grad": grad}
 
 
+def _phase_array(phases) -> ctypes.Array:
+    arr = (L.HmIso * len(phases))()
+    for p, ph in enumerate(phases):
+        arr[p].lam = float(ph[0])
+        arr[p].mu = float(ph[1])
+    return arr
+
+
+def hm_filter_phases(n, dim, spheres, labels, n_phases: int, radius_vox: float, subsamples: int, rule: str,
+                     prec: str = "fp64", device="cuda:0"):
+    """Per-phase counts and fractions, each (n_phases - 1, N)."""
+    dev = _device(device)
+    N = int(n[0] * n[1] * n[2])
+    count = torch.empty((n_phases - 1, N), dtype=torch.int32, device=dev)
+    frac = torch.empty((n_phases - 1, N), dtype=_DT[prec], device=dev)
+    g = _grid(n, dim)
+    sph, ns = _spheres(spheres)
+    lab = (ctypes.c_int * max(1, ns))(*(int(v) for v in np.asarray(labels).reshape(-1)))
+    rc = _lib().hm_filter_phases(ctypes.byref(g), sph, lab, ns, int(n_phases), float(radius_vox), int(subsamples),
+                                 L.RULES[rule], L.PRECS[prec], _ptr(count), _ptr(frac), _stream(dev))
+    L.check(rc)
+    return count, frac
+
+
+def hm_solve_phases(n, dim, phases, rule: str, frac: torch.Tensor, E, prec: str = "fp64", tol: float = 1e-4,
+                    max_iter: int = 10000, c0_alpha: float = 1.0, check_every: int = 1, stall_window: int = 0,
+                    use_graph: bool = False, want_eps: bool = False, method: str = "fixed_point"):
+    """hm_solve for a cell of len(phases) phases; frac is (len(phases) - 1, N)."""
+    dev = frac.device
+    N = int(n[0] * n[1] * n[2])
+    _check_field(frac, N * (len(phases) - 1), _DT[prec], dev, "frac")
+    Ea = np.ascontiguousarray(np.asarray(E, dtype=np.float64).reshape(-1, 6))
+    nl = Ea.shape[0]
+    sig = np.zeros((nl, 6))
+    rep = (L.HmReport * nl)()
+    eps = torch.empty((nl, 6, N), dtype=_DT[prec], device=dev) if want_eps else None
+    g = _grid(n, dim)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, False, False, None, method)
+    rc = _lib().hm_solve_phases(ctypes.byref(g), _phase_array(phases), len(phases), L.RULES[rule], _ptr(frac),
+                                Ea.ctypes.data_as(L._dp), nl, ctypes.byref(o), _ptr(eps),
+                                sig.ctypes.data_as(L._dp), rep, _stream(dev))
+    L.check(rc)
+    return {"status": rc, "sig_mean": sig, "reports": _reports(rep, nl), "eps": eps}
+
+
+def hm_effective_tensor_phases(n, dim, phases, rule: str, frac: torch.Tensor, prec: str = "fp64",
+                               tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
+                               check_every: int = 1, stall_window: int = 0, use_graph: bool = False,
+                               method: str = "fixed_point"):
+    """Effective Mandel tensor of a cell of len(phases) phases."""
+    dev = frac.device
+    N = int(n[0] * n[1] * n[2])
+    _check_field(frac, N * (len(phases) - 1), _DT[prec], dev, "frac")
+    k = 3 if dim == 2 else 6
+    C = np.zeros((k, k))
+    rep = (L.HmReport * k)()
+    g = _grid(n, dim)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, False, False, None, method)
+    rc = _lib().hm_effective_tensor_phases(ctypes.byref(g), _phase_array(phases), len(phases), L.RULES[rule],
+                                           _ptr(frac), ctypes.byref(o), C.ctypes.data_as(L._dp), None, rep,
+                                           _stream(dev))
+    L.check(rc)
+    return {"status": rc, "C": C, "reports": _reports(rep, k)}
+
+
 def hm_fourier_series(n, dim, field: torch.Tensor, m, prec: str = "fp64"):
     """Truncated Fourier series of a grid field on the voxel centres of an m grid, (m_z, m_y, m_x)."""
     dev = field.device

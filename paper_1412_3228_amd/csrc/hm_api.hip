@@ -524,6 +524,8 @@ struct ProblemIn {
   hm_iso phases[2];
   int cond;      // conduction problem: phase conductivities in k, phases unused
   double k[2];
+  int nphase;    // multi-phase cell (>= 2): phases in ph, fractions [nphase - 1][N]
+  hm_iso ph[8];
   hm_rule rule;
   const void* frac;
   const int32_t* incl;
@@ -546,6 +548,13 @@ int check_problem(const ProblemIn& d) {
   if (d.cond) {
     for (int p = 0; p < 2; ++p)
       if (!(d.k[p] > 0.0) || !isfinite(d.k[p])) return fail(HM_E_ARG, "conductivity %d must be finite and > 0", p);
+  } else if (d.nphase) {
+    if (d.nphase < 2 || d.nphase > 8) return fail(HM_E_ARG, "n_phases must be in 2..8");
+    for (int p = 0; p < d.nphase; p += 2) {
+      hm_iso two[2] = {d.ph[p], d.ph[p + 1 < d.nphase ? p + 1 : p]};
+      if ((rc = check_phases(two))) return rc;
+    }
+    if (d.rule == HM_RULE_LAMINATE) return fail(HM_E_ARG, "the 2-layer rule is written for two phases");
   } else if ((rc = check_phases(d.phases))) {
     return rc;
   }
@@ -627,11 +636,20 @@ int upload_params(Group& g, const std::vector<ProblemIn>& all, const hm_solve_op
       }
     } else {
       for (int ph = 0; ph < 2; ++ph) {
-        q.pl[ph] = d.phases[ph].lambda;
-        q.pm[ph] = d.phases[ph].mu;
+        q.pl[ph] = d.nphase ? d.ph[ph].lambda : d.phases[ph].lambda;
+        q.pm[ph] = d.nphase ? d.ph[ph].mu : d.phases[ph].mu;
       }
-      const double lmin = fmin(q.pl[0], q.pl[1]), lmax = fmax(q.pl[0], q.pl[1]);
-      const double mmin = fmin(q.pm[0], q.pm[1]), mmax = fmax(q.pm[0], q.pm[1]);
+      double lmin = fmin(q.pl[0], q.pl[1]), lmax = fmax(q.pl[0], q.pl[1]);
+      double mmin = fmin(q.pm[0], q.pm[1]), mmax = fmax(q.pm[0], q.pm[1]);
+      q.nphase = d.nphase;
+      for (int ph = 0; ph < d.nphase; ++ph) {
+        q.ph_l[ph] = d.ph[ph].lambda;
+        q.ph_m[ph] = d.ph[ph].mu;
+        lmin = fmin(lmin, q.ph_l[ph]);
+        lmax = fmax(lmax, q.ph_l[ph]);
+        mmin = fmin(mmin, q.ph_m[ph]);
+        mmax = fmax(mmax, q.ph_m[ph]);
+      }
       q.rl = opts->c0_alpha * 0.5 * (lmin + lmax);
       q.rm = opts->c0_alpha * 0.5 * (mmin + mmax);
       if (opts->method == HM_CONJUGATE_GRADIENT) {
@@ -687,6 +705,31 @@ int prepare_material(Group& g, const std::vector<ProblemIn>& all, const hm_solve
   }
   for (int attempt = 0; attempt < 2; ++attempt) {
     HM_HIP(hipMemsetAsync(p->mcount, 0, 2 * sizeof(int), s));
+    // a multi-phase cell (solved alone) keeps its pure phases 2.. in the
+    // first rows of the table
+    const ProblemIn& d0 = all[g.probs[0]];
+    if (d0.nphase > 2) {
+      if (g.probs.size() != 1) return fail(HM_E_ARG, "multi-phase cells are solved one at a time");
+      const int nr = d0.nphase - 2;
+      if ((size_t)nr > p->coef_cap) return fail(HM_E_DEVICE, "material table too small");
+      const ProblemParams* hq = reinterpret_cast<const ProblemParams*>(
+          p->prm_host + align16(align16(sizeof(SolveParams)) + g.loads.size() * sizeof(LoadParams)));
+      std::vector<double> rd((size_t)nr * 8, 0.0);
+      std::vector<float> rf((size_t)nr * 8, 0.0f);
+      for (int r = 0; r < nr; ++r) {
+        const double l = hq->ph_l[r + 2], m2 = 2.0 * hq->ph_m[r + 2];
+        rd[8 * r] = l - hq->rl;
+        rd[8 * r + 1] = m2 - 2.0 * hq->rm;
+        rf[8 * r] = (float)l - (float)hq->rl;
+        rf[8 * r + 1] = (float)m2 - (float)(2.0 * hq->rm);
+      }
+      p->mcount_host[0] = nr;
+      p->mcount_host[1] = 0;
+      HM_HIP(hipMemcpyAsync(p->coef, p->fp64 ? (const void*)rd.data() : (const void*)rf.data(),
+                            (size_t)nr * 8 * (p->fp64 ? 8 : 4), hipMemcpyHostToDevice, s));
+      HM_HIP(hipMemcpyAsync(p->mcount, p->mcount_host, 2 * sizeof(int), hipMemcpyHostToDevice, s));
+      HM_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+    }
     size_t mo = 0;
     for (int j = 0; j < (int)g.probs.size(); ++j) {
       const hm_grid& gr = all[g.probs[j]].grid;
@@ -694,7 +737,13 @@ int prepare_material(Group& g, const std::vector<ProblemIn>& all, const hm_solve
       const SolveParams* prm = reinterpret_cast<const SolveParams*>(p->prm);
       const int cap = (int)std::min<size_t>(p->coef_cap, (size_t)1 << 30);
       const dim3 grid((N + 255) / 256), blk(256);
-      if (p->fp64 && p->cond)
+      if (all[g.probs[j]].nphase && p->fp64)
+        hipLaunchKernelGGL((k_material_nphase<double>), grid, blk, 0, s, prm, j, gr.n[0], gr.n[1], gr.n[2],
+                           p->mid + mo, static_cast<double*>(p->coef), cap, p->mcount);
+      else if (all[g.probs[j]].nphase)
+        hipLaunchKernelGGL((k_material_nphase<float>), grid, blk, 0, s, prm, j, gr.n[0], gr.n[1], gr.n[2],
+                           p->mid + mo, static_cast<float*>(p->coef), cap, p->mcount);
+      else if (p->fp64 && p->cond)
         hipLaunchKernelGGL((k_material<double, true>), grid, blk, 0, s, prm, j, gr.n[0], gr.n[1], gr.n[2], gr.dim,
                            p->mid + mo, static_cast<double*>(p->coef), cap, p->mcount);
       else if (p->fp64)
@@ -1391,8 +1440,11 @@ void hm_release_plans(void) {
   g_series.clear();
 }
 
-int hm_filter(const hm_grid* grid, const hm_sphere* spheres, int n_spheres, double radius_vox, int subsamples,
-              hm_rule rule, hm_prec prec, uint32_t* d_count, void* d_frac, int32_t* d_incl, void* stream) {
+// The two-phase filter (labels == NULL) and the multi-phase one (labels
+// 1..nlab per sphere, spheres of different labels must not overlap).
+static int filter_impl(const hm_grid* grid, const hm_sphere* spheres, int n_spheres, const int* labels, int nlab,
+                       double radius_vox, int subsamples, hm_rule rule, hm_prec prec, uint32_t* d_count,
+                       void* d_frac, int32_t* d_incl, void* stream) {
   int rc;
   if ((rc = check_grid(grid))) return rc;
   if ((rc = check_spheres(grid, spheres, n_spheres))) return rc;
@@ -1445,20 +1497,126 @@ int hm_filter(const hm_grid* grid, const hm_sphere* spheres, int n_spheres, doub
     if (M < 1) return fail(HM_E_ARG, "filter radius keeps no refined point");
     a.M = M;
   }
+  if (labels) {
+    // spheres of different phases may not share a refined point: their
+    // lattice balls must be disjoint (minimum image per axis)
+    const int axes = grid->dim == 2 ? 2 : 3;
+    for (int i = 0; i < n_spheres; ++i) {
+      if (labels[i] < 1 || labels[i] > nlab) return fail(HM_E_ARG, "sphere %d: label must be in 1..%d", i, nlab);
+      for (int j = 0; j < i; ++j) {
+        if (labels[j] == labels[i]) continue;
+        double d2 = 0.0;
+        for (int d = 0; d < axes; ++d) {
+          long long v = tab[i].c[d] - tab[j].c[d];
+          const long long P = a.P[d];
+          v = ((v % P) + P) % P;
+          if (v >= P / 2) v -= P;
+          d2 += (double)v * (double)v;
+        }
+        const double rr = tab[i].t + tab[j].t;
+        if (!(d2 > rr * rr)) return fail(HM_E_ARG, "spheres %d and %d of different phases overlap", j, i);
+      }
+    }
+  }
   hipStream_t s = (hipStream_t)stream;
   LatSphere* dtab = nullptr;
+  int* dlab = nullptr;
   const size_t tb = tab.size() * sizeof(LatSphere);
   if ((rc = device_alloc((void**)&dtab, tb, "sphere table"))) return rc;
+  if (labels && (rc = device_alloc((void**)&dlab, (size_t)(n_spheres > 0 ? n_spheres : 1) * sizeof(int), "labels"))) {
+    (void)hipFree(dtab);
+    return rc;
+  }
   hipError_t e = hipMemcpyAsync(dtab, tab.data(), tb, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && labels && n_spheres > 0)
+    e = hipMemcpyAsync(dlab, labels, (size_t)n_spheres * sizeof(int), hipMemcpyHostToDevice, s);
   a.sph = dtab;
   a.count = d_count;
   a.frac = d_frac;
-  a.incl = d_incl;
+  a.incl = labels ? nullptr : d_incl;
+  a.lab = dlab;
+  a.nlab = labels ? nlab : 1;
   if (e == hipSuccess) e = launch_filter(a, prec == HM_FP64, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(dtab);
+  (void)hipFree(dlab);
   if (e != hipSuccess) return fail(HM_E_DEVICE, "filter: %s", hipGetErrorString(e));
   return HM_OK;
+}
+
+int hm_filter(const hm_grid* grid, const hm_sphere* spheres, int n_spheres, double radius_vox, int subsamples,
+              hm_rule rule, hm_prec prec, uint32_t* d_count, void* d_frac, int32_t* d_incl, void* stream) {
+  return filter_impl(grid, spheres, n_spheres, nullptr, 1, radius_vox, subsamples, rule, prec, d_count, d_frac,
+                     d_incl, stream);
+}
+
+int hm_filter_phases(const hm_grid* grid, const hm_sphere* spheres, const int32_t* labels, int n_spheres,
+                     int n_phases, double radius_vox, int subsamples, hm_rule rule, hm_prec prec, uint32_t* d_count,
+                     void* d_frac, void* stream) {
+  if (n_phases < 2 || n_phases > 8) return fail(HM_E_ARG, "n_phases must be in 2..8");
+  if (n_spheres > 0 && !labels) return fail(HM_E_ARG, "labels is NULL");
+  return filter_impl(grid, spheres, n_spheres, labels, n_phases - 1, radius_vox, subsamples, rule, prec, d_count,
+                     d_frac, nullptr, stream);
+}
+
+// A multi-phase cell as a ProblemIn.
+static ProblemIn phases_problem(const hm_grid* grid, const hm_iso* phases, int n_phases, hm_rule rule,
+                                const void* d_frac) {
+  ProblemIn d = make_problem(grid, nullptr, rule, d_frac, nullptr, nullptr, 0);
+  d.nphase = n_phases;
+  if (phases && n_phases >= 2 && n_phases <= 8)
+    for (int p = 0; p < n_phases; ++p) d.ph[p] = phases[p];
+  return d;
+}
+
+int hm_solve_phases(const hm_grid* grid, const hm_iso* phases, int n_phases, hm_rule rule, const void* d_frac,
+                    const double* E, int n_load, const hm_solve_opts* opts, void* d_eps, double* sig_mean,
+                    hm_report* rep, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!phases) return fail(HM_E_ARG, "phases is NULL");
+  if (n_phases < 2 || n_phases > 8) return fail(HM_E_ARG, "n_phases must be in 2..8");
+  if (!E || !sig_mean) return fail(HM_E_ARG, "E and sig_mean must not be NULL");
+  Plan* p = nullptr;
+  int rc = solve_one(phases_problem(grid, phases, n_phases, rule, d_frac), E, n_load, opts, d_eps,
+                     (hipStream_t)stream, &p);
+  if (rc) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = HM_OK;
+  for (int l = 0; l < n_load; ++l) {
+    const SolverState& st = p->state_host[l];
+    for (int c = 0; c < 6; ++c) sig_mean[6 * l + c] = st.sig[c];
+    const int status = load_status(st);
+    if (rep) rep[l] = hm_report{st.iters, status, st.err, st.err0, secs};
+    worst = std::max(worst, status);
+  }
+  return worst;
+}
+
+int hm_effective_tensor_phases(const hm_grid* grid, const hm_iso* phases, int n_phases, hm_rule rule,
+                               const void* d_frac, const hm_solve_opts* opts, double* C_mandel, void* d_eps,
+                               hm_report* rep, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  int rc;
+  if ((rc = check_grid(grid))) return rc;
+  if (!phases) return fail(HM_E_ARG, "phases is NULL");
+  if (n_phases < 2 || n_phases > 8) return fail(HM_E_ARG, "n_phases must be in 2..8");
+  if (!C_mandel) return fail(HM_E_ARG, "C_mandel is NULL");
+  double E[36];
+  const int* idx = nullptr;
+  const int k = unit_loads(grid->dim, E, &idx);
+  Plan* p = nullptr;
+  rc = solve_one(phases_problem(grid, phases, n_phases, rule, d_frac), E, k, opts, d_eps, (hipStream_t)stream, &p);
+  if (rc) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  assemble_mandel(k, idx, p->state_host, C_mandel);
+  int worst = HM_OK;
+  for (int l = 0; l < k; ++l) {
+    const SolverState& st = p->state_host[l];
+    const int status = load_status(st);
+    if (rep) rep[l] = hm_report{st.iters, status, st.err, st.err0, secs};
+    worst = std::max(worst, status);
+  }
+  return worst;
 }
 
 int hm_solve(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac, const int32_t* d_incl,

@@ -67,6 +67,13 @@ struct ProblemParams {
   // them: in single precision from single-precision inputs, or in double
   float pure_f[4];
   double pure_d[4];
+  // multi-phase cells (nphase >= 2 through the multi-phase entry points, 0
+  // otherwise): Lame parameters of every phase (0: matrix), fractions of
+  // phases 1..nphase-1 in frac as [phase - 1][N]; table rows 0..nphase-3
+  // hold the pure phases 2..nphase-1
+  int nphase;
+  int pad;
+  double ph_l[8], ph_m[8];
 };
 
 // One load case: its macroscopic strain (tensor components) and problem;

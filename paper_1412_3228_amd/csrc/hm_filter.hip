@@ -21,6 +21,9 @@
 // every stencil point to be the voxel's own image shifted by the offset
 // (the ball does not straddle half a period from the sphere); otherwise, or
 // with more candidates than the list holds, the points are tested one by one.
+// A multi-phase filter counts each inclusion phase on its own (the spheres
+// of other phases are skipped), which partitions the union when spheres of
+// different phases do not overlap.
 #include <math.h>
 #include <stdint.h>
 
@@ -53,20 +56,15 @@ __device__ __forceinline__ long long odd_count(long long lo, long long hi) {
   return fdiv2(hi - 1) - fdiv2(lo) + 1;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_filter(FilterArgs a) {
-  const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= N) return;
-  const int x = (int)(v % a.n[0]);
-  const int y = (int)((v / a.n[0]) % a.n[1]);
-  const int z = (int)(v / ((long long)a.n[0] * a.n[1]));
-  const int axes = a.dim == 2 ? 2 : 3;
-  const long long X[3] = {(2LL * x + 1) * a.S, (2LL * y + 1) * a.S, (2LL * z + 1) * a.S};
-
+// Refined points of the filter around the voxel centre X (lattice units)
+// that lie inside the spheres of label `want` (every sphere when want is 0;
+// labels are the inclusion phases of a multi-phase filter).
+__device__ uint32_t filter_count(const FilterArgs& a, const long long X[3], int axes, int want) {
+  auto take = [&](int k) { return want == 0 || a.lab[k] == want; };
   uint32_t cnt = 0;
   if (a.point) {
     for (int k = 0; k < a.nsph; ++k) {
+      if (!take(k)) continue;
       long long d2 = 0;
       for (int ax = 0; ax < axes; ++ax) {
         const long long d = min_image(X[ax] - a.sph[k].c[ax], a.P[ax]);
@@ -77,122 +75,149 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a) {
         break;
       }
     }
-  } else {
-    int cand[kMaxCand];
-    int nc = 0;
-    bool overflow = false, full = false;
-    for (int k = 0; k < a.nsph && !full; ++k) {
-      long long d2 = 0;
-      for (int ax = 0; ax < axes; ++ax) {
-        const long long d = min_image(X[ax] - a.sph[k].c[ax], a.P[ax]);
-        d2 += d * d;
+    return cnt;
+  }
+  int cand[kMaxCand];
+  int nc = 0;
+  bool overflow = false, full = false;
+  for (int k = 0; k < a.nsph && !full; ++k) {
+    if (!take(k)) continue;
+    long long d2 = 0;
+    for (int ax = 0; ax < axes; ++ax) {
+      const long long d = min_image(X[ax] - a.sph[k].c[ax], a.P[ax]);
+      d2 += d * d;
+    }
+    const double D = sqrt((double)d2);
+    if (D + a.rho <= a.sph[k].t - 1.0) {
+      full = true;
+    } else if (D - a.rho <= a.sph[k].t + 1.0) {
+      if (nc < kMaxCand)
+        cand[nc++] = k;
+      else
+        overflow = true;
+    }
+  }
+  // per-candidate minimum-image offset of the voxel centre; the row method
+  // needs every stencil point's image to follow from it (no wrap)
+  long long d0[kMaxCand][3] = {};
+  long long rint[kMaxCand] = {};
+  bool rows_ok = !overflow;
+  if (!full && rows_ok) {
+    for (int q = 0; q < nc; ++q) {
+      const int k = cand[q];
+      for (int ax = 0; ax < 3; ++ax) {
+        const long long h = a.P[ax] / 2;
+        const long long d = ax < axes ? min_image(X[ax] - a.sph[k].c[ax], a.P[ax]) : 0;
+        d0[q][ax] = d;
+        if (ax < axes && (d - a.m < -h || d + a.m >= h)) rows_ok = false;
       }
-      const double D = sqrt((double)d2);
-      if (D + a.rho <= a.sph[k].t - 1.0) {
-        full = true;
-      } else if (D - a.rho <= a.sph[k].t + 1.0) {
-        if (nc < kMaxCand)
-          cand[nc++] = k;
-        else
-          overflow = true;
+      rint[q] = (long long)floor(a.sph[k].R2);
+    }
+  }
+  if (full) {
+    cnt = (uint32_t)a.M;
+  } else if (nc > 0 && rows_ok) {
+    const long long rho_i = (long long)floor(a.rho2);
+    const int zlo = axes == 3 ? -a.m : 0;
+    const int zhi = axes == 3 ? a.m : 0;
+    long long total = 0;
+    for (int oz = zlo; oz <= zhi; ++oz) {
+      if (axes == 3 && (oz & 1) == 0) continue;
+      for (int oy = -a.m; oy <= a.m; ++oy) {
+        if ((oy & 1) == 0) continue;
+        const long long rest = rho_i - (long long)oy * oy - (long long)oz * oz;
+        if (rest < 1) continue;
+        const long long al = isqrt(rest);  // |ox| <= al inside the filter ball
+        long long lo[kMaxCand], hi[kMaxCand];
+        int ni = 0;
+        for (int q = 0; q < nc; ++q) {
+          const long long dy = d0[q][1] + oy, dz = d0[q][2] + oz;
+          const long long Q = rint[q] - dy * dy - dz * dz;
+          if (Q < 0) continue;
+          const long long b = isqrt(Q);  // |d0x + ox| <= b inside sphere q
+          const long long l = max(-al, -b - d0[q][0]), u = min(al, b - d0[q][0]);
+          if (l > u) continue;
+          // insert sorted by lower end
+          int j = ni++;
+          while (j > 0 && lo[j - 1] > l) {
+            lo[j] = lo[j - 1];
+            hi[j] = hi[j - 1];
+            --j;
+          }
+          lo[j] = l;
+          hi[j] = u;
+        }
+        // odd integers in the union of the sorted intervals
+        long long cl = 0, ch = -1;
+        bool open = false;
+        for (int j = 0; j < ni; ++j) {
+          if (open && lo[j] <= ch + 1) {
+            ch = max(ch, hi[j]);
+          } else {
+            if (open) total += odd_count(cl, ch);
+            cl = lo[j];
+            ch = hi[j];
+            open = true;
+          }
+        }
+        if (open) total += odd_count(cl, ch);
       }
     }
-    // per-candidate minimum-image offset of the voxel centre; the row method
-    // needs every stencil point's image to follow from it (no wrap)
-    long long d0[kMaxCand][3] = {};
-    long long rint[kMaxCand] = {};
-    bool rows_ok = !overflow;
-    if (!full && rows_ok) {
-      for (int q = 0; q < nc; ++q) {
-        const int k = cand[q];
-        for (int ax = 0; ax < 3; ++ax) {
-          const long long h = a.P[ax] / 2;
-          const long long d = ax < axes ? min_image(X[ax] - a.sph[k].c[ax], a.P[ax]) : 0;
-          d0[q][ax] = d;
-          if (ax < axes && (d - a.m < -h || d + a.m >= h)) rows_ok = false;
-        }
-        rint[q] = (long long)floor(a.sph[k].R2);
-      }
-    }
-    if (full) {
-      cnt = (uint32_t)a.M;
-    } else if (nc > 0 && rows_ok) {
-      const long long rho_i = (long long)floor(a.rho2);
-      const int zlo = axes == 3 ? -a.m : 0;
-      const int zhi = axes == 3 ? a.m : 0;
-      long long total = 0;
-      for (int oz = zlo; oz <= zhi; ++oz) {
-        if (axes == 3 && (oz & 1) == 0) continue;
-        for (int oy = -a.m; oy <= a.m; ++oy) {
-          if ((oy & 1) == 0) continue;
-          const long long rest = rho_i - (long long)oy * oy - (long long)oz * oz;
-          if (rest < 1) continue;
-          const long long al = isqrt(rest);  // |ox| <= al inside the filter ball
-          long long lo[kMaxCand], hi[kMaxCand];
-          int ni = 0;
-          for (int q = 0; q < nc; ++q) {
-            const long long dy = d0[q][1] + oy, dz = d0[q][2] + oz;
-            const long long Q = rint[q] - dy * dy - dz * dz;
-            if (Q < 0) continue;
-            const long long b = isqrt(Q);  // |d0x + ox| <= b inside sphere q
-            const long long l = max(-al, -b - d0[q][0]), u = min(al, b - d0[q][0]);
-            if (l > u) continue;
-            // insert sorted by lower end
-            int j = ni++;
-            while (j > 0 && lo[j - 1] > l) {
-              lo[j] = lo[j - 1];
-              hi[j] = hi[j - 1];
-              --j;
+    cnt = (uint32_t)total;
+  } else if (nc > 0) {
+    const int zlo = axes == 3 ? -a.m : 0;
+    const int zhi = axes == 3 ? a.m : 0;
+    for (int oz = zlo; oz <= zhi; ++oz) {
+      if (axes == 3 && (oz & 1) == 0) continue;
+      for (int oy = -a.m; oy <= a.m; ++oy) {
+        if ((oy & 1) == 0) continue;
+        for (int ox = -a.m; ox <= a.m; ++ox) {
+          if ((ox & 1) == 0) continue;
+          const long long o2 = (long long)ox * ox + (long long)oy * oy + (long long)oz * oz;
+          if ((double)o2 > a.rho2) continue;
+          const long long p[3] = {X[0] + ox, X[1] + oy, X[2] + oz};
+          bool in = false;
+          const int nk = overflow ? a.nsph : nc;
+          for (int q = 0; q < nk && !in; ++q) {
+            const int k = overflow ? q : cand[q];
+            if (!take(k)) continue;
+            long long d2 = 0;
+            for (int ax = 0; ax < axes; ++ax) {
+              const long long d = min_image(p[ax] - a.sph[k].c[ax], a.P[ax]);
+              d2 += d * d;
             }
-            lo[j] = l;
-            hi[j] = u;
+            in = (double)d2 <= a.sph[k].R2;
           }
-          // odd integers in the union of the sorted intervals
-          long long cl = 0, ch = -1;
-          bool open = false;
-          for (int j = 0; j < ni; ++j) {
-            if (open && lo[j] <= ch + 1) {
-              ch = max(ch, hi[j]);
-            } else {
-              if (open) total += odd_count(cl, ch);
-              cl = lo[j];
-              ch = hi[j];
-              open = true;
-            }
-          }
-          if (open) total += odd_count(cl, ch);
-        }
-      }
-      cnt = (uint32_t)total;
-    } else if (nc > 0) {
-      const int zlo = axes == 3 ? -a.m : 0;
-      const int zhi = axes == 3 ? a.m : 0;
-      for (int oz = zlo; oz <= zhi; ++oz) {
-        if (axes == 3 && (oz & 1) == 0) continue;
-        for (int oy = -a.m; oy <= a.m; ++oy) {
-          if ((oy & 1) == 0) continue;
-          for (int ox = -a.m; ox <= a.m; ++ox) {
-            if ((ox & 1) == 0) continue;
-            const long long o2 = (long long)ox * ox + (long long)oy * oy + (long long)oz * oz;
-            if ((double)o2 > a.rho2) continue;
-            const long long p[3] = {X[0] + ox, X[1] + oy, X[2] + oz};
-            bool in = false;
-            const int nk = overflow ? a.nsph : nc;
-            for (int q = 0; q < nk && !in; ++q) {
-              const int k = overflow ? q : cand[q];
-              long long d2 = 0;
-              for (int ax = 0; ax < axes; ++ax) {
-                const long long d = min_image(p[ax] - a.sph[k].c[ax], a.P[ax]);
-                d2 += d * d;
-              }
-              in = (double)d2 <= a.sph[k].R2;
-            }
-            cnt += in ? 1u : 0u;
-          }
+          cnt += in ? 1u : 0u;
         }
       }
     }
   }
+  return cnt;
+}
+
+// One thread per voxel.  NPH: counts and fractions per inclusion phase
+// (labels 1..nlab, written to [label - 1][voxel]); otherwise one count for
+// the union of all spheres and the normal-sphere id.
+template <typename T, bool NPH>
+__global__ __launch_bounds__(256) void k_filter(FilterArgs a) {
+  const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const int x = (int)(v % a.n[0]);
+  const int y = (int)((v / a.n[0]) % a.n[1]);
+  const int z = (int)(v / ((long long)a.n[0] * a.n[1]));
+  const int axes = a.dim == 2 ? 2 : 3;
+  const long long X[3] = {(2LL * x + 1) * a.S, (2LL * y + 1) * a.S, (2LL * z + 1) * a.S};
+  if constexpr (NPH) {
+    for (int p = 1; p <= a.nlab; ++p) {
+      const uint32_t c = filter_count(a, X, axes, p);
+      a.count[(size_t)(p - 1) * N + v] = c;
+      static_cast<T*>(a.frac)[(size_t)(p - 1) * N + v] = (T)c / (T)a.M;
+    }
+    return;
+  }
+  const uint32_t cnt = filter_count(a, X, axes, 0);
   a.count[v] = cnt;
   static_cast<T*>(a.frac)[v] = (T)cnt / (T)a.M;
   if (a.incl) {
@@ -219,10 +244,14 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a) {
 hipError_t launch_filter(const FilterArgs& a, bool fp64, hipStream_t s) {
   const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
   const dim3 grid((unsigned)((N + 255) / 256));
-  if (fp64)
-    hipLaunchKernelGGL((k_filter<double>), grid, dim3(256), 0, s, a);
+  if (fp64 && a.lab)
+    hipLaunchKernelGGL((k_filter<double, true>), grid, dim3(256), 0, s, a);
+  else if (fp64)
+    hipLaunchKernelGGL((k_filter<double, false>), grid, dim3(256), 0, s, a);
+  else if (a.lab)
+    hipLaunchKernelGGL((k_filter<float, true>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k_filter<float>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_filter<float, false>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -27,6 +27,10 @@ struct FilterArgs {
   uint32_t* count;
   void* frac;
   int32_t* incl;
+  // multi-phase filter: inclusion phase (1..nlab) of every sphere, device;
+  // null for the two-phase filter
+  const int* lab;
+  int nlab;
 };
 
 hipError_t launch_filter(const FilterArgs& a, bool fp64, hipStream_t s);

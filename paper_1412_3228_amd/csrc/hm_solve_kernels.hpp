@@ -134,6 +134,87 @@ __global__ __launch_bounds__(256) void k_material(const SolveParams* prm, int pr
   }
 }
 
+// Multi-phase form of k_material (eqs. 3-4 with Nphase phases): fractions
+// f_1..f_(P-1) of the voxel, f_0 = 1 - (f_1 + ... + f_(P-1)); all zero is
+// pure matrix (-1), f_1 = 1 pure phase 1 (-2), f_p = 1 for p >= 2 the
+// reserved row p - 2; fractional voxels take a new row with the Voigt
+// (sum f_i lambda_i, sum f_i mu_i) or Reuss (K = 1 / sum f_i / K_i,
+// mu = 1 / sum f_i / mu_i) isotropic tensor.  count[0] starts at the number
+// of reserved rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_material_nphase(const SolveParams* prm, int prob, int nx, int ny, int nz,
+                                                         int* mid, T* coef, int cap, int* count) {
+  const ProblemParams& P = prm->probs[prob];
+  const int N = nx * ny * nz;
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const T* fr = static_cast<const T*>(P.frac);
+  const int np = P.nphase;
+  constexpr int kFractional = 1 << 30;
+  T sum = T(0);
+  int pure = kFractional;  // or -1 / -2: pure matrix / phase 1, r >= 0: reserved row
+  if (v < N) {
+    bool any = false;
+    for (int p = 1; p < np; ++p) {
+      const T f = fr[(size_t)(p - 1) * N + v];
+      sum += f;
+      any = any || f != T(0);
+      if (f == T(1) && pure == kFractional) pure = p == 1 ? -2 : p - 2;
+    }
+    if (!any) pure = -1;
+  }
+  const bool frac_voxel = v < N && pure == kFractional;
+  const unsigned long long m = __ballot(frac_voxel);
+  int base = 0;
+  if (m) {
+    const int leader = __ffsll((long long)m) - 1;
+    if (lane == leader) base = atomicAdd(&count[0], __popcll(m));
+    base = __shfl(base, leader, 64);
+  }
+  if (v >= N) return;
+  if (!frac_voxel) {
+    mid[v] = pure;
+    return;
+  }
+  const int row = base + __popcll(m & ((1ull << lane) - 1ull));
+  mid[v] = row;
+  int rule = P.rule;
+  if (rule != RULE_VOIGT && rule != RULE_REUSS) {
+    atomicOr(&count[1], FLAG_NONE_FRACTIONAL);
+    rule = RULE_VOIGT;
+  }
+  const T f0 = T(1) - sum;
+  T a1, a2;
+  if (rule == RULE_REUSS) {
+    T sk = f0 / (T(P.ph_l[0]) + T(2.0 / 3.0) * T(P.ph_m[0]));
+    T sm = f0 / T(P.ph_m[0]);
+    for (int p = 1; p < np; ++p) {
+      const T f = fr[(size_t)(p - 1) * N + v];
+      sk += f / (T(P.ph_l[p]) + T(2.0 / 3.0) * T(P.ph_m[p]));
+      sm += f / T(P.ph_m[p]);
+    }
+    const T K = T(1) / sk, mu = T(1) / sm;
+    a1 = K - T(2.0 / 3.0) * mu;
+    a2 = T(2) * mu;
+  } else {
+    T l = f0 * T(P.ph_l[0]), u = f0 * T(P.ph_m[0]);
+    for (int p = 1; p < np; ++p) {
+      const T f = fr[(size_t)(p - 1) * N + v];
+      l += f * T(P.ph_l[p]);
+      u += f * T(P.ph_m[p]);
+    }
+    a1 = l;
+    a2 = T(2) * u;
+  }
+  if (row < cap) {
+    T* r = coef + (size_t)row * 8;
+    r[0] = a1 - T(P.rl);
+    r[1] = a2 - T(2.0 * P.rm);
+#pragma unroll
+    for (int i = 2; i < 8; ++i) r[i] = T(0);
+  }
+}
+
 // Material constants of one problem in the working precision, copied into
 // registers once per block (the voxel loop stores to global memory, so
 // values read through the parameter pointer would otherwise be re-read for
