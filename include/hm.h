@@ -376,6 +376,37 @@ int hm_effective_tensor_phases(const hm_grid* grid, const hm_iso* phases, int n_
                                double* C_mandel, void* d_eps, hm_report* rep, void* stream);
 
 /*
+ * hm_solve_aniso / hm_effective_tensor_aniso - hm_solve and
+ * hm_effective_tensor for two anisotropic phases (Section 2's rules are
+ * written for general phase tensors).  c~ per voxel: the phase tensor where
+ * f is 0 or 1, else Voigt (eq. 3), Reuss (eq. 4, compliances averaged) or
+ * the 2-layer rule (eq. 5: continuous in-plane strain and out-of-plane
+ * stress across an interface of normal n, with the fraction-weighted means
+ * of the other parts), evaluated in double once per solve and stored as the
+ * 21 upper-triangle entries of the Mandel matrix of c~ - c0.  Reference
+ * medium: c0 = 2 mu0 I (lambda0 = 0) with 2 mu0 = c0_alpha times the mean
+ * of the smallest and largest eigenvalue of the two phase Mandel matrices,
+ * which keeps c - c0 within (-c0, c0).
+ * Inputs:  C_phases (host, 2 x 36 doubles: the Mandel 6x6 matrices of the
+ *          matrix then the inclusion phase, row-major, symmetric positive
+ *          definite; order 11, 22, 33, 23, 13, 12 with sqrt(2) on shear
+ *          rows and columns), other inputs and outputs as hm_solve /
+ *          hm_effective_tensor (autotune is ignored; schedule -1 or 0).
+ * The tables of these solves hold 24 reals per fractional voxel and two
+ * rows for the pure phases.
+ */
+int hm_solve_aniso(const hm_grid* grid, const double* C_phases, hm_rule rule,
+                   const void* d_frac, const int32_t* d_incl,
+                   const hm_sphere* spheres, int n_spheres,
+                   const double* E, int n_load, const hm_solve_opts* opts,
+                   void* d_eps, double* sig_mean, hm_report* rep, void* stream);
+int hm_effective_tensor_aniso(const hm_grid* grid, const double* C_phases, hm_rule rule,
+                              const void* d_frac, const int32_t* d_incl,
+                              const hm_sphere* spheres, int n_spheres,
+                              const hm_solve_opts* opts, double* C_mandel,
+                              void* d_eps, hm_report* rep, void* stream);
+
+/*
  * hm_fourier_series - the truncated Fourier series of a grid field,
  * evaluated on a finer grid (the extrapolated material properties of
  * Figure 4, Section 6).

@@ -11,12 +11,14 @@ from .api import (  # noqa: F401
     hm_conduct_solve,
     hm_effective_conductivity,
     hm_effective_tensor,
+    hm_effective_tensor_aniso,
     hm_effective_tensor_batch,
     hm_effective_tensor_phases,
     hm_filter,
     hm_filter_phases,
     hm_fourier_series,
     hm_solve,
+    hm_solve_aniso,
     hm_solve_adjoint,
     hm_solve_phases,
     hm_stiffness_component,

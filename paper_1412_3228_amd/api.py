@@ -277,6 +277,59 @@ def hm_effective_tensor_phases(n, dim, phases, rule: str, frac: torch.Tensor, pr
     return {"status": rc, "C": C, "reports": _reports(rep, k)}
 
 
+def _mandel_pair(C_phases) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(C_phases, dtype=np.float64).reshape(2, 6, 6))
+    return a
+
+
+def hm_solve_aniso(n, dim, C_phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres, E,
+                   prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
+                   check_every: int = 1, stall_window: int = 0, use_graph: bool = False, want_eps: bool = False,
+                   method: str = "fixed_point"):
+    """hm_solve for two anisotropic phases given as Mandel matrices (2, 6, 6)."""
+    dev = frac.device
+    N = int(n[0] * n[1] * n[2])
+    _check_field(frac, N, _DT[prec], dev, "frac")
+    _check_field(incl, N, torch.int32, dev, "incl")
+    Cp = _mandel_pair(C_phases)
+    Ea = np.ascontiguousarray(np.asarray(E, dtype=np.float64).reshape(-1, 6))
+    nl = Ea.shape[0]
+    sig = np.zeros((nl, 6))
+    rep = (L.HmReport * nl)()
+    eps = torch.empty((nl, 6, N), dtype=_DT[prec], device=dev) if want_eps else None
+    g = _grid(n, dim)
+    sph, ns = _spheres(spheres)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, False, False, None, method)
+    rc = _lib().hm_solve_aniso(ctypes.byref(g), Cp.ctypes.data_as(L._dp), L.RULES[rule], _ptr(frac), _ptr(incl),
+                               sph, ns, Ea.ctypes.data_as(L._dp), nl, ctypes.byref(o), _ptr(eps),
+                               sig.ctypes.data_as(L._dp), rep, _stream(dev))
+    L.check(rc)
+    return {"status": rc, "sig_mean": sig, "reports": _reports(rep, nl), "eps": eps}
+
+
+def hm_effective_tensor_aniso(n, dim, C_phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor],
+                              spheres, prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000,
+                              c0_alpha: float = 1.0, check_every: int = 1, stall_window: int = 0,
+                              use_graph: bool = False, method: str = "fixed_point"):
+    """Effective Mandel tensor for two anisotropic phases."""
+    dev = frac.device
+    N = int(n[0] * n[1] * n[2])
+    _check_field(frac, N, _DT[prec], dev, "frac")
+    _check_field(incl, N, torch.int32, dev, "incl")
+    Cp = _mandel_pair(C_phases)
+    k = 3 if dim == 2 else 6
+    C = np.zeros((k, k))
+    rep = (L.HmReport * k)()
+    g = _grid(n, dim)
+    sph, ns = _spheres(spheres)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, False, False, None, method)
+    rc = _lib().hm_effective_tensor_aniso(ctypes.byref(g), Cp.ctypes.data_as(L._dp), L.RULES[rule], _ptr(frac),
+                                          _ptr(incl), sph, ns, ctypes.byref(o), C.ctypes.data_as(L._dp), None, rep,
+                                          _stream(dev))
+    L.check(rc)
+    return {"status": rc, "C": C, "reports": _reports(rep, k)}
+
+
 def hm_fourier_series(n, dim, field: torch.Tensor, m, prec: str = "fp64"):
     """Truncated Fourier series of a grid field on the voxel centres of an m grid, (m_z, m_y, m_x)."""
     dev = field.device

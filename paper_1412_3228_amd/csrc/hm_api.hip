@@ -25,6 +25,7 @@
 #include "hm_common.hpp"
 #include "hm_adjoint.hpp"
 #include "hm_filter.hpp"
+#include "hm_aniso_kernels.hpp"
 #include "hm_conduct_kernels.hpp"
 #include "hm_extrapolate.hpp"
 #include "hm_solve_kernels.hpp"
@@ -60,6 +61,17 @@ const CondKernels* cond_kernels_f64_g0(int n);
 const CondKernels* cond_kernels_f64_g1(int n);
 const CondKernels* cond_kernels_f32_g0(int n);
 const CondKernels* cond_kernels_f32_g1(int n);
+
+const AnisoKernels* aniso_kernels_f64_g0(int n);
+const AnisoKernels* aniso_kernels_f64_g1(int n);
+const AnisoKernels* aniso_kernels_f32_g0(int n);
+const AnisoKernels* aniso_kernels_f32_g1(int n);
+
+const AnisoKernels* aniso_kernels(bool fp64, int n) {
+  const AnisoKernels* k = fp64 ? aniso_kernels_f64_g0(n) : aniso_kernels_f32_g0(n);
+  if (!k) k = fp64 ? aniso_kernels_f64_g1(n) : aniso_kernels_f32_g1(n);
+  return k;
+}
 
 const CondKernels* cond_kernels(bool fp64, int n) {
   const CondKernels* k = fp64 ? cond_kernels_f64_g0(n) : cond_kernels_f32_g0(n);
@@ -174,7 +186,9 @@ void set_schedule(Plan* p, const XKern* X, const YKern* Y, const ZKern* Z);
 
 struct Plan {
   bool fp64 = true;
-  bool cond = false;  // conduction plan: 3 gradient components, conduction kernels
+  bool cond = false;   // conduction plan: 3 gradient components, conduction kernels
+  bool aniso = false;  // anisotropic phases: general-row x-sweep, elastic y / z sweeps
+  const AnisoKernels* ak = nullptr;
   int n[3] = {0, 0, 0};
   int n_load = 0;
   int device = 0;
@@ -217,7 +231,7 @@ struct Plan {
 };
 
 std::mutex g_mutex;
-std::map<std::tuple<int, bool, bool, int, int, int, int>, Plan*> g_plans;
+std::map<std::tuple<int, bool, int, int, int, int, int>, Plan*> g_plans;
 
 void free_plan(Plan* p) {
   if (p->graph) (void)hipGraphExecDestroy(p->graph);
@@ -276,11 +290,16 @@ int upload_twiddles(Plan* p, int axis, int n) {
   return HM_OK;
 }
 
-int get_plan(bool fp64, const int n[3], int dim, int n_load, bool cond, Plan** out) {
+// Physics of a plan: elasticity with isotropic phases, conduction, or
+// elasticity with anisotropic phases.
+enum : int { PHYS_ELASTIC = 0, PHYS_CONDUCTION = 1, PHYS_ANISO = 2 };
+
+int get_plan(bool fp64, const int n[3], int dim, int n_load, int phys, Plan** out) {
+  const bool cond = phys == PHYS_CONDUCTION;
   int dev = 0;
   HM_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lock(g_mutex);
-  auto key = std::make_tuple(dev, fp64, cond, n[0], n[1], n[2], n_load);
+  auto key = std::make_tuple(dev, fp64, phys, n[0], n[1], n[2], n_load);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) {
     *out = it->second;
@@ -292,6 +311,7 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, bool cond, Plan** o
   for (int d = 0; d < 3; ++d) p->n[d] = n[d];
   p->n_load = n_load;
   p->cond = cond;
+  p->aniso = phys == PHYS_ANISO;
   bool have = true;
   if (cond) {
     for (int d = 0; d < 3; ++d) have = have && (p->ck[d] = cond_kernels(fp64, n[d])) != nullptr;
@@ -300,6 +320,7 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, bool cond, Plan** o
     p->ky = axis_kernels(fp64, n[1]);
     p->kz = axis_kernels(fp64, n[2]);
     have = p->kx && p->ky && p->kz;
+    if (p->aniso) have = have && (p->ak = aniso_kernels(fp64, n[0])) != nullptr;
   }
   if (!have) {
     delete p;
@@ -359,6 +380,8 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, bool cond, Plan** o
   a.cond = cond ? 1 : 0;
   if (cond)
     set_schedule(p, &p->ck[0]->x, &p->ck[1]->y, &p->ck[2]->z);
+  else if (p->aniso)
+    set_schedule(p, &p->ak->x, &p->ky->y[0], &p->kz->z[0]);
   else
     set_schedule(p, &p->kx->x[0], &p->ky->y[0], &p->kz->z[0]);
   g_plans[key] = p;
@@ -526,6 +549,8 @@ struct ProblemIn {
   double k[2];
   int nphase;    // multi-phase cell (>= 2): phases in ph, fractions [nphase - 1][N]
   hm_iso ph[8];
+  int aniso;     // anisotropic phases: Mandel matrices in cm, phases unused
+  double cm[2][36];
   hm_rule rule;
   const void* frac;
   const int32_t* incl;
@@ -542,6 +567,67 @@ struct Group {
   bool active = true;
 };
 
+// Extreme eigenvalues of a symmetric 6x6 matrix (cyclic Jacobi rotations).
+void sym6_eig_range(const double* M, double* lo, double* hi) {
+  double a[6][6];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) a[i][j] = 0.5 * (M[i * 6 + j] + M[j * 6 + i]);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j) off += a[i][j] * a[i][j];
+    if (off < 1e-30) break;
+    for (int p = 0; p < 6; ++p)
+      for (int q = p + 1; q < 6; ++q) {
+        if (a[p][q] == 0.0) continue;
+        const double th = 0.5 * (a[q][q] - a[p][p]) / a[p][q];
+        const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 6; ++k) {  // columns p, q
+          const double akp = a[k][p], akq = a[k][q];
+          a[k][p] = c * akp - sn * akq;
+          a[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 6; ++k) {  // rows p, q
+          const double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = c * apk - sn * aqk;
+          a[q][k] = sn * apk + c * aqk;
+        }
+      }
+  }
+  *lo = a[0][0];
+  *hi = a[0][0];
+  for (int i = 1; i < 6; ++i) {
+    *lo = fmin(*lo, a[i][i]);
+    *hi = fmax(*hi, a[i][i]);
+  }
+}
+
+// Symmetric (to 1e-12 relative) and positive definite (Cholesky succeeds).
+bool spd6(const double* M) {
+  double scale = 0.0;
+  for (int i = 0; i < 36; ++i) {
+    if (!isfinite(M[i])) return false;
+    scale = fmax(scale, fabs(M[i]));
+  }
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < i; ++j)
+      if (fabs(M[i * 6 + j] - M[j * 6 + i]) > 1e-12 * scale) return false;
+  double L[36] = {};
+  for (int j = 0; j < 6; ++j) {
+    double d = M[j * 6 + j];
+    for (int k = 0; k < j; ++k) d -= L[j * 6 + k] * L[j * 6 + k];
+    if (!(d > 0.0)) return false;
+    L[j * 6 + j] = sqrt(d);
+    for (int i = j + 1; i < 6; ++i) {
+      double v = M[i * 6 + j];
+      for (int k = 0; k < j; ++k) v -= L[i * 6 + k] * L[j * 6 + k];
+      L[i * 6 + j] = v / L[j * 6 + j];
+    }
+  }
+  return true;
+}
+
 int check_problem(const ProblemIn& d) {
   int rc;
   if ((rc = check_grid(&d.grid))) return rc;
@@ -555,6 +641,9 @@ int check_problem(const ProblemIn& d) {
       if ((rc = check_phases(two))) return rc;
     }
     if (d.rule == HM_RULE_LAMINATE) return fail(HM_E_ARG, "the 2-layer rule is written for two phases");
+  } else if (d.aniso) {
+    for (int p = 0; p < 2; ++p)
+      if (!spd6(d.cm[p])) return fail(HM_E_ARG, "phase %d: the Mandel matrix must be symmetric positive definite", p);
   } else if ((rc = check_phases(d.phases))) {
     return rc;
   }
@@ -625,7 +714,21 @@ int upload_params(Group& g, const std::vector<ProblemIn>& all, const hm_solve_op
   for (int j = 0; j < np; ++j) {
     const ProblemIn& d = all[g.probs[j]];
     ProblemParams& q = PP[j];
-    if (d.cond) {
+    if (d.aniso) {
+      // reference c0 = 2 mu0 I with 2 mu0 = alpha (m + M) / 2 over the phases'
+      // Mandel eigenvalues (so c - c0 stays within (-c0, c0))
+      double lo = 0.0, hi = 0.0, l1 = 0.0, h1 = 0.0;
+      sym6_eig_range(d.cm[0], &lo, &hi);
+      sym6_eig_range(d.cm[1], &l1, &h1);
+      lo = fmin(lo, l1);
+      hi = fmax(hi, h1);
+      q.gen = 1;
+      q.rl = 0.0;
+      q.rm = opts->c0_alpha * 0.25 * (lo + hi);
+      if (opts->method == HM_CONJUGATE_GRADIENT) q.rm = 0.5;
+      for (int ph = 0; ph < 2; ++ph)
+        for (int i = 0; i < 36; ++i) q.cm[ph][i] = d.cm[ph][i];
+    } else if (d.cond) {
       // conductivities in pl, k0 = alpha * mean of the smallest and largest
       q.pl[0] = d.k[0];
       q.pl[1] = d.k[1];
@@ -708,6 +811,32 @@ int prepare_material(Group& g, const std::vector<ProblemIn>& all, const hm_solve
     // a multi-phase cell (solved alone) keeps its pure phases 2.. in the
     // first rows of the table
     const ProblemIn& d0 = all[g.probs[0]];
+    if (d0.aniso) {
+      // pure phases in rows 0 and 1: upper triangles of M_p - c0
+      if (g.probs.size() != 1) return fail(HM_E_ARG, "anisotropic cells are solved one at a time");
+      const ProblemParams* hq = reinterpret_cast<const ProblemParams*>(
+          p->prm_host + align16(align16(sizeof(SolveParams)) + g.loads.size() * sizeof(LoadParams)));
+      std::vector<double> rd(2 * kGenRow, 0.0);
+      std::vector<float> rf(2 * kGenRow, 0.0f);
+      for (int ph = 0; ph < 2; ++ph) {
+        int o = 0;
+        for (int I = 0; I < 6; ++I)
+          for (int J = I; J < 6; ++J) {
+            double v = 0.5 * (hq->cm[ph][I * 6 + J] + hq->cm[ph][J * 6 + I]);
+            if (I < 3 && J < 3) v -= hq->rl;
+            if (I == J) v -= 2.0 * hq->rm;
+            rd[ph * kGenRow + o] = v;
+            rf[ph * kGenRow + o] = (float)v;
+            ++o;
+          }
+      }
+      p->mcount_host[0] = 2;
+      p->mcount_host[1] = 0;
+      HM_HIP(hipMemcpyAsync(p->coef, p->fp64 ? (const void*)rd.data() : (const void*)rf.data(),
+                            (size_t)2 * kGenRow * (p->fp64 ? 8 : 4), hipMemcpyHostToDevice, s));
+      HM_HIP(hipMemcpyAsync(p->mcount, p->mcount_host, 2 * sizeof(int), hipMemcpyHostToDevice, s));
+      HM_HIP(hipStreamSynchronize(s));
+    }
     if (d0.nphase > 2) {
       if (g.probs.size() != 1) return fail(HM_E_ARG, "multi-phase cells are solved one at a time");
       const int nr = d0.nphase - 2;
@@ -735,9 +864,16 @@ int prepare_material(Group& g, const std::vector<ProblemIn>& all, const hm_solve
       const hm_grid& gr = all[g.probs[j]].grid;
       const int N = gr.n[0] * gr.n[1] * gr.n[2];
       const SolveParams* prm = reinterpret_cast<const SolveParams*>(p->prm);
-      const int cap = (int)std::min<size_t>(p->coef_cap, (size_t)1 << 30);
+      const size_t rw = p->aniso ? kGenRow / 8 : 1;  // row width in units of 8 reals
+      const int cap = (int)std::min<size_t>(p->coef_cap / rw, (size_t)1 << 30);
       const dim3 grid((N + 255) / 256), blk(256);
-      if (all[g.probs[j]].nphase && p->fp64)
+      if (p->aniso && p->fp64)
+        hipLaunchKernelGGL((k_material_aniso<double>), grid, blk, 0, s, prm, j, gr.n[0], gr.n[1], gr.n[2], gr.dim,
+                           p->mid + mo, static_cast<double*>(p->coef), cap, p->mcount);
+      else if (p->aniso)
+        hipLaunchKernelGGL((k_material_aniso<float>), grid, blk, 0, s, prm, j, gr.n[0], gr.n[1], gr.n[2], gr.dim,
+                           p->mid + mo, static_cast<float*>(p->coef), cap, p->mcount);
+      else if (all[g.probs[j]].nphase && p->fp64)
         hipLaunchKernelGGL((k_material_nphase<double>), grid, blk, 0, s, prm, j, gr.n[0], gr.n[1], gr.n[2],
                            p->mid + mo, static_cast<double*>(p->coef), cap, p->mcount);
       else if (all[g.probs[j]].nphase)
@@ -761,7 +897,7 @@ int prepare_material(Group& g, const std::vector<ProblemIn>& all, const hm_solve
     HM_HIP(hipMemcpyAsync(p->mcount_host, p->mcount, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HM_HIP(hipStreamSynchronize(s));
     if ((rc = data_flags_error(p->mcount_host[1]))) return rc;
-    const size_t rows = (size_t)p->mcount_host[0];
+    const size_t rows = (size_t)p->mcount_host[0] * (p->aniso ? kGenRow / 8 : 1);  // in units of 8 reals
     if (rows <= p->coef_cap) return HM_OK;
     // too small: grow (stays allocated for later solves), re-queue the
     // parameters with the new table address and build again
@@ -1015,8 +1151,8 @@ int run_groups(std::vector<Group>& G, const std::vector<ProblemIn>& all, const h
     if ((rc = ensure_hist(g.p, opts->max_iter + 1))) return rc;
     if ((rc = upload_params(g, all, opts, s))) return rc;
     if ((rc = prepare_material(g, all, opts, s))) return rc;
-    if (g.p->cond) {
-      // conduction plans have one compiled schedule
+    if (g.p->cond || g.p->aniso) {
+      // conduction and anisotropic plans have one compiled schedule
       if (opts->schedule >= 0 && opts->schedule != 0) return fail(HM_E_ARG, "conduction solves have one schedule");
     } else if (opts->autotune) {
       if (!g.p->tuned && (rc = tune_plan(g.p, s))) return rc;
@@ -1161,7 +1297,8 @@ int solve_one(const ProblemIn& d, const double* E, int n_load, const hm_solve_op
     if (!isfinite(E[i])) return fail(HM_E_ARG, "E has a non-finite entry");
   std::vector<ProblemIn> all{d};
   std::vector<Group> G(1);
-  if ((rc = get_plan(opts->prec == HM_FP64, d.grid.n, d.grid.dim, n_load, d.cond != 0, &G[0].p))) return rc;
+  const int phys = d.cond ? PHYS_CONDUCTION : (d.aniso ? PHYS_ANISO : PHYS_ELASTIC);
+  if ((rc = get_plan(opts->prec == HM_FP64, d.grid.n, d.grid.dim, n_load, phys, &G[0].p))) return rc;
   G[0].probs = {0};
   G[0].loads.resize(n_load);
   for (int l = 0; l < n_load; ++l) {
@@ -1188,7 +1325,7 @@ int solve_cond(const ProblemIn& d, const double* G, int n_load, const hm_solve_o
     if (!isfinite(G[i])) return fail(HM_E_ARG, "G has a non-finite entry");
   std::vector<ProblemIn> all{d};
   std::vector<Group> grp(1);
-  if ((rc = get_plan(opts->prec == HM_FP64, d.grid.n, d.grid.dim, n_load, true, &grp[0].p))) return rc;
+  if ((rc = get_plan(opts->prec == HM_FP64, d.grid.n, d.grid.dim, n_load, PHYS_CONDUCTION, &grp[0].p))) return rc;
   grp[0].probs = {0};
   grp[0].loads.resize(n_load);
   for (int l = 0; l < n_load; ++l) {
@@ -1286,6 +1423,67 @@ int upload_matrix(const std::vector<double>& K, int rows, int cols, bool transpo
 }  // namespace
 
 extern "C" {
+
+// An anisotropic two-phase cell as a ProblemIn.
+static ProblemIn aniso_problem(const hm_grid* grid, const double* C_phases, hm_rule rule, const void* d_frac,
+                               const int32_t* d_incl, const hm_sphere* spheres, int n_spheres) {
+  ProblemIn d = make_problem(grid, nullptr, rule, d_frac, d_incl, spheres, n_spheres);
+  d.aniso = 1;
+  if (C_phases)
+    for (int p = 0; p < 2; ++p)
+      for (int i = 0; i < 36; ++i) d.cm[p][i] = C_phases[36 * p + i];
+  return d;
+}
+
+int hm_solve_aniso(const hm_grid* grid, const double* C_phases, hm_rule rule, const void* d_frac,
+                   const int32_t* d_incl, const hm_sphere* spheres, int n_spheres, const double* E, int n_load,
+                   const hm_solve_opts* opts, void* d_eps, double* sig_mean, hm_report* rep, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!C_phases) return fail(HM_E_ARG, "C_phases is NULL");
+  if (!E || !sig_mean) return fail(HM_E_ARG, "E and sig_mean must not be NULL");
+  Plan* p = nullptr;
+  int rc = solve_one(aniso_problem(grid, C_phases, rule, d_frac, d_incl, spheres, n_spheres), E, n_load, opts,
+                     d_eps, (hipStream_t)stream, &p);
+  if (rc) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = HM_OK;
+  for (int l = 0; l < n_load; ++l) {
+    const SolverState& st = p->state_host[l];
+    for (int c = 0; c < 6; ++c) sig_mean[6 * l + c] = st.sig[c];
+    const int status = load_status(st);
+    if (rep) rep[l] = hm_report{st.iters, status, st.err, st.err0, secs};
+    worst = std::max(worst, status);
+  }
+  return worst;
+}
+
+int hm_effective_tensor_aniso(const hm_grid* grid, const double* C_phases, hm_rule rule, const void* d_frac,
+                              const int32_t* d_incl, const hm_sphere* spheres, int n_spheres,
+                              const hm_solve_opts* opts, double* C_mandel, void* d_eps, hm_report* rep,
+                              void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  int rc;
+  if ((rc = check_grid(grid))) return rc;
+  if (!C_phases) return fail(HM_E_ARG, "C_phases is NULL");
+  if (!C_mandel) return fail(HM_E_ARG, "C_mandel is NULL");
+  double E[36];
+  const int* idx = nullptr;
+  const int k = unit_loads(grid->dim, E, &idx);
+  Plan* p = nullptr;
+  rc = solve_one(aniso_problem(grid, C_phases, rule, d_frac, d_incl, spheres, n_spheres), E, k, opts, d_eps,
+                 (hipStream_t)stream, &p);
+  if (rc) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  assemble_mandel(k, idx, p->state_host, C_mandel);
+  int worst = HM_OK;
+  for (int l = 0; l < k; ++l) {
+    const SolverState& st = p->state_host[l];
+    const int status = load_status(st);
+    if (rep) rep[l] = hm_report{st.iters, status, st.err, st.err0, secs};
+    worst = std::max(worst, status);
+  }
+  return worst;
+}
 
 int hm_fourier_series(const hm_grid* grid, const int m[3], hm_prec prec, const void* d_field, void* d_out,
                       void* stream) {
@@ -1764,7 +1962,7 @@ int hm_effective_tensor_batch(const hm_problem* problems, int n_problems, const 
     const int k = unit_loads(d0.grid.dim, E, &idx);
     const int nl = k * (int)g.probs.size();
     if (nl > kMaxLoads) return fail(HM_E_ARG, "more than %d load cases on one grid", kMaxLoads);
-    if ((rc = get_plan(opts->prec == HM_FP64, d0.grid.n, d0.grid.dim, nl, false, &g.p))) return rc;
+    if ((rc = get_plan(opts->prec == HM_FP64, d0.grid.n, d0.grid.dim, nl, PHYS_ELASTIC, &g.p))) return rc;
     g.loads.resize(nl);
     for (int j = 0; j < (int)g.probs.size(); ++j)
       for (int J = 0; J < k; ++J) {

@@ -72,8 +72,12 @@ struct ProblemParams {
   // phases 1..nphase-1 in frac as [phase - 1][N]; table rows 0..nphase-3
   // hold the pure phases 2..nphase-1
   int nphase;
-  int pad;
+  int gen;  // 1: anisotropic phases, general table rows (see below)
   double ph_l[8], ph_m[8];
+  // anisotropic phases (gen = 1): Mandel matrices of the two phases,
+  // row-major; the table holds rows of 24 reals (upper triangle of
+  // c~ - c0, then padding), rows 0 and 1 the pure phases
+  double cm[2][36];
 };
 
 // One load case: its macroscopic strain (tensor components) and problem;

@@ -284,6 +284,46 @@ template <typename T> __device__ __forceinline__ void row_tau(bool aniso, const 
   apply_form<T>(c, e, tau);
 }
 
+// Polarization from a general (anisotropic) table row: the upper triangle,
+// row by row, of the Mandel matrix D = c~ - c0 (21 reals, then 3 of
+// padding); pure matrix (-1) and pure inclusion (-2) voxels use rows 0 and
+// 1.  tau = D e in Mandel form, e and tau as tensor components.
+constexpr int kGenRow = 24;
+template <typename T> __device__ __forceinline__ void gen_tau(const T* coef, int mv, const T e[6], T tau[6]) {
+  const int row = mv == -1 ? 0 : (mv == -2 ? 1 : mv);
+  const T* r = coef + (size_t)row * kGenRow;
+  T d[kGenRow];
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int i = 0; i < kGenRow / 4; ++i) {
+      const v4f u = load_global(reinterpret_cast<const v4f*>(r) + i);
+      d[4 * i] = u.x;
+      d[4 * i + 1] = u.y;
+      d[4 * i + 2] = u.z;
+      d[4 * i + 3] = u.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kGenRow / 2; ++i) {
+      const v2d u = load_global(reinterpret_cast<const v2d*>(r) + i);
+      d[2 * i] = u.x;
+      d[2 * i + 1] = u.y;
+    }
+  }
+  const T r2 = T(1.41421356237309504880), ir2 = T(0.70710678118654752440);
+  const T em[6] = {e[0], e[1], e[2], r2 * e[3], r2 * e[4], r2 * e[5]};
+  T sv[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int I = 0; I < 6; ++I)
+#pragma unroll
+    for (int J = 0; J < 6; ++J) {
+      const int a = I < J ? I : J, b = I < J ? J : I;
+      sv[I] += d[a * 6 - a * (a - 1) / 2 + (b - a)] * em[J];
+    }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) tau[c] = c < 3 ? sv[c] : ir2 * sv[c];
+}
+
 // ---------------------------------------------------------------- xsweep --
 // A block owns L consecutive (y, z) lines.  All of its global reads (the
 // six half-lines of each line and the material of its voxels) are issued
@@ -291,7 +331,9 @@ template <typename T> __device__ __forceinline__ void row_tau(bool aniso, const 
 // in flight at once.  Element loops give each wavefront whole rows (a
 // component pair of one line, or one line of voxels) with the lanes along
 // kx or x, so row indices are wave-uniform and need no per-lane division.
-template <typename T, int NX, int L, int NT, int MODE, int RMAX = max_radix<T>()>
+// GEN: general (anisotropic) material rows, gathered per voxel in the
+// polarization pass instead of before it.
+template <typename T, int NX, int L, int NT, int MODE, int RMAX = max_radix<T>(), bool GEN = false>
 __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
   constexpr int LL = 3 * L;
   constexpr int LD = LL | 1;  // odd row stride: element rows spread over the banks
@@ -397,10 +439,12 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
 
   // all table gathers of the thread's voxels first, then the polarizations
   T rows[RV][KX][8];
+  if constexpr (!GEN) {
 #pragma unroll
-  for (int i = 0; i < RV; ++i)
+    for (int i = 0; i < RV; ++i)
 #pragma unroll
-    for (int m = 0; m < KX; ++m) material_row<T>(MAT, mv[i][m], rows[i][m]);
+      for (int m = 0; m < KX; ++m) material_row<T>(MAT, mv[i][m], rows[i][m]);
+  }
   T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};  // thread partials, then FP64 block sums
 #pragma unroll
   for (int i = 0; i < RV; ++i) {
@@ -425,7 +469,10 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
       }
       T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
       if (line < nlines) {
-        row_tau<T>(MAT.aniso && mv[i][m] >= 0, rows[i][m], e, tau);
+        if constexpr (GEN)
+          gen_tau<T>(MAT.coef, mv[i][m], e, tau);
+        else
+          row_tau<T>(MAT.aniso && mv[i][m] >= 0, rows[i][m], e, tau);
 #pragma unroll
         for (int c = 0; c < 6; ++c) acc[c] += tau[c];
       }

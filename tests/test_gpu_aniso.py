@@ -1,0 +1,115 @@
+"""GPU parity of the anisotropic-phase path against oracle/aniso.py: an
+isotropic matrix with a rotated cubic inclusion under the Voigt, Reuss and
+2-layer rules; FP64 mean stress, error and strain field within 1e-10 at
+fixed iteration counts (the general 2-layer rows come from the block
+formula on the GPU and from the oracle's linear solve of eq. 5's
+conditions); tolerance stops in the same iteration; mixed precision within
+1e-5; isotropic phases through this path give the isotropic solver's
+tensor; conjugate gradients reach the same tensor; non-SPD phases are
+refused."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import COMPS, log, oracle_fields_to_comps, rel
+from oracle import aniso as A, filter as ofilter, rules, solver as osolver
+from workloads import lame, small_sphere_case
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _rot(seed):
+    q, r = np.linalg.qr(np.random.default_rng(seed).normal(size=(3, 3)))
+    return q * np.sign(np.diag(r))[None, :]
+
+
+C0 = rules.iso_tensor(*lame(1.0, 0.3))
+C1 = A.cubic_tensor(30.0, 12.0, 20.0, _rot(7))
+CM = np.stack([rules.to_mandel(C0), rules.to_mandel(C1)])
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import paper_1412_3228_amd as hm_mod
+    assert torch.cuda.is_available() and hm_mod.device_ok()
+    return hm_mod
+
+
+def _case(rule, n=(15, 9, 21)):
+    w = small_sphere_case(n=n, fraction=0.15, contrast=10.0, rule=rule, radius_vox=1.0, subsamples=4,
+                          offset=(0.25, 0.5, -0.75))
+    ff = ofilter.filter_field(w)
+    nrm = ofilter.interface_normals(w.n, 3, w.spheres, ff["incl"], ofilter.all_voxels(w.n)) if rule == "laminate" \
+        else None
+    return w, A.AnisoField(w.n, 3, [C0, C1], rule, ff["frac"], nrm)
+
+
+def _sig6(s):
+    return np.array([s[i, j] for (i, j) in COMPS])
+
+
+@pytest.mark.parametrize("rule", ["voigt", "reuss", "laminate"])
+@pytest.mark.parametrize("k", [0, 1, 5])
+def test_fixed_iterations_match_oracle(hm, rule, k):
+    log("aniso fixed iterations %s k=%d" % (rule, k))
+    w, fld = _case(rule)
+    _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", DEV)
+    E = np.array([[0.01, -0.004, 0.002, 0.001, -0.003, 0.005], [0.0, 0.0, 0.0, 0.0, 0.0, 0.01]])
+    out = hm.hm_solve_aniso(w.n, w.dim, CM, rule, frac, incl, w.spheres, E, prec="fp64", tol=0.0, max_iter=k,
+                            want_eps=True)
+    c0 = A.reference_medium([C0, C1])
+    for l in range(2):
+        r = osolver.solve(fld, E[l], c0, 0.0, k)
+        rep = out["reports"][l]
+        assert rep["iters"] == r["iters"] == k
+        assert rel(out["sig_mean"][l], _sig6(r["sig_mean"])) < 1e-10
+        assert abs(rep["err"] - r["err"]) <= 1e-10 * r["err"] + 1e-13
+        assert rel(out["eps"][l].cpu().numpy(), oracle_fields_to_comps(r["eps"])) < 1e-10
+
+
+@pytest.mark.parametrize("prec,tol,tol_c", [("fp64", 1e-6, 1e-9), ("mixed", 1e-4, 1e-5)])
+def test_effective_tensor_tolerance_stop(hm, prec, tol, tol_c):
+    log("aniso effective tensor %s" % prec)
+    w, fld = _case("laminate", n=(15, 15, 15))
+    _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, prec, DEV)
+    C, reps = osolver.effective_tensor(fld, A.reference_medium([C0, C1]), tol, 5000, 3)
+    out = hm.hm_effective_tensor_aniso(w.n, w.dim, CM, "laminate", frac, incl, w.spheres, prec=prec, tol=tol,
+                                       max_iter=5000, use_graph=True, check_every=4)
+    assert out["status"] == 0
+    assert rel(out["C"], C) < tol_c
+    if prec == "fp64":
+        assert [r["iters"] for r in out["reports"]] == [r["iters"] for r in reps]
+
+
+def test_isotropic_phases_give_the_isotropic_tensor(hm):
+    w = small_sphere_case(n=(15, 9, 21), fraction=0.15, contrast=10.0, rule="laminate", radius_vox=1.0, subsamples=4)
+    _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", DEV)
+    cm = np.stack([rules.to_mandel(rules.iso_tensor(*p)) for p in w.phases])
+    a = hm.hm_effective_tensor_aniso(w.n, w.dim, cm, "laminate", frac, incl, w.spheres, tol=1e-10, max_iter=20000,
+                                     check_every=16, use_graph=True)
+    b = hm.hm_effective_tensor(w.n, w.dim, w.phases, "laminate", frac, incl, w.spheres, tol=1e-10, max_iter=20000,
+                               check_every=16, use_graph=True)
+    assert a["status"] == 0 and b["status"] == 0
+    assert rel(a["C"], b["C"]) < 1e-8
+
+
+def test_conjugate_gradients_reach_the_fixed_point_tensor(hm):
+    w, _ = _case("reuss")
+    _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", DEV)
+    fp = hm.hm_effective_tensor_aniso(w.n, w.dim, CM, "reuss", frac, incl, w.spheres, tol=1e-10, max_iter=20000,
+                                      check_every=16, use_graph=True)
+    cg = hm.hm_effective_tensor_aniso(w.n, w.dim, CM, "reuss", frac, incl, w.spheres, tol=1e-10, max_iter=3000,
+                                      method="cg", check_every=8, use_graph=True)
+    assert fp["status"] == 0 and cg["status"] == 0
+    assert rel(cg["C"], fp["C"]) < 1e-7
+
+
+def test_non_spd_phase_is_refused(hm):
+    w, _ = _case("voigt", n=(9, 9, 9))
+    _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", DEV)
+    bad = CM.copy()
+    bad[1, 3, 3] = -1.0
+    with pytest.raises(hm.HmError) as e:
+        hm.hm_effective_tensor_aniso(w.n, w.dim, bad, "voigt", frac, incl, w.spheres, max_iter=2)
+    assert e.value.code == -1
