@@ -44,8 +44,8 @@ METRIC = "voxel-iterations/s of LS fixed point, mixed vs FP64 at equal C_eff err
 CONTRASTS = (100.0, 0.01)
 
 
-KERNEL_SOURCES = ("hm_solve_kernels.hpp", "hm_conduct_kernels.hpp", "hm_fft.hpp", "hm_material.hpp",
-                  "hm_common.hpp")
+KERNEL_SOURCES = ("hm_solve_kernels.hpp", "hm_conduct_kernels.hpp", "hm_aniso_kernels.hpp", "hm_fft.hpp",
+                  "hm_material.hpp", "hm_common.hpp", "hm_extrapolate.hip")
 PROFILE_GLOB = os.path.join(ROOT, "profiles", "hbm_traffic_*.txt")
 
 
@@ -136,14 +136,15 @@ def _sync():
     torch.cuda.synchronize()
 
 
-def kernel_bytes(n, prec, kernel, n_frac=0, nc=6, nh=3):
+def kernel_bytes(n, prec, kernel, n_frac=0, nc=6, nh=3, row_reals=8):
     """Algorithmic HBM bytes of one launch of `kernel` for ONE load case.
 
     The stored state is the x-half-spectrum: nc components (6 strain, or 3
     gradient components for conduction) x nz x ny x H complex values
     (H = (nx + 1) / 2).  xsweep reads and writes it and reads the material:
     a 4-byte id per voxel and, for each of the n_frac fractional voxels, its
-    8-real row of the material table; each ysweep reads and writes the
+    row of the material table (8 reals, 24 for anisotropic phases); each
+    ysweep reads and writes the
     spectrum; zsweep also reads and writes the nh-component history
     (3 traction components, or 1 for conduction).
     """
@@ -153,7 +154,7 @@ def kernel_bytes(n, prec, kernel, n_frac=0, nc=6, nh=3):
     plane = nz * ny * H
     spec = 2 * nc * plane * cb
     if kernel == "xsweep":
-        return spec + nx * ny * nz * 4 + n_frac * 8 * (cb // 2)
+        return spec + nx * ny * nz * 4 + n_frac * row_reals * (cb // 2)
     if kernel in ("ysweep_fwd", "ysweep_inv"):
         return spec
     if kernel == "zsweep":
@@ -183,7 +184,7 @@ def run_path(hm, w, prec, contrast, dev, profile=True, C_target=None, max_iter=5
             "dLdphase": dph}
 
 
-def roofline(timings, n, prec, reports, n_frac=0, nc=6, nh=3, n_load=6):
+def roofline(timings, n, prec, reports, n_frac=0, nc=6, nh=3, n_load=6, row_reals=8):
     """Dominant kernel of the profiled solves, its algorithmic bandwidth vs peak."""
     tot = {}
     for t in timings:
@@ -194,7 +195,7 @@ def roofline(timings, n, prec, reports, n_frac=0, nc=6, nh=3, n_load=6):
     its = sum(t["iterations"] for t in timings)
     active = sum(sum(r["iters"] + 1 for r in rep) for rep in reports) / max(1, its)
     ms = tot[dom] / its
-    bytes_launch = kernel_bytes(n, prec, dom, n_frac, nc, nh) * active
+    bytes_launch = kernel_bytes(n, prec, dom, n_frac, nc, nh, row_reals) * active
     achieved = bytes_launch / (ms * 1e-3) / 1e9
     key = timings[-1]["kernels"][dom]
     tr = measured_traffic(key)
@@ -265,6 +266,49 @@ def conduction(hm, works, dev, n_frac):
         n = next(iter(works.values())).n
         out[prec] = {"value": vit / secs, "unit": "voxel-iterations/s", "seconds": secs, "solves": K,
                      "roofline": roofline(timings, n, prec, reps, n_frac, nc=3, nh=1, n_load=3)}
+    return out
+
+
+def phase_cells(hm, dev):
+    """Anisotropic-phase (cubic inclusion, 2-layer rule) and three-phase
+    (Voigt) 125^3 cells: profiled six-load solves to tol 1e-4 per path,
+    voxel-iterations per second and the roofline of the dominant sweep, with
+    the x-sweep's share.  Untimed context beside the metric."""
+    from workloads import workload_aniso, workload_nphase
+    out = {}
+    for name, w in (("aniso", workload_aniso()), ("nphase", workload_nphase())):
+        row = {}
+        for prec in ("fp64", "mixed"):
+            if name == "aniso":
+                _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, prec, dev)
+                n_frac = int(((frac > 0) & (frac < 1)).sum().item())
+
+                def solve(**kw):
+                    return hm.hm_effective_tensor_aniso(w.n, 3, w.meta["C_mandel"], w.rule, frac, incl, w.spheres,
+                                                        **kw)
+            else:
+                _, frac = hm.hm_filter_phases(w.n, 3, w.spheres, w.meta["labels"], 3, w.radius_vox, w.subsamples,
+                                              w.rule, prec, dev)
+                n_frac = int((((frac > 0) & (frac < 1)).any(dim=0)).sum().item())
+
+                def solve(**kw):
+                    return hm.hm_effective_tensor_phases(w.n, 3, w.meta["phases"], w.rule, frac, **kw)
+            kw = dict(prec=prec, tol=w.tol, max_iter=5000, check_every=16, stall_window=(20 if prec == "mixed" else 0))
+            solve(**kw)  # plan warm
+            _sync()
+            t0 = time.perf_counter()
+            o = solve(profile=True, **kw)
+            _sync()
+            secs = time.perf_counter() - t0
+            t = hm.last_timing()
+            vit = sum(r["iters"] + 1 for r in o["reports"]) * w.nvox
+            rf = roofline([t], w.n, prec, [o["reports"]], n_frac, row_reals=(24 if name == "aniso" else 8))
+            row[prec] = {"value": vit / secs, "unit": "voxel-iterations/s", "seconds": secs,
+                         "iters": [r["iters"] for r in o["reports"]], "status": [r["status"] for r in o["reports"]],
+                         "C_diag": [float(v) for v in np.diag(o["C"])], "xsweep_ms": t["ms"]["xsweep"],
+                         "xsweep_instance": t["kernels"]["xsweep"], "roofline": rf}
+            del frac
+        out[name] = row
     return out
 
 
@@ -406,6 +450,17 @@ def main():
         for _ in range(3):
             hm.hm_fourier_series(w.n, 3, c11, (375, 375, 375))
         print(json.dumps({"kernel_pass": "fourier series 125^3 -> 375^3"}), flush=True)
+        from workloads import workload_aniso, workload_nphase
+        wa, wn = workload_aniso(), workload_nphase()
+        for prec in ("fp64", "mixed"):
+            _, frac, incl = hm.hm_filter(wa.n, 3, wa.spheres, wa.radius_vox, wa.subsamples, wa.rule, prec, dev)
+            hm.hm_effective_tensor_aniso(wa.n, 3, wa.meta["C_mandel"], wa.rule, frac, incl, wa.spheres, prec=prec,
+                                         tol=0.0, max_iter=9, check_every=10, profile=True)
+            _, frac = hm.hm_filter_phases(wn.n, 3, wn.spheres, wn.meta["labels"], 3, wn.radius_vox, wn.subsamples,
+                                          wn.rule, prec, dev)
+            hm.hm_effective_tensor_phases(wn.n, 3, wn.meta["phases"], wn.rule, frac, prec=prec, tol=0.0, max_iter=9,
+                                          check_every=10, profile=True)
+            print(json.dumps({"kernel_pass": "anisotropic and three-phase cells " + prec}), flush=True)
         # calibration copy of a known size for the rocprofv3 byte counters
         x = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
         y = torch.empty_like(x)
@@ -493,6 +548,7 @@ def main():
     line["time_to_solution"] = time_to_solution(hm, works, ref, dev)
     line["conduction"] = conduction(hm, works, dev, n_frac)
     line["fourier_series"] = series(hm, works[CONTRASTS[0]], dev)
+    line["phase_cells"] = phase_cells(hm, dev)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
         line["conduction"]["cpu_baseline"] = conduction_cpu_baseline(iters=8)

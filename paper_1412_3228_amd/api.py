@@ -260,7 +260,7 @@ def hm_solve_phases(n, dim, phases, rule: str, frac: torch.Tensor, E, prec: str 
 def hm_effective_tensor_phases(n, dim, phases, rule: str, frac: torch.Tensor, prec: str = "fp64",
                                tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
                                check_every: int = 1, stall_window: int = 0, use_graph: bool = False,
-                               method: str = "fixed_point"):
+                               method: str = "fixed_point", profile: bool = False):
     """Effective Mandel tensor of a cell of len(phases) phases."""
     dev = frac.device
     N = int(n[0] * n[1] * n[2])
@@ -269,7 +269,7 @@ def hm_effective_tensor_phases(n, dim, phases, rule: str, frac: torch.Tensor, pr
     C = np.zeros((k, k))
     rep = (L.HmReport * k)()
     g = _grid(n, dim)
-    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, False, False, None, method)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, False, None, method)
     rc = _lib().hm_effective_tensor_phases(ctypes.byref(g), _phase_array(phases), len(phases), L.RULES[rule],
                                            _ptr(frac), ctypes.byref(o), C.ctypes.data_as(L._dp), None, rep,
                                            _stream(dev))
@@ -310,7 +310,7 @@ def hm_solve_aniso(n, dim, C_phases, rule: str, frac: torch.Tensor, incl: Option
 def hm_effective_tensor_aniso(n, dim, C_phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor],
                               spheres, prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000,
                               c0_alpha: float = 1.0, check_every: int = 1, stall_window: int = 0,
-                              use_graph: bool = False, method: str = "fixed_point"):
+                              use_graph: bool = False, method: str = "fixed_point", profile: bool = False):
     """Effective Mandel tensor for two anisotropic phases."""
     dev = frac.device
     N = int(n[0] * n[1] * n[2])
@@ -322,7 +322,7 @@ def hm_effective_tensor_aniso(n, dim, C_phases, rule: str, frac: torch.Tensor, i
     rep = (L.HmReport * k)()
     g = _grid(n, dim)
     sph, ns = _spheres(spheres)
-    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, False, False, None, method)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, False, None, method)
     rc = _lib().hm_effective_tensor_aniso(ctypes.byref(g), Cp.ctypes.data_as(L._dp), L.RULES[rule], _ptr(frac),
                                           _ptr(incl), sph, ns, ctypes.byref(o), C.ctypes.data_as(L._dp), None, rep,
                                           _stream(dev))

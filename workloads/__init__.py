@@ -22,4 +22,9 @@ from .microstructures import (  # noqa: F401
     fig1_disk_case,
     FIG1_RESOLUTIONS,
     FIG1_DISK_RADIUS,
+    workload_aniso,
+    workload_nphase,
+    cubic_mandel,
+    iso_mandel,
+    rotation_from_seed,
 )

@@ -349,3 +349,91 @@ def fig1_disk_case(n: int, contrast: float, rule: str = "none", radius_vox: floa
         tol=1e-4,
         meta={"contrast": contrast},
     )
+
+
+def rotation_from_seed(seed: int) -> np.ndarray:
+    """A seeded proper rotation (3x3, columns orthonormal, det +1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+    q = q * np.sign(np.diag(r))[None, :]
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+_MANDEL_PAIRS = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))
+
+
+def cubic_mandel(c11: float, c12: float, c44: float, R=None) -> np.ndarray:
+    """Mandel 6x6 matrix of a cubic crystal (Voigt constants C11, C12, C44)
+    whose cube axes are the columns of R (the identity when R is None)."""
+    c = np.zeros((3, 3, 3, 3))
+    for i in range(3):
+        for j in range(3):
+            c[i, i, j, j] = c11 if i == j else c12
+            if i != j:
+                c[i, j, i, j] = c[i, j, j, i] = c44
+    if R is not None:
+        c = np.einsum("ai,bj,ck,dl,ijkl->abcd", R, R, R, R, c)
+    w = np.array([1.0, 1.0, 1.0, math.sqrt(2.0), math.sqrt(2.0), math.sqrt(2.0)])
+    m = np.zeros((6, 6))
+    for A, (i, j) in enumerate(_MANDEL_PAIRS):
+        for B, (k, l) in enumerate(_MANDEL_PAIRS):
+            m[A, B] = w[A] * w[B] * c[i, j, k, l]
+    return m
+
+
+def iso_mandel(lam: float, mu: float) -> np.ndarray:
+    """Mandel 6x6 matrix of an isotropic phase."""
+    m = np.zeros((6, 6))
+    m[:3, :3] = lam
+    m += 2.0 * mu * np.eye(6)
+    return m
+
+
+def workload_aniso(n: int = 125, seed: int = 8) -> Workload:
+    """The n^3 centred-sphere cell (fraction 0.25) with an isotropic matrix
+    (E = 1, nu = 0.3) and a cubic inclusion (C11, C12, C44 = 30, 12, 20)
+    whose cube axes take a seeded rotation; 2-layer filter r = 1 voxel with
+    8^3 sub-samples, six unit loads, tol 1e-4.  meta["C_mandel"] holds the
+    two phase Mandel matrices."""
+    cm = np.stack([iso_mandel(*lame(1.0, 0.3)), cubic_mandel(30.0, 12.0, 20.0, rotation_from_seed(seed))])
+    return Workload(
+        name="aniso-3d-%d-cubic-sphere" % n,
+        dim=3,
+        n=(n, n, n),
+        spheres=centred_inclusion(n, 3, 0.25),
+        phases=(lame(1.0, 0.3), lame(1.0, 0.3)),
+        radius_vox=1.0,
+        subsamples=8,
+        rule="laminate",
+        loads=_unit_mandel_loads(3),
+        tol=1e-4,
+        meta={"C_mandel": cm, "seed": seed},
+    )
+
+
+def workload_nphase(seed: int = 6, n: int = 125, count: int = 20, rule: str = "voigt") -> Workload:
+    """Three-phase n^3 cell: `count` seeded non-overlapping spheres (radii
+    U[10, 16] voxels, surfaces 2 voxels apart) labelled alternately 1 and 2;
+    phases E = 1 (matrix), 20 and 0.05, nu = 0.3; filter r = 1 voxel with
+    8^3 sub-samples; six unit loads, tol 1e-4.  meta["labels"] holds the
+    sphere labels and meta["phases"] the three Lame pairs."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    radii = rng.uniform(10.0, 16.0, size=count)
+    sph = rsa_spheres(rng, (n, n, n), radii, gap=2.0)
+    labels = np.array([1 + (i % 2) for i in range(sph.shape[0])], dtype=np.int32)
+    phases = [lame(1.0, 0.3), lame(20.0, 0.3), lame(0.05, 0.3)]
+    return Workload(
+        name="nphase-3d-%d-%dspheres" % (n, count),
+        dim=3,
+        n=(n, n, n),
+        spheres=sph,
+        phases=(phases[0], phases[1]),
+        radius_vox=1.0,
+        subsamples=8,
+        rule=rule,
+        loads=_unit_mandel_loads(3),
+        tol=1e-4,
+        meta={"labels": labels, "phases": phases, "seed": seed},
+    )
