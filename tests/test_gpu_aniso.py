@@ -113,3 +113,29 @@ def test_non_spd_phase_is_refused(hm):
     with pytest.raises(hm.HmError) as e:
         hm.hm_effective_tensor_aniso(w.n, w.dim, bad, "voigt", frac, incl, w.spheres, max_iter=2)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("rule", ["reuss", "laminate"])
+def test_2d_disk_matches_oracle(hm, rule):
+    # plane strain: a one-voxel-thick cell, disk of the rotated cubic phase
+    w = small_sphere_case(n=(25, 15, 1), dim=2, fraction=0.3, contrast=10.0, rule=rule, radius_vox=1.0,
+                          subsamples=8, offset=(0.3, -0.2, 0.0))
+    ff = ofilter.filter_field(w)
+    nrm = ofilter.interface_normals(w.n, 2, w.spheres, ff["incl"], ofilter.all_voxels(w.n)) if rule == "laminate" \
+        else None
+    fld = A.AnisoField(w.n, 2, [C0, C1], rule, ff["frac"], nrm)
+    C, reps = osolver.effective_tensor(fld, A.reference_medium([C0, C1]), 0.0, 7, 2)
+    _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", DEV)
+    out = hm.hm_effective_tensor_aniso(w.n, 2, CM, rule, frac, incl, w.spheres, tol=0.0, max_iter=7)
+    assert out["C"].shape == (3, 3)
+    assert rel(out["C"], C) < 1e-10
+
+
+def test_interface_free_cell_is_the_phase_tensor(hm):
+    # every voxel pure (no filter, inclusion fills the cell): C_eff is the
+    # inclusion's own Mandel matrix after the first iterate
+    n = (9, 9, 9)
+    frac = torch.ones(9 * 9 * 9, dtype=torch.float64, device=DEV)
+    out = hm.hm_effective_tensor_aniso(n, 3, CM, "none", frac, None, np.zeros((0, 4)), tol=1e-12, max_iter=5)
+    assert out["status"] == 0
+    assert rel(out["C"], CM[1]) < 1e-13

@@ -117,3 +117,17 @@ def test_bad_input_is_refused(hm):
     with pytest.raises(hm.HmError) as e:
         hm.hm_effective_tensor_phases(N_CELL, 3, PH4, "none", frac, max_iter=2)
     assert e.value.code == -5
+
+
+def test_2d_cell_and_an_unused_phase(hm):
+    # plane strain, four phases of which label 3 has no inclusion
+    n = (21, 15, 1)
+    sph = np.array([[5.0, 4.0, 0.5, 3.2], [15.0, 10.5, 0.5, 3.6], [14.5, 3.0, 0.5, 2.1]])
+    lab = np.array([1, 2, 1])
+    cnt, frac = hm.hm_filter_phases(n, 2, sph, lab, 4, 1.0, 8, "voigt", "fp64", DEV)
+    ref, M = NP.phase_counts(n, 2, sph, lab, 4, 1.0, 8)
+    assert np.array_equal(cnt.cpu().numpy(), ref) and not ref[2].any()
+    fld = NP.NPhaseField(n, 2, PH4, "voigt", NP.fractions(ref, M))
+    C, _ = osolver.effective_tensor(fld, NP.reference_medium(PH4), 0.0, 6, 2)
+    out = hm.hm_effective_tensor_phases(n, 2, PH4, "voigt", frac, tol=0.0, max_iter=6)
+    assert rel(out["C"], C) < 1e-10
