@@ -24,7 +24,8 @@ namespace hm {
 
 constexpr int kPassThreads = 256;
 constexpr int kLinePass = 8;    // lines per block of the contiguous pass
-constexpr int kStridedOut = 32; // outputs per thread of the strided pass
+constexpr int kStridedOut = 16; // outputs per thread of the strided pass
+constexpr int kStridedCols = 2; // columns per thread of the strided pass
 
 // Contiguous lines (I == 1): a block stages kLinePass input lines in LDS and
 // its threads run along the outputs j'; the matrix is read transposed
@@ -57,35 +58,49 @@ __global__ __launch_bounds__(kPassThreads) void k_series_lines(const T* in, T* o
 }
 
 // Strided axis (I > 1): threads run along i (coalesced), each computes
-// kStridedOut consecutive outputs j'.  The matrix entries are the same for
-// every thread of the block, so they are read through the scalar cache
-// (read-only, no aliasing) and each loaded input value feeds kStridedOut
-// multiply-adds; the input is re-read once per block of outputs.
+// kStridedOut consecutive outputs j' for kStridedCols columns i (256 apart,
+// so every load stays coalesced).  The matrix entries are the same for every
+// thread of the block, so they are read through the scalar cache (read-only,
+// no aliasing) and each one feeds kStridedCols multiply-adds; each loaded
+// input value feeds kStridedOut.  (Tile measured on the 125^3 -> 375^3
+// series: 16 x 2 beat 32 x 1, 16 x 1, 8 x 4, 16 x 4 and 12 x 3.)
 template <typename T>
 __global__ __launch_bounds__(kPassThreads) void k_series_strided(const T* __restrict__ in, T* __restrict__ out,
                                                                  const T* __restrict__ K, long long I, int n,
                                                                  int mj) {
-  const long long i = (long long)blockIdx.x * kPassThreads + threadIdx.x;
+  const long long ib = (long long)blockIdx.x * kPassThreads * kStridedCols + threadIdx.x;
   const int j0 = blockIdx.y * kStridedOut;
   const long long o = blockIdx.z;
-  if (i >= I) return;
-  T acc[kStridedOut];
+  bool ok[kStridedCols];
 #pragma unroll
-  for (int t = 0; t < kStridedOut; ++t) acc[t] = T(0);
-  const T* src = in + (size_t)o * n * I + i;
+  for (int c = 0; c < kStridedCols; ++c) ok[c] = ib + (long long)kPassThreads * c < I;
+  T acc[kStridedOut][kStridedCols];
+#pragma unroll
+  for (int t = 0; t < kStridedOut; ++t)
+#pragma unroll
+    for (int c = 0; c < kStridedCols; ++c) acc[t][c] = T(0);
+  const T* src = in + (size_t)o * n * I + ib;
   // rows past mj repeat the last row (their results are not stored)
   const T* kr = K + (size_t)j0 * n;
   const int tmax = mj - 1 - j0;
 #pragma unroll 2
   for (int j = 0; j < n; ++j) {
-    const T v = src[(size_t)j * I];
+    T v[kStridedCols];
 #pragma unroll
-    for (int t = 0; t < kStridedOut; ++t) acc[t] += kr[(size_t)(t < tmax ? t : tmax) * n + j] * v;
+    for (int c = 0; c < kStridedCols; ++c) v[c] = ok[c] ? src[(size_t)j * I + kPassThreads * c] : T(0);
+#pragma unroll
+    for (int t = 0; t < kStridedOut; ++t) {
+      const T k = kr[(size_t)(t < tmax ? t : tmax) * n + j];
+#pragma unroll
+      for (int c = 0; c < kStridedCols; ++c) acc[t][c] += k * v[c];
+    }
   }
-  T* dst = out + (size_t)o * mj * I + i;
+  T* dst = out + (size_t)o * mj * I + ib;
 #pragma unroll
   for (int t = 0; t < kStridedOut; ++t)
-    if (j0 + t < mj) dst[(size_t)(j0 + t) * I] = acc[t];
+#pragma unroll
+    for (int c = 0; c < kStridedCols; ++c)
+      if (j0 + t < mj && ok[c]) dst[(size_t)(j0 + t) * I + kPassThreads * c] = acc[t][c];
 }
 
 template <typename T> hipError_t series_pass(const AxisPass& p, hipStream_t s) {
@@ -97,7 +112,8 @@ template <typename T> hipError_t series_pass(const AxisPass& p, hipStream_t s) {
     hipLaunchKernelGGL((k_series_lines<T>), grid, dim3(kPassThreads), (size_t)kLinePass * p.n * sizeof(T), s, in, out,
                        K, p.O, p.n, p.mj);
   } else {
-    const dim3 grid((unsigned)((p.I + kPassThreads - 1) / kPassThreads), (unsigned)((p.mj + kStridedOut - 1) / kStridedOut),
+    const long long cols = (long long)kPassThreads * kStridedCols;
+    const dim3 grid((unsigned)((p.I + cols - 1) / cols), (unsigned)((p.mj + kStridedOut - 1) / kStridedOut),
                     (unsigned)p.O);
     hipLaunchKernelGGL((k_series_strided<T>), grid, dim3(kPassThreads), 0, s, in, out, K, p.I, p.n, p.mj);
   }
