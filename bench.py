@@ -59,6 +59,9 @@ def kernel_source_hash():
 
 
 def _short(name):
+    # a defaulted trailing bool template argument is left out of instance
+    # names when false and written as 1 when true
+    name = name.replace(", false>", ">").replace(", true>", ", 1>")
     m = re.search(r"k_(\w+?)<(double|float), (\d+)((?:, -?\d+)*)>", name)
     if m:
         return "%s<%s,%s%s>" % (m.group(1), m.group(2), m.group(3), m.group(4).replace(" ", ""))
