@@ -367,7 +367,7 @@ __global__ __launch_bounds__(NT) void k_czsweep(SolveArgs a) {
 // x: 8 lines per block while the tile fits in 56 KB of LDS, else fewer
 template <typename T, int N> struct CXTile {
   static constexpr int fits(int L) { return N * (((3 * L) / 2) | 1) * (int)sizeof(cx<T>) <= 56 * 1024; }
-  static constexpr int L = fits(8) ? 8 : (fits(4) ? 4 : 2);
+  static constexpr int L = (sizeof(T) == 4 && fits(16)) ? 16 : (fits(8) ? 8 : (fits(4) ? 4 : 2));
   static constexpr int NT = 256;
 };
 // y: the elastic 256-byte tile (YTile variant 1); z: 128-byte tiles with at
