@@ -351,6 +351,62 @@ def series(hm, w, dev, m=(375, 375, 375)):
                          "note": "whole call (three passes and three matrix uploads of <400 KB each)"}}
 
 
+def phase_cells_cpu_baseline():
+    """The oracle on bounded samples of the anisotropic and three-phase
+    cells: two fixed-point evaluations of one load case on the full 125^3
+    grid each (FP64, field construction not timed).  The anisotropic field
+    uses the oracle's counts on the interface band (pure voxels elsewhere);
+    the three-phase field uses the phase indicator at the voxel centres (the
+    per-iteration arithmetic does not depend on the fraction values)."""
+    from oracle import aniso as A, filter as ofilter, nphase as NP, rules, solver as osolver
+    from workloads import workload_aniso, workload_nphase
+    out = {}
+    w = workload_aniso()
+    vox = ofilter.all_voxels(w.n)
+    d = np.linalg.norm(vox + 0.5 - w.spheres[0, :3], axis=1)
+    R = w.spheres[0, 3]
+    band = np.abs(d - R) <= w.radius_vox + 2.0
+    frac = (d < R).astype(np.float64)
+    cnt, M = ofilter.counts_at(w.n, 3, w.spheres, w.radius_vox, w.subsamples, vox[band])
+    frac[band] = cnt / M
+    incl = np.where((frac > 0) & (frac < 1), 0, -1)
+    nrm = ofilter.interface_normals(w.n, 3, w.spheres, incl, vox)
+    cph = [rules.from_mandel(w.meta["C_mandel"][0]), rules.from_mandel(w.meta["C_mandel"][1])]
+    fields = {"aniso": (A.AnisoField(w.n, 3, cph, w.rule, frac, nrm), A.reference_medium(cph), w)}
+    v = workload_nphase()
+    vox = ofilter.all_voxels(v.n)
+    fr = np.zeros((2, vox.shape[0]))
+    for k, sp in enumerate(v.spheres):
+        dd = vox + 0.5 - sp[:3]
+        dd -= np.array(v.n) * np.round(dd / np.array(v.n))
+        fr[v.meta["labels"][k] - 1][np.sum(dd * dd, axis=1) <= sp[3] ** 2] = 1.0
+    fields["nphase"] = (NP.NPhaseField(v.n, 3, v.meta["phases"], "voigt", fr), NP.reference_medium(v.meta["phases"]), v)
+    for name, (fld, c0, wk) in fields.items():
+        w0, c0t = time.perf_counter(), time.process_time()
+        r = osolver.solve(fld, wk.loads[0], c0, 0.0, 1)
+        wall = time.perf_counter() - w0
+        cpu = time.process_time() - c0t
+        out[name] = {"value": (r["iters"] + 1) * wk.nvox / wall, "unit": "voxel-iterations/s",
+                     "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
+                     "sample": "2 fixed-point evaluations of one load case on the full 125^3 grid, FP64; %.1f s wall"
+                               % wall}
+    return out
+
+
+def series_cpu_baseline(points=200):
+    """The extrapolation oracle on a sample: the series of a 125^3 field at
+    `points` fine-grid points (explicit sums over J), points per second."""
+    from oracle import extrapolate as X
+    c = np.random.default_rng(1).random((125, 125, 125))
+    pts = (np.random.default_rng(2).integers(0, 375, size=(points, 3)) + 0.5) / 375.0
+    w0, c0t = time.perf_counter(), time.process_time()
+    X.evaluate(X.coefficients(c), pts)
+    wall = time.perf_counter() - w0
+    cpu = time.process_time() - c0t
+    return {"value": points / wall, "unit": "points/s", "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
+            "sample": "%d points of the 125^3 -> 375^3 series, FP64; %.1f s wall" % (points, wall)}
+
+
 def conduction_cpu_baseline(iters=1):
     """The conduction oracle timed on a bounded sample: iterations of one
     unit gradient on the full 125^3 cell, FP64."""
@@ -555,6 +611,11 @@ def main():
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
         line["conduction"]["cpu_baseline"] = conduction_cpu_baseline(iters=8)
+        fs = line["fourier_series"]
+        fs["cpu_baseline"] = series_cpu_baseline()
+        fs["gpu_points_per_s"] = float(np.prod(fs["fine_grid"])) / (fs["ms_per_call"] * 1e-3)
+        for name, b in phase_cells_cpu_baseline().items():
+            line["phase_cells"][name]["cpu_baseline"] = b
     print(json.dumps(line), flush=True)
 
 
