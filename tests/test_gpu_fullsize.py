@@ -9,6 +9,10 @@
 * 243^3 cell with 40 spheres: sampled voxels against the oracle's counts
   (radius 1 and 2), and properties of the batched six-load solves that hold
   at any size (symmetry, phase bounds, mixed vs FP64 agreement).
+* 125^3 centred sphere in the launch configuration bench.py times (mixed,
+  autotuned, profiled, poll every 16, stall window 20): two iterations of
+  six loads against the oracle within 1e-5, and the converged tensor within
+  1e-5 of the tight FP64 one, cubic, and inside the Voigt / Reuss bounds.
 * 135^3 cell with 25 spheres: the adjoint gradient against central finite
   differences (step 1e-4) of tightly converged solves, and through the
   torch.autograd.Function.
@@ -176,3 +180,41 @@ def test_c5_autograd_function_and_mixed_gradient(hm):
     d32, f32 = hm.hm_solve_adjoint(w.n, 3, w.phases, w.rule, frac32, incl32, w.spheres, G, m["eps"], prec="mixed")
     log("mixed vs fp64 gradient: phases %.2e" % rel(d32, dph))
     assert rel(d32, dph) < 1e-4
+
+
+def test_c2_bench_configuration_mixed(hm):
+    # the launch configuration bench.py times: mixed precision, autotuned
+    # schedule, profiled direct launches, host poll every 16 iterations,
+    # stall window 20; first iterates against the oracle, then the
+    # converged tensor against the tight FP64 solve and the bounds
+    w = workload_c2(100.0)
+    cnt_o, frac_o, incl_o, M = band_oracle_filter(w)
+    _, f32, i32 = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "mixed", DEV)
+    log("c2 bench config: two iterations, six loads, against the oracle")
+    out = hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, f32, i32, w.spheres, prec="mixed", tol=0.0,
+                                 max_iter=2, check_every=16, stall_window=20, profile=True)
+    nrm = ofilter.interface_normals(w.n, 3, w.spheres, incl_o, ofilter.all_voxels(w.n))
+    fld = osolver.StiffnessField(w.n, 3, w.phases, w.rule, cnt_o.astype(np.float32) / np.float32(M), nrm)
+    c0 = osolver.reference_medium(w.phases)
+    for J in (0, 5):
+        r = osolver.solve(fld, osolver.unit_mandel_strains(3)[J], c0, 0.0, 2)
+        col = osolver.mandel_vector(r["sig_mean"], 3)
+        assert np.max(np.abs(out["C"][:, J] - col)) < 1e-5 * np.max(np.abs(col))
+    log("c2 bench config: converged")
+    mixed = hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, f32, i32, w.spheres, prec="mixed", tol=w.tol,
+                                   max_iter=5000, check_every=16, stall_window=20, profile=True)
+    _, f64, i64 = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", DEV)
+    tight = hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, f64, i64, w.spheres, tol=1e-9, max_iter=20000,
+                                   check_every=32, use_graph=True)
+    C, Ct = mixed["C"], tight["C"]
+    assert rel(C, Ct) < 1e-5
+    # cubic symmetry of the centred sphere and the Voigt / Reuss bounds of
+    # the oracle's mean inclusion fraction
+    assert abs(C[0, 0] - C[1, 1]) < 1e-5 * C[0, 0] and abs(C[0, 0] - C[2, 2]) < 1e-5 * C[0, 0]
+    assert abs(C[3, 3] - C[5, 5]) < 1e-5 * C[3, 3]
+    f = frac_o.mean()
+    cph = [orules.iso_tensor(*p) for p in w.phases]
+    up = orules.to_mandel(orules.voigt(f, cph[0], cph[1]))
+    lo = orules.to_mandel(orules.reuss(f, cph[0], cph[1]))
+    Cs = 0.5 * (C + C.T)
+    assert np.min(np.linalg.eigvalsh(up - Cs)) > 0.0 and np.min(np.linalg.eigvalsh(Cs - lo)) > 0.0
