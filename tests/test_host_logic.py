@@ -1,0 +1,62 @@
+"""Host-side logic that runs without a GPU: the benchmark's byte and flop
+accounting and profile-name normalisation, and the seeded workloads
+(reproducible, non-overlapping inclusions, valid phase matrices)."""
+import math
+
+import numpy as np
+
+import bench
+from workloads import cubic_mandel, iso_mandel, lame, rotation_from_seed, workload_aniso, workload_c2, workload_nphase
+
+
+def test_kernel_bytes_by_hand():
+    n = (125, 125, 125)
+    plane = 125 * 125 * 63
+    # FP32 elastic z-sweep: spectrum 6 components and 3 history components, read and written
+    assert bench.kernel_bytes(n, "mixed", "zsweep") == 2 * 6 * plane * 8 + 2 * 3 * plane * 8
+    # FP64 conduction x-sweep with 1000 fractional voxels: 3 components, ids, 8-real rows
+    assert bench.kernel_bytes(n, "fp64", "xsweep", 1000, nc=3, nh=1) == 2 * 3 * plane * 16 + 4 * 125 ** 3 + 1000 * 64
+    # anisotropic rows hold 24 reals
+    assert (bench.kernel_bytes(n, "mixed", "xsweep", 10, row_reals=24) -
+            bench.kernel_bytes(n, "mixed", "xsweep", 0)) == 10 * 24 * 4
+    assert bench.kernel_bytes(n, "mixed", "ysweep_fwd") == 2 * 6 * plane * 8
+
+
+def test_series_flops_and_profile_names():
+    assert bench.series_flops((125, 125, 125), (375, 375, 375)) == 2.0 * (
+        125 * 125 * 125 * 375 + 125 * 375 * 125 * 375 + 375 * 375 * 125 * 375)
+    assert bench._short("void hm::k_xsweep<float, 125, 8, 256, 1, 27, false>(hm::SolveArgs)") == \
+        "xsweep<float,125,8,256,1,27>"
+    assert bench._short("void hm::k_xsweep<double, 125, 8, 256, 1, 9, true>(hm::SolveArgs)") == \
+        "xsweep<double,125,8,256,1,9,1>"
+    assert bench._short("void hm::k_zsweep<float, 125, 16, 512, 1, 2, 1>(hm::SolveArgs)") == \
+        "zsweep<float,125,16,512,1,2,1>"
+
+
+def _min_gap(sph, n):
+    gaps = []
+    for i in range(len(sph)):
+        for j in range(i):
+            d = sph[i, :3] - sph[j, :3]
+            d -= np.asarray(n) * np.round(d / np.asarray(n))
+            gaps.append(np.linalg.norm(d) - sph[i, 3] - sph[j, 3])
+    return min(gaps)
+
+
+def test_workloads_are_seeded_and_valid():
+    a, b = workload_nphase(), workload_nphase()
+    assert np.array_equal(a.spheres, b.spheres) and np.array_equal(a.meta["labels"], b.meta["labels"])
+    assert _min_gap(a.spheres, a.n) >= 2.0 - 1e-9
+    assert set(a.meta["labels"].tolist()) == {1, 2}
+    w = workload_aniso()
+    for m in w.meta["C_mandel"]:
+        assert np.allclose(m, m.T) and np.linalg.eigvalsh(m).min() > 0.0
+    R = rotation_from_seed(8)
+    assert np.allclose(R.T @ R, np.eye(3)) and np.isclose(np.linalg.det(R), 1.0)
+    # rotation leaves the cubic invariants: trace and Frobenius norm of the Mandel matrix
+    c0, c1 = cubic_mandel(30.0, 12.0, 20.0), cubic_mandel(30.0, 12.0, 20.0, R)
+    assert np.isclose(np.trace(c0), np.trace(c1)) and np.isclose(np.linalg.norm(c0), np.linalg.norm(c1))
+    lam, mu = lame(1.0, 0.3)
+    assert np.allclose(np.linalg.eigvalsh(iso_mandel(lam, mu)), sorted([2 * mu] * 5 + [3 * lam + 2 * mu]))
+    c2 = workload_c2(100.0)
+    assert math.isclose(4.0 / 3.0 * math.pi * c2.spheres[0, 3] ** 3 / 125 ** 3, 0.25, rel_tol=1e-6)
