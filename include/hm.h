@@ -447,6 +447,21 @@ int hm_stiffness_component(const hm_grid* grid, const hm_iso phases[2], hm_rule 
                            const hm_sphere* spheres, int n_spheres, hm_prec prec,
                            int I, int J, void* d_out, void* stream);
 
+/*
+ * hm_stress_field - local stress sigma = c~ : eps at every voxel (the
+ * stress maps of Figure 2, Section 4), for strain fields such as the d_eps
+ * written by hm_solve.  c~ as hm_solve builds it (evaluated in double).
+ * Inputs:  material as hm_solve, d_eps (device, n_load x 6 x N reals of the
+ *          precision, [load][component][z][y][x], tensor components 11, 22,
+ *          33, 23, 13, 12).
+ * Output:  d_sig (device, same layout and type).  Returns after the kernel;
+ *          HM_E_DATA as hm_solve.
+ */
+int hm_stress_field(const hm_grid* grid, const hm_iso phases[2], hm_rule rule,
+                    const void* d_frac, const int32_t* d_incl,
+                    const hm_sphere* spheres, int n_spheres, hm_prec prec,
+                    const void* d_eps, int n_load, void* d_sig, void* stream);
+
 /* Timing of the calling thread's last solve run with opts->profile set.
  * Returns HM_E_ARG when there is none. */
 int hm_last_timing(hm_timing* out);

@@ -22,6 +22,7 @@ from .api import (  # noqa: F401
     hm_solve_adjoint,
     hm_solve_phases,
     hm_stiffness_component,
+    hm_stress_field,
     last_timing,
     release_plans,
     schedule_count,

@@ -330,6 +330,24 @@ def hm_effective_tensor_aniso(n, dim, C_phases, rule: str, frac: torch.Tensor, i
     return {"status": rc, "C": C, "reports": _reports(rep, k)}
 
 
+def hm_stress_field(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres,
+                    eps: torch.Tensor, prec: str = "fp64"):
+    """Local stress c~ : eps for strain fields eps (n_load, 6, N); returns the same shape."""
+    dev = frac.device
+    N = int(n[0] * n[1] * n[2])
+    _check_field(frac, N, _DT[prec], dev, "frac")
+    _check_field(incl, N, torch.int32, dev, "incl")
+    nl = eps.numel() // (6 * N)
+    _check_field(eps, 6 * N * nl, _DT[prec], dev, "eps")
+    sig = torch.empty((nl, 6, N), dtype=_DT[prec], device=dev)
+    g = _grid(n, dim)
+    sph, ns = _spheres(spheres)
+    rc = _lib().hm_stress_field(ctypes.byref(g), _phases(phases), L.RULES[rule], _ptr(frac), _ptr(incl), sph, ns,
+                                L.PRECS[prec], _ptr(eps), nl, _ptr(sig), _stream(dev))
+    L.check(rc)
+    return sig
+
+
 def hm_fourier_series(n, dim, field: torch.Tensor, m, prec: str = "fp64"):
     """Truncated Fourier series of a grid field on the voxel centres of an m grid, (m_z, m_y, m_x)."""
     dev = field.device

@@ -1539,15 +1539,18 @@ int hm_fourier_series(const hm_grid* grid, const int m[3], hm_prec prec, const v
   return HM_OK;
 }
 
-int hm_stiffness_component(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,
-                           const int32_t* d_incl, const hm_sphere* spheres, int n_spheres, hm_prec prec, int I,
-                           int J, void* d_out, void* stream) {
+// Per-voxel material kernels after a solve (a Mandel entry of c~, or the
+// stress of strain fields): the sphere table and a flag word on the device,
+// the kernel, the flags read back (the call returns after the kernel).
+static int voxel_material_call(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,
+                               const int32_t* d_incl, const hm_sphere* spheres, int n_spheres, hm_prec prec, int I,
+                               int J, void* d_out, const void* d_eps, int n_load, void* stream, const char* what) {
   ProblemIn d = make_problem(grid, phases, rule, d_frac, d_incl, spheres, n_spheres);
   int rc;
   if ((rc = check_problem(d))) return rc;
   if (prec != HM_FP64 && prec != HM_MIXED) return fail(HM_E_ARG, "unknown precision");
   if (I < 0 || I > 5 || J < 0 || J > 5) return fail(HM_E_ARG, "Mandel indices must be in 0..5");
-  if (!d_out) return fail(HM_E_ARG, "d_out is NULL");
+  if (!d_out) return fail(HM_E_ARG, "the output pointer is NULL");
   hipStream_t s = (hipStream_t)stream;
   double* dsph = nullptr;
   int* dflags = nullptr;
@@ -1582,15 +1585,38 @@ int hm_stiffness_component(const hm_grid* grid, const hm_iso phases[2], hm_rule 
   int flags = 0;
   hipError_t e = hipMemcpyAsync(dsph, tab.data(), sb, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(dflags, 0, sizeof(int), s);
-  if (e == hipSuccess) e = launch_stiffness_component(a, prec == HM_FP64, s);
+  if (e == hipSuccess) {
+    if (d_eps) {
+      StressArgs sa{a, d_eps, d_out, n_load};
+      e = launch_stress_field(sa, prec == HM_FP64, s);
+    } else {
+      e = launch_stiffness_component(a, prec == HM_FP64, s);
+    }
+  }
   if (e == hipSuccess) e = hipMemcpyAsync(&flags, dflags, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(dsph);
   (void)hipFree(dflags);
-  if (e != hipSuccess) return fail(HM_E_DEVICE, "stiffness component: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return fail(HM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
   if (flags & 1) return fail(HM_E_DATA, "fractional voxel with HM_RULE_NONE");
   if (flags & 2) return fail(HM_E_DATA, "d_incl holds a sphere index >= n_spheres");
   return HM_OK;
+}
+
+int hm_stiffness_component(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,
+                           const int32_t* d_incl, const hm_sphere* spheres, int n_spheres, hm_prec prec, int I,
+                           int J, void* d_out, void* stream) {
+  return voxel_material_call(grid, phases, rule, d_frac, d_incl, spheres, n_spheres, prec, I, J, d_out, nullptr, 0,
+                             stream, "stiffness component");
+}
+
+int hm_stress_field(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,
+                    const int32_t* d_incl, const hm_sphere* spheres, int n_spheres, hm_prec prec, const void* d_eps,
+                    int n_load, void* d_sig, void* stream) {
+  if (!d_eps) return fail(HM_E_ARG, "d_eps is NULL");
+  if (n_load < 1 || n_load > kMaxLoads) return fail(HM_E_ARG, "n_load must be in 1..%d", kMaxLoads);
+  return voxel_material_call(grid, phases, rule, d_frac, d_incl, spheres, n_spheres, prec, 0, 0, d_sig, d_eps,
+                             n_load, stream, "stress field");
 }
 
 const char* hm_last_error(void) { return g_last_error.c_str(); }

@@ -14,6 +14,7 @@
 //
 // Stiffness component: the filtered stiffness of Section 2 (eqs. 3-5) at
 // each voxel applied to a unit Mandel strain, one Mandel entry kept.
+// Stress field: the same stiffness applied to a solve's strain fields.
 #include <math.h>
 
 #include "hm_common.hpp"
@@ -124,11 +125,10 @@ hipError_t launch_series_pass(const AxisPass& p, bool fp64, hipStream_t s) {
   return fp64 ? series_pass<double>(p, s) : series_pass<float>(p, s);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_stiffness_component(StiffnessArgs a) {
-  const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
-  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (v >= N) return;
+// Filtered stiffness c~ of voxel v in the transversely isotropic form of
+// hm_material.hpp, in double: the phase tensor where f is 0 or 1, else the
+// rule at f (flags as StiffnessArgs describes).
+template <typename T> __device__ Coef<double> voxel_coef(const StiffnessArgs& a, long long v) {
   const double f = (double)static_cast<const T*>(a.frac)[v];
   Coef<double> c;
   c.n[0] = c.n[1] = c.n[2] = 0.0;
@@ -156,12 +156,49 @@ __global__ __launch_bounds__(256) void k_stiffness_component(StiffnessArgs a) {
       }
     }
   }
+  return c;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_stiffness_component(StiffnessArgs a) {
+  const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (v >= N) return;
+  const Coef<double> c = voxel_coef<T>(a, v);
   // unit Mandel strain J as tensor components, Mandel entry I of the stress
   const double r2 = 1.4142135623730950488;
   double e[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, s6[6];
   e[a.J] = a.J < 3 ? 1.0 : 1.0 / r2;
   apply_form<double>(c, e, s6);
   static_cast<T*>(a.out)[v] = (T)(a.I < 3 ? s6[a.I] : r2 * s6[a.I]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_stress_field(StressArgs a) {
+  const long long N = (long long)a.m.n[0] * a.m.n[1] * a.m.n[2];
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (v >= N) return;
+  const Coef<double> c = voxel_coef<T>(a.m, v);
+  const T* eps = static_cast<const T*>(a.eps);
+  T* sig = static_cast<T*>(a.sig);
+  for (int l = 0; l < a.n_load; ++l) {
+    double e[6], s6[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) e[k] = (double)eps[((size_t)l * 6 + k) * N + v];
+    apply_form<double>(c, e, s6);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sig[((size_t)l * 6 + k) * N + v] = (T)s6[k];
+  }
+}
+
+hipError_t launch_stress_field(const StressArgs& a, bool fp64, hipStream_t s) {
+  const long long N = (long long)a.m.n[0] * a.m.n[1] * a.m.n[2];
+  const dim3 grid((unsigned)((N + 255) / 256));
+  if (fp64)
+    hipLaunchKernelGGL((k_stress_field<double>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_stress_field<float>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_stiffness_component(const StiffnessArgs& a, bool fp64, hipStream_t s) {

@@ -1,6 +1,7 @@
 // Launch interface of the post-processing kernels: the truncated Fourier
-// series of a grid field on a finer grid (Figure 4) and a Mandel entry of
-// the filtered stiffness per voxel (the field that figure extrapolates).
+// series of a grid field on a finer grid (Figure 4), a Mandel entry of the
+// filtered stiffness per voxel (the field that figure extrapolates) and the
+// local stress field of a solve (the maps of Figure 2).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,5 +39,17 @@ struct StiffnessArgs {
 };
 
 hipError_t launch_stiffness_component(const StiffnessArgs& a, bool fp64, hipStream_t s);
+
+// Local stress sigma = c~ : eps at every voxel for n_load strain fields
+// [load][6][N] (tensor components), written to sig with the same layout;
+// the material arguments as above (I, J unused).
+struct StressArgs {
+  StiffnessArgs m;
+  const void* eps;
+  void* sig;
+  int n_load;
+};
+
+hipError_t launch_stress_field(const StressArgs& a, bool fp64, hipStream_t s);
 
 }  // namespace hm
