@@ -462,6 +462,19 @@ int hm_stress_field(const hm_grid* grid, const hm_iso phases[2], hm_rule rule,
                     const hm_sphere* spheres, int n_spheres, hm_prec prec,
                     const void* d_eps, int n_load, void* d_sig, void* stream);
 
+/*
+ * hm_flux_field - local flux q = k~ g at every voxel for gradient fields
+ * such as the d_grad written by hm_conduct_solve; k~ as hm_conduct_solve
+ * builds it (evaluated in double).  Inputs as hm_conduct_solve, d_grad
+ * (device, n_load x 3 x N reals of the precision, [load][component][z][y][x]).
+ * Output: d_flux (device, same layout and type).  Returns after the kernel;
+ * HM_E_DATA as hm_solve.
+ */
+int hm_flux_field(const hm_grid* grid, const double k[2], hm_rule rule,
+                  const void* d_frac, const int32_t* d_incl,
+                  const hm_sphere* spheres, int n_spheres, hm_prec prec,
+                  const void* d_grad, int n_load, void* d_flux, void* stream);
+
 /* Timing of the calling thread's last solve run with opts->profile set.
  * Returns HM_E_ARG when there is none. */
 int hm_last_timing(hm_timing* out);

@@ -24,7 +24,7 @@ METHODS = {"fixed_point": 0, "cg": 1}
 EXPORTS = ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_effective_tensor_batch", "hm_solve_adjoint",
            "hm_conduct_solve", "hm_effective_conductivity", "hm_fourier_series", "hm_stiffness_component",
            "hm_filter_phases", "hm_solve_phases", "hm_effective_tensor_phases", "hm_solve_aniso",
-           "hm_effective_tensor_aniso", "hm_stress_field", "hm_last_error", "hm_last_timing", "hm_schedule_count", "hm_release_plans",
+           "hm_effective_tensor_aniso", "hm_stress_field", "hm_flux_field", "hm_last_error", "hm_last_timing", "hm_schedule_count", "hm_release_plans",
            "hm_device_ok")
 
 
@@ -100,6 +100,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hm_effective_conductivity.argtypes = [_P(HmGrid), _dp, ctypes.c_int, _vp, _vp, _P(HmSphere),
                                               ctypes.c_int, _P(HmSolveOpts), _dp, _vp, _P(HmReport), _vp]
     lib.hm_fourier_series.argtypes = [_P(HmGrid), _P(ctypes.c_int), ctypes.c_int, _vp, _vp, _vp]
+    lib.hm_flux_field.argtypes = [_P(HmGrid), _dp, ctypes.c_int, _vp, _vp, _P(HmSphere), ctypes.c_int, ctypes.c_int,
+                                  _vp, ctypes.c_int, _vp, _vp]
     lib.hm_stress_field.argtypes = [_P(HmGrid), _P(HmIso), ctypes.c_int, _vp, _vp, _P(HmSphere), ctypes.c_int,
                                     ctypes.c_int, _vp, ctypes.c_int, _vp, _vp]
     lib.hm_solve_aniso.argtypes = [_P(HmGrid), _dp, ctypes.c_int, _vp, _vp, _P(HmSphere), ctypes.c_int, _dp,
@@ -117,7 +119,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     for f in ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_effective_tensor_batch", "hm_solve_adjoint",
               "hm_conduct_solve", "hm_effective_conductivity", "hm_fourier_series", "hm_stiffness_component",
               "hm_filter_phases", "hm_solve_phases", "hm_effective_tensor_phases", "hm_solve_aniso",
-              "hm_effective_tensor_aniso", "hm_stress_field", "hm_device_ok"):
+              "hm_effective_tensor_aniso", "hm_stress_field", "hm_flux_field", "hm_device_ok"):
         getattr(lib, f).restype = ctypes.c_int
     lib.hm_schedule_count.argtypes = [_P(HmGrid), ctypes.c_int, _P(ctypes.c_int), _P(ctypes.c_int),
                                       _P(ctypes.c_int)]

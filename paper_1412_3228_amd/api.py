@@ -348,6 +348,25 @@ def hm_stress_field(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optiona
     return sig
 
 
+def hm_flux_field(n, dim, k, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres,
+                  grad: torch.Tensor, prec: str = "fp64"):
+    """Local flux k~ g for gradient fields grad (n_load, 3, N); returns the same shape."""
+    dev = frac.device
+    N = int(n[0] * n[1] * n[2])
+    _check_field(frac, N, _DT[prec], dev, "frac")
+    _check_field(incl, N, torch.int32, dev, "incl")
+    nl = grad.numel() // (3 * N)
+    _check_field(grad, 3 * N * nl, _DT[prec], dev, "grad")
+    q = torch.empty((nl, 3, N), dtype=_DT[prec], device=dev)
+    g = _grid(n, dim)
+    sph, ns = _spheres(spheres)
+    kk = _conductivities(k)
+    rc = _lib().hm_flux_field(ctypes.byref(g), kk.ctypes.data_as(L._dp), L.RULES[rule], _ptr(frac), _ptr(incl), sph,
+                              ns, L.PRECS[prec], _ptr(grad), nl, _ptr(q), _stream(dev))
+    L.check(rc)
+    return q
+
+
 def hm_fourier_series(n, dim, field: torch.Tensor, m, prec: str = "fp64"):
     """Truncated Fourier series of a grid field on the voxel centres of an m grid, (m_z, m_y, m_x)."""
     dev = field.device

@@ -1544,8 +1544,14 @@ int hm_fourier_series(const hm_grid* grid, const int m[3], hm_prec prec, const v
 // the kernel, the flags read back (the call returns after the kernel).
 static int voxel_material_call(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,
                                const int32_t* d_incl, const hm_sphere* spheres, int n_spheres, hm_prec prec, int I,
-                               int J, void* d_out, const void* d_eps, int n_load, void* stream, const char* what) {
+                               int J, void* d_out, const void* d_eps, int n_load, void* stream, const char* what,
+                               const double* k = nullptr) {
   ProblemIn d = make_problem(grid, phases, rule, d_frac, d_incl, spheres, n_spheres);
+  if (k) {
+    d.cond = 1;
+    d.k[0] = k[0];
+    d.k[1] = k[1];
+  }
   int rc;
   if ((rc = check_problem(d))) return rc;
   if (prec != HM_FP64 && prec != HM_MIXED) return fail(HM_E_ARG, "unknown precision");
@@ -1574,8 +1580,8 @@ static int voxel_material_call(const hm_grid* grid, const hm_iso phases[2], hm_r
   for (int k = 0; k < 3; ++k) a.n[k] = grid->n[k];
   a.dim = grid->dim;
   for (int p = 0; p < 2; ++p) {
-    a.pl[p] = phases[p].lambda;
-    a.pm[p] = phases[p].mu;
+    a.pl[p] = k ? k[p] : phases[p].lambda;
+    a.pm[p] = k ? 0.0 : phases[p].mu;
   }
   a.rule = (int)rule;
   a.I = I;
@@ -1588,7 +1594,7 @@ static int voxel_material_call(const hm_grid* grid, const hm_iso phases[2], hm_r
   if (e == hipSuccess) {
     if (d_eps) {
       StressArgs sa{a, d_eps, d_out, n_load};
-      e = launch_stress_field(sa, prec == HM_FP64, s);
+      e = k ? launch_flux_field(sa, prec == HM_FP64, s) : launch_stress_field(sa, prec == HM_FP64, s);
     } else {
       e = launch_stiffness_component(a, prec == HM_FP64, s);
     }
@@ -1608,6 +1614,16 @@ int hm_stiffness_component(const hm_grid* grid, const hm_iso phases[2], hm_rule 
                            int J, void* d_out, void* stream) {
   return voxel_material_call(grid, phases, rule, d_frac, d_incl, spheres, n_spheres, prec, I, J, d_out, nullptr, 0,
                              stream, "stiffness component");
+}
+
+int hm_flux_field(const hm_grid* grid, const double k[2], hm_rule rule, const void* d_frac, const int32_t* d_incl,
+                  const hm_sphere* spheres, int n_spheres, hm_prec prec, const void* d_grad, int n_load,
+                  void* d_flux, void* stream) {
+  if (!k) return fail(HM_E_ARG, "k is NULL");
+  if (!d_grad) return fail(HM_E_ARG, "d_grad is NULL");
+  if (n_load < 1 || n_load > kMaxLoads) return fail(HM_E_ARG, "n_load must be in 1..%d", kMaxLoads);
+  return voxel_material_call(grid, nullptr, rule, d_frac, d_incl, spheres, n_spheres, prec, 0, 0, d_flux, d_grad,
+                             n_load, stream, "flux field", k);
 }
 
 int hm_stress_field(const hm_grid* grid, const hm_iso phases[2], hm_rule rule, const void* d_frac,

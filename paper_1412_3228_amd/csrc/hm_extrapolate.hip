@@ -14,7 +14,8 @@
 //
 // Stiffness component: the filtered stiffness of Section 2 (eqs. 3-5) at
 // each voxel applied to a unit Mandel strain, one Mandel entry kept.
-// Stress field: the same stiffness applied to a solve's strain fields.
+// Stress field: the same stiffness applied to a solve's strain fields; flux
+// field: a conduction solve's filtered conductivity applied to its gradients.
 #include <math.h>
 
 #include "hm_common.hpp"
@@ -198,6 +199,62 @@ hipError_t launch_stress_field(const StressArgs& a, bool fp64, hipStream_t s) {
     hipLaunchKernelGGL((k_stress_field<double>), grid, dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((k_stress_field<float>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// Local flux: the conductivity of voxel v is k_p where f is 0 or 1, else
+// the rule at f (Voigt <k>, Reuss <1/k>^-1, 2-layer <k> along the interface
+// and <1/k>^-1 across it), held as k~ = a I + b n (x) n and applied to each
+// gradient field.
+template <typename T>
+__global__ __launch_bounds__(256) void k_flux_field(StressArgs a) {
+  const StiffnessArgs& m = a.m;
+  const long long N = (long long)m.n[0] * m.n[1] * m.n[2];
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (v >= N) return;
+  const double f = (double)static_cast<const T*>(m.frac)[v];
+  double ka = f == 0.0 ? m.pl[0] : m.pl[1], kb = 0.0;
+  double n[3] = {0.0, 0.0, 0.0};
+  if (f != 0.0 && f != 1.0) {
+    int rule = m.rule;
+    if (rule == RULE_NONE) {
+      atomicOr(m.flags, 1);
+      rule = RULE_VOIGT;
+    }
+    const double arith = (1.0 - f) * m.pl[0] + f * m.pl[1];
+    const double harm = 1.0 / ((1.0 - f) / m.pl[0] + f / m.pl[1]);
+    ka = rule == RULE_REUSS ? harm : arith;
+    if (rule == RULE_LAMINATE) {
+      kb = harm - arith;
+      const int k = m.incl ? m.incl[v] : -1;
+      if (k >= m.nsph) atomicOr(m.flags, 2);
+      if (k >= 0 && k < m.nsph) {
+        const int x = (int)(v % m.n[0]), y = (int)((v / m.n[0]) % m.n[1]), z = (int)(v / ((long long)m.n[0] * m.n[1]));
+        interface_normal<double>(m.sph, k, x, y, z, m.n[0], m.n[1], m.n[2], m.dim, n);
+      } else {
+        n[0] = 1.0;
+      }
+    }
+  }
+  const T* g = static_cast<const T*>(a.eps);
+  T* q = static_cast<T*>(a.sig);
+  for (int l = 0; l < a.n_load; ++l) {
+    double gv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gv[c] = (double)g[((size_t)l * 3 + c) * N + v];
+    const double ng = n[0] * gv[0] + n[1] * gv[1] + n[2] * gv[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q[((size_t)l * 3 + c) * N + v] = (T)(ka * gv[c] + kb * ng * n[c]);
+  }
+}
+
+hipError_t launch_flux_field(const StressArgs& a, bool fp64, hipStream_t s) {
+  const long long N = (long long)a.m.n[0] * a.m.n[1] * a.m.n[2];
+  const dim3 grid((unsigned)((N + 255) / 256));
+  if (fp64)
+    hipLaunchKernelGGL((k_flux_field<double>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_flux_field<float>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -52,4 +52,9 @@ struct StressArgs {
 
 hipError_t launch_stress_field(const StressArgs& a, bool fp64, hipStream_t s);
 
+// Local flux q = k~ g of a conduction solve: the same arguments with the
+// phase conductivities in m.pl, gradient fields [load][3][N] in eps and the
+// fluxes written to sig with that layout.
+hipError_t launch_flux_field(const StressArgs& a, bool fp64, hipStream_t s);
+
 }  // namespace hm

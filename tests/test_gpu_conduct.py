@@ -169,3 +169,17 @@ def test_bad_input_is_refused(hm):
     with pytest.raises(hm.HmError) as e:  # 11 is not a product of 3, 5 and 7
         hm.hm_conduct_solve((11, 9, 9), 3, K2, "voigt", f11, None, w.spheres, G, max_iter=3)
     assert e.value.code == -2
+
+
+@pytest.mark.parametrize("rule", ["voigt", "reuss", "laminate"])
+def test_flux_field_matches_oracle(hm, rule):
+    # local flux q = k~ g of the exported gradient fields
+    w = _case(rule)
+    _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", DEV)
+    ref_f = ofilter.filter_field(w)
+    fld = _oracle_field(w, ref_f, K2)
+    G = np.array([[0.3, -0.7, 0.2]])
+    out = hm.hm_conduct_solve(w.n, w.dim, K2, rule, frac, incl, w.spheres, G, tol=0.0, max_iter=4, want_grad=True)
+    q = hm.hm_flux_field(w.n, w.dim, K2, rule, frac, incl, w.spheres, out["grad"]).cpu().numpy()
+    r = othermal.solve(fld, G[0], othermal.reference_conductivity(K2), 0.0, 4)
+    assert rel(q[0], _grad_comps(fld.apply(r["grad"]))) < 1e-10
