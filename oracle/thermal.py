@@ -61,10 +61,12 @@ class ConductivityField:
         self.kt[f == 0.0] = k[0] * np.eye(3)
         self.kt[f == 1.0] = k[1] * np.eye(3)
         mid = np.nonzero((f > 0.0) & (f < 1.0))[0]
+        if mid.size and rule == "none":
+            # without a filter every voxel is pure (the indicator at its centre)
+            raise ValueError("fractional voxels need a homogenisation rule")
         for v in mid:
             nh = normals[v] if normals is not None else np.array([1.0, 0.0, 0.0])
-            r = "voigt" if rule == "none" else rule
-            self.kt[v] = rule_tensor(r, f[v], nh, k)
+            self.kt[v] = rule_tensor(rule, f[v], nh, k)
 
     def apply(self, g: np.ndarray) -> np.ndarray:
         """q = k~ g for a field (nz, ny, nx, 3)."""
