@@ -183,8 +183,64 @@ def run_path(hm, w, prec, contrast, dev, profile=True, C_target=None, max_iter=5
     N = w.nvox
     vit = sum((r["iters"] + 1) for r in out["reports"]) * N
     del out["eps"], frac, incl, cnt, dfr
+    # per-iterate errors and mean stresses of the six solves (after the timed region)
+    cap = max(r["iters"] for r in out["reports"]) + 1
+    herr, hsig = hm.last_history(6, cap)
     return {"seconds": dt, "voxel_iterations": vit, "C": C, "reports": out["reports"], "timing": timing,
-            "dLdphase": dph}
+            "dLdphase": dph, "history": (herr, hsig)}
+
+
+MANDEL_W = np.array([1.0, 1.0, 1.0, math.sqrt(2.0), math.sqrt(2.0), math.sqrt(2.0)])
+
+
+def ceff_trajectory(hsig):
+    """C_i (Mandel) at every iterate i from the six unit-strain solves' mean
+    stresses; a load case that stopped earlier keeps its last column."""
+    nl, cap, _ = hsig.shape
+    traj = np.zeros((cap, 6, 6))
+    for J in range(nl):
+        col = hsig[J]
+        last = col[0]
+        for i in range(cap):
+            if not np.isnan(col[i, 0]):
+                last = col[i]
+            traj[i, :, J] = MANDEL_W * last
+    return traj
+
+
+def iterations_to(traj, Cref, eps):
+    """First iterate whose effective tensor is within eps (relative Frobenius)
+    of Cref and stays within it afterwards, or None."""
+    e = np.linalg.norm(traj - Cref, axis=(1, 2)) / np.linalg.norm(Cref)
+    ok = e <= eps
+    if not ok[-1]:
+        return None
+    bad = np.nonzero(~ok)[0]
+    return int(bad[-1] + 1) if bad.size else 0
+
+
+def equal_error(last, ref, eps_list=(1e-5, 1e-6)):
+    """Mixed vs FP64 at equal effective-tensor error: per contrast and target
+    error, the iterations each path needs before its C_eff trajectory stays
+    within eps of the tightly converged FP64 tensor, the device time of that
+    many iterations (profiled per-iteration kernel time, all six load cases
+    active) and the ratio FP64 / mixed."""
+    out = {}
+    for c in CONTRASTS:
+        row = {}
+        for eps in eps_list:
+            r = {}
+            for prec in ("fp64", "mixed"):
+                res = last[(prec, c)]
+                it = iterations_to(ceff_trajectory(res["history"][1]), ref[c], eps)
+                t_it = sum(res["timing"]["ms"].values())  # ms per iteration, all loads active
+                r[prec] = {"iterations": it, "ms_per_iteration": t_it,
+                           "ms_to_eps": None if it is None else (it + 1) * t_it}
+            a, b = r["fp64"]["ms_to_eps"], r["mixed"]["ms_to_eps"]
+            r["time_ratio_fp64_over_mixed"] = None if (a is None or b is None) else a / b
+            row["%g" % eps] = r
+        out[str(c)] = row
+    return out
 
 
 def roofline(timings, n, prec, reports, n_frac=0, nc=6, nh=3, n_load=6, row_reals=8):
@@ -209,6 +265,99 @@ def roofline(timings, n, prec, reports, n_frac=0, nc=6, nh=3, n_load=6, row_real
             "traffic_source": None if tr is None else tr["file"], "ms_per_launch": ms,
             "algorithmic_bytes_per_launch": bytes_launch, "active_loads_per_launch": active,
             "ms_per_kernel": {k: v / its for k, v in tot.items()}}
+
+
+B_ALG = {"fp64": 104.0, "mixed": 52.0}  # algorithmic floor, bytes per voxel-iteration
+
+
+def design_bytes_per_voxel_it(n, prec, n_frac=0):
+    """Algorithmic bytes of the four sweeps per voxel-iteration (per load case)."""
+    tot = sum(kernel_bytes(n, prec, k, n_frac) for k in ("xsweep", "ysweep_fwd", "zsweep", "ysweep_inv"))
+    return tot / float(n[0] * n[1] * n[2])
+
+
+def floor_fraction(value, prec):
+    """B_alg x voxel-iterations/s / peak: the rate against the method's own
+    minimum traffic (the iterate read and written once plus the fractions)."""
+    return B_ALG[prec] * value / (HBM_PEAK_GBS * 1e9)
+
+
+def c3_section(hm, dev):
+    """243^3 cell with 40 spheres (fraction 0.30, contrast 20), 2-layer filter
+    r = 1 with 8^3 sub-samples, the six unit strains in one launch, tol 1e-4:
+    a profiled solve per path, its voxel-iterations per second and the
+    roofline of its dominant sweep (the working set is far beyond the 256 MB
+    Infinity Cache)."""
+    from workloads import workload_c3
+    w = workload_c3()
+    out = {"grid": list(w.n), "spheres": int(len(w.spheres)), "fraction": w.meta["nominal_fraction"]}
+    Cs = {}
+    for prec in ("mixed", "fp64"):
+        _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, prec, dev)
+        n_frac = int(((frac > 0) & (frac < 1)).sum().item())
+        kw = dict(prec=prec, tol=w.tol, max_iter=5000, check_every=16, stall_window=(20 if prec == "mixed" else 0))
+        hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, max_iter=2, prec=prec, tol=0.0,
+                               check_every=16)  # plan and schedule warm
+        _sync()
+        t0 = time.perf_counter()
+        o = hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, profile=True, **kw)
+        _sync()
+        secs = time.perf_counter() - t0
+        t = hm.last_timing()
+        vit = sum(r["iters"] + 1 for r in o["reports"]) * w.nvox
+        value = vit / secs
+        Cs[prec] = o["C"]
+        out[prec] = {"value": value, "unit": "voxel-iterations/s", "seconds": secs,
+                     "iters": [r["iters"] for r in o["reports"]], "status": [r["status"] for r in o["reports"]],
+                     "final_equilibrium_error": [r["err"] for r in o["reports"]],
+                     "floor_frac": floor_fraction(value, prec),
+                     "roofline": roofline([t], w.n, prec, [o["reports"]], n_frac),
+                     "ms_per_kernel": t["ms"], "kernels": t["kernels"]}
+        del frac, incl
+        print("c3 %s done" % prec, file=sys.stderr, flush=True)
+    out["mixed_vs_fp64_ceff_rel_err"] = float(np.linalg.norm(Cs["mixed"] - Cs["fp64"]) / np.linalg.norm(Cs["fp64"]))
+    hm.release_plans()
+    return out
+
+
+def c4_section(hm, dev):
+    """The batch of 64 seeded cells of uneven sizes {45..135}^3 (5-30 spheres,
+    fraction 0.1-0.35, contrast log-uniform in [0.01, 100], 2-layer filter,
+    the six unit strains of every cell), mixed precision, tol 1e-4 with the
+    stall window, one hm_effective_tensor_batch call (grid groups replayed
+    together in captured graphs): aggregate voxel-iterations per second."""
+    from workloads import workload_c4
+    works = workload_c4()
+    probs = []
+    for w in works:
+        _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, "mixed", dev)
+        probs.append({"n": w.n, "dim": w.dim, "phases": w.phases, "rule": w.rule, "frac": frac, "incl": incl,
+                      "spheres": w.spheres})
+    kw = dict(prec="mixed", tol=1e-4, max_iter=5000, check_every=16, stall_window=20, use_graph=True)
+    hm.hm_effective_tensor_batch(probs, **dict(kw, max_iter=2, tol=0.0))  # plans, tuning, graphs warm
+    _sync()
+    t0 = time.perf_counter()
+    o = hm.hm_effective_tensor_batch(probs, **kw)
+    _sync()
+    secs = time.perf_counter() - t0
+    vit = 0
+    design = 0.0
+    its = []
+    for w, res in zip(works, o["results"]):
+        v = sum(r["iters"] + 1 for r in res["reports"]) * w.nvox
+        vit += v
+        design += v * design_bytes_per_voxel_it(w.n, "mixed")
+        its.append(max(r["iters"] for r in res["reports"]))
+    value = vit / secs
+    statuses = [r["status"] for res in o["results"] for r in res["reports"]]
+    del probs
+    hm.release_plans()
+    return {"cells": len(works), "sizes": sorted(set(w.n[0] for w in works)), "value": value,
+            "unit": "voxel-iterations/s", "seconds": secs, "voxel_iterations": vit,
+            "iterations_min_max": [min(its), max(its)],
+            "statuses": {str(k): statuses.count(k) for k in sorted(set(statuses))},
+            "floor_frac": floor_fraction(value, "mixed"),
+            "design_bytes_frac": design / secs / (HBM_PEAK_GBS * 1e9)}
 
 
 def time_to_solution(hm, works, ref, dev):
@@ -452,16 +601,19 @@ def cpu_baseline(iters=1):
     incl = np.where((frac > 0) & (frac < 1), 0, -1)
     fld = osolver.build_field(w, frac, incl)
     c0 = osolver.reference_medium(w.phases)
+    cores = len(os.sched_getaffinity(0))
+    import scipy.fft as sfft
+    dft = (lambda a: sfft.fftn(a, axes=(0, 1, 2), workers=cores),
+           lambda a: sfft.ifftn(a, axes=(0, 1, 2), workers=cores))
     w0, c0t = time.perf_counter(), time.process_time()
-    r = osolver.solve(fld, w.loads[0], c0, 0.0, iters)
+    r = osolver.solve(fld, w.loads[0], c0, 0.0, iters, dft=dft)
     wall = time.perf_counter() - w0
     cpu = time.process_time() - c0t
     evals = r["iters"] + 1
-    return {"value": evals * w.nvox / wall, "unit": "voxel-iterations/s", "cores": max(1, int(round(cpu / wall))),
-            "kind": "oracle",
+    return {"value": evals * w.nvox / wall, "unit": "voxel-iterations/s", "cores": cores, "kind": "oracle",
             "sample": "%d fixed-point iterations of one load case (first unit strain, contrast 100) on the full "
-                      "125^3 grid, FP64; %.1f s wall" % (evals, wall),
-            "host_cores_available": len(os.sched_getaffinity(0))}
+                      "125^3 grid, FP64, SciPy FFTs with workers = %d; %.1f s wall, %.1f CPU-s (the rest of the "
+                      "oracle's arithmetic is single-threaded NumPy)" % (evals, cores, wall, cpu)}
 
 
 def main():
@@ -581,7 +733,10 @@ def main():
                        "ceff_rel_err_vs_fp64_tol1e-9": errs, "iters": iters, "status": status,
                        "final_equilibrium_error": finals,
                        "roofline": roofline(timings, n, prec, reps, n_frac)}
+    for prec in ("fp64", "mixed"):
+        paths[prec]["floor_frac"] = floor_fraction(paths[prec]["value"], prec)
     mixed, fp64 = paths["mixed"], paths["fp64"]
+    eq = equal_error(steps[-1], ref)
     line = {
         "metric": METRIC,
         "value": mixed["value"],
@@ -599,11 +754,13 @@ def main():
                                "r=1 voxel with 8^3 sub-samples, 6 unit Mandel strains batched, tol 1e-4" % n[0],
                    "grid": list(n), "load_cases": 6, "voxels": N},
         "mixed_over_fp64": mixed["value"] / fp64["value"],
-        "equal_ceff_error": "both paths within 1e-5 of the tightly converged FP64 effective tensor",
+        "equal_ceff_error": eq,
         "paths": paths,
         "roofline": mixed["roofline"],
         "cpu_baseline": None,
     }
+    line["c3"] = c3_section(hm, dev)
+    line["c4"] = c4_section(hm, dev)
     line["time_to_solution"] = time_to_solution(hm, works, ref, dev)
     line["conduction"] = conduction(hm, works, dev, n_frac)
     line["fourier_series"] = series(hm, works[CONTRASTS[0]], dev)

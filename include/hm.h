@@ -479,6 +479,24 @@ int hm_flux_field(const hm_grid* grid, const double k[2], hm_rule rule,
  * Returns HM_E_ARG when there is none. */
 int hm_last_timing(hm_timing* out);
 
+/*
+ * hm_last_history - the iterates of the calling thread's last solve of one
+ * grid (hm_solve, hm_effective_tensor and their conduction, multi-phase and
+ * anisotropic forms; not hm_effective_tensor_batch): the equilibrium error
+ * e_i of every evaluated iterate (Section 2 setup) and its mean stress
+ * <sigma_i> (Section 3's average, tensor components 11, 22, 33, 23, 13, 12;
+ * the mean flux in slots 0-2 for conduction), so that an effective-tensor
+ * trajectory can be followed iterate by iterate.
+ * n_load: the load count of that solve (HM_E_ARG otherwise).
+ * cap:    iterates per load case the host arrays hold.
+ * err:    host, n_load x cap doubles: err[l * cap + i] = e_i of load case l.
+ * sig:    host, n_load x cap x 6 doubles, or NULL.
+ * Iterates beyond a load case's reported one (hm_report.iters), or beyond
+ * max_iter + 1, are set to NaN.  Synchronous device-to-host copies.  Fails
+ * with HM_E_ARG when there is no such solve or its plans were released.
+ */
+int hm_last_history(int n_load, int cap, double* err, double* sig);
+
 /* Number of compiled tile-schedule variants of the x, y and z sweeps for a
  * grid and precision (all > 0 on success). */
 int hm_schedule_count(const hm_grid* grid, hm_prec prec, int* nx, int* ny, int* nz);

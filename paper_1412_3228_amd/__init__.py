@@ -7,6 +7,7 @@ package is its thin Python binding.
 """
 from .api import (  # noqa: F401
     EffectiveTensor,
+    HmSolveError,
     device_ok,
     hm_conduct_solve,
     hm_effective_conductivity,
@@ -24,6 +25,7 @@ from .api import (  # noqa: F401
     hm_solve_phases,
     hm_stiffness_component,
     hm_stress_field,
+    last_history,
     last_timing,
     release_plans,
     schedule_count,

@@ -24,7 +24,8 @@ METHODS = {"fixed_point": 0, "cg": 1}
 EXPORTS = ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_effective_tensor_batch", "hm_solve_adjoint",
            "hm_conduct_solve", "hm_effective_conductivity", "hm_fourier_series", "hm_stiffness_component",
            "hm_filter_phases", "hm_solve_phases", "hm_effective_tensor_phases", "hm_solve_aniso",
-           "hm_effective_tensor_aniso", "hm_stress_field", "hm_flux_field", "hm_last_error", "hm_last_timing", "hm_schedule_count", "hm_release_plans",
+           "hm_effective_tensor_aniso", "hm_stress_field", "hm_flux_field", "hm_last_error", "hm_last_timing",
+           "hm_last_history", "hm_schedule_count", "hm_release_plans",
            "hm_device_ok")
 
 
@@ -126,6 +127,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hm_schedule_count.restype = ctypes.c_int
     lib.hm_last_timing.argtypes = [_P(HmTiming)]
     lib.hm_last_timing.restype = ctypes.c_int
+    lib.hm_last_history.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
+    lib.hm_last_history.restype = ctypes.c_int
     lib.hm_last_error.argtypes = []
     lib.hm_last_error.restype = ctypes.c_char_p
     lib.hm_release_plans.argtypes = []

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+import warnings
 from typing import Optional, Sequence
 
 import numpy as np
@@ -112,8 +113,9 @@ def hm_filter(n, dim, spheres, radius_vox: float, subsamples: int, rule: str, pr
 def hm_solve(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres, E,
              prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
              check_every: int = 1, stall_window: int = 0, use_graph: bool = False, want_eps: bool = False,
-             profile: bool = False, autotune: bool = True, method: str = "fixed_point"):
-    """Solve for the rows of E (n_load x 6 tensor components); method "fixed_point" or "cg"."""
+             profile: bool = False, autotune: bool = True, method: str = "fixed_point", schedule=None):
+    """Solve for the rows of E (n_load x 6 tensor components); method "fixed_point" or "cg";
+    schedule = (x, y, z) variant indices pins the tile schedules (no autotuning)."""
     dev = frac.device
     N = int(n[0] * n[1] * n[2])
     _check_field(frac, N, _DT[prec], dev, "frac")
@@ -125,7 +127,8 @@ def hm_solve(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch
     eps = torch.empty((nl, 6, N), dtype=_DT[prec], device=dev) if want_eps else None
     g = _grid(n, dim)
     sph, ns = _spheres(spheres)
-    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, autotune, None, method)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, autotune, schedule,
+              method)
     rc = _lib().hm_solve(ctypes.byref(g), _phases(phases), L.RULES[rule], _ptr(frac), _ptr(incl), sph, ns,
                          Ea.ctypes.data_as(L._dp), nl, ctypes.byref(o), _ptr(eps),
                          sig.ctypes.data_as(L._dp), rep, _stream(dev))
@@ -472,6 +475,16 @@ def last_timing():
             "kernels": {n: t.kernel[i].value.decode() for i, n in enumerate(names)}}
 
 
+def last_history(n_load: int, cap: int):
+    """Errors (n_load x cap) and mean stresses (n_load x cap x 6) of every
+    iterate of this thread's last single-cell solve; NaN past each load
+    case's reported iterate."""
+    err = np.zeros((n_load, cap))
+    sig = np.zeros((n_load, cap, 6))
+    L.check(_lib().hm_last_history(int(n_load), int(cap), err.ctypes.data_as(L._dp), sig.ctypes.data_as(L._dp)))
+    return err, sig
+
+
 def schedule_count(n, dim, prec="fp64"):
     """Numbers of compiled schedule variants of the x, y and z sweeps."""
     g = _grid(n, dim)
@@ -479,6 +492,10 @@ def schedule_count(n, dim, prec="fp64"):
     L.check(_lib().hm_schedule_count(ctypes.byref(g), L.PRECS[prec], ctypes.byref(a), ctypes.byref(b),
                                      ctypes.byref(c)))
     return a.value, b.value, c.value
+
+
+class HmSolveError(RuntimeError):
+    """A solve whose stop status makes a derived quantity invalid."""
 
 
 def release_plans():
@@ -499,16 +516,38 @@ class EffectiveTensor(torch.autograd.Function):
     fields are kept for the backward pass unless cell["checkpoint"] is
     true, in which case they are recomputed there (less memory, one more
     batched solve).
+
+    The gradient uses the variational (Hill) identity, which holds at the
+    discrete equilibrium only, so the solve's stop matters: a load case that
+    diverged or hit max_iter raises HmSolveError; a stalled one (the mixed
+    path's stop at its single-precision floor, with cell["stall_window"])
+    gives a gradient accurate to that floor and emits a warning.  The final
+    equilibrium errors and statuses of the forward solve are written to
+    cell["reports"] so callers can bound the gradient error.
     """
+
+    @staticmethod
+    def _solve(cell, ph, frac, want_eps):
+        out = hm_effective_tensor(cell["n"], cell["dim"], ph, cell["rule"], frac.detach(), cell.get("incl"),
+                                  cell["spheres"], prec=cell.get("prec", "fp64"), tol=cell.get("tol", 1e-4),
+                                  max_iter=cell.get("max_iter", 10000), check_every=cell.get("check_every", 8),
+                                  stall_window=cell.get("stall_window", 0), want_eps=want_eps)
+        cell["reports"] = out["reports"]
+        bad = [r for r in out["reports"] if r["status"] in (1, 3)]
+        if bad:
+            raise HmSolveError("the effective-tensor solve did not converge (statuses %s, errors %s): its "
+                               "gradient would not satisfy the equilibrium the adjoint identity needs"
+                               % ([r["status"] for r in out["reports"]], [r["err"] for r in out["reports"]]))
+        if any(r["status"] == 2 for r in out["reports"]):
+            warnings.warn("effective-tensor solve stalled at equilibrium errors %s: the gradient is accurate to "
+                          "that floor only" % ["%.2e" % r["err"] for r in out["reports"]], RuntimeWarning)
+        return out
 
     @staticmethod
     def forward(ctx, lame, frac, cell):
         ph = ((float(lame[0]), float(lame[1])), (float(lame[2]), float(lame[3])))
         keep = not cell.get("checkpoint", False)
-        out = hm_effective_tensor(cell["n"], cell["dim"], ph, cell["rule"], frac.detach(), cell.get("incl"),
-                                  cell["spheres"], prec=cell.get("prec", "fp64"), tol=cell.get("tol", 1e-4),
-                                  max_iter=cell.get("max_iter", 10000), check_every=cell.get("check_every", 8),
-                                  want_eps=keep)
+        out = EffectiveTensor._solve(cell, ph, frac, keep)
         ctx.cell = cell
         ctx.ph = ph
         ctx.eps = out["eps"]
@@ -522,10 +561,7 @@ class EffectiveTensor(torch.autograd.Function):
         cell = ctx.cell
         eps = ctx.eps
         if eps is None:
-            eps = hm_effective_tensor(cell["n"], cell["dim"], ctx.ph, cell["rule"], frac.detach(),
-                                      cell.get("incl"), cell["spheres"], prec=cell.get("prec", "fp64"),
-                                      tol=cell.get("tol", 1e-4), max_iter=cell.get("max_iter", 10000),
-                                      check_every=cell.get("check_every", 8), want_eps=True)["eps"]
+            eps = EffectiveTensor._solve(cell, ctx.ph, frac, True)["eps"]
         dph, dfr = hm_solve_adjoint(cell["n"], cell["dim"], ctx.ph, cell["rule"], frac.detach(), cell.get("incl"),
                                     cell["spheres"], gC.detach().cpu().numpy(), eps,
                                     prec=cell.get("prec", "fp64"))

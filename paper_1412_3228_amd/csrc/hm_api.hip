@@ -40,6 +40,8 @@ const AxisKernels* axis_kernels_f32_g0(int n);
 const AxisKernels* axis_kernels_f32_g1(int n);
 const AxisKernels* axis_kernels_f32_g2(int n);
 const AxisKernels* axis_kernels_f32_g3(int n);
+const AxisKernels* axis_kernels_f64_g4(int n);
+const AxisKernels* axis_kernels_f32_g4(int n);
 
 const AxisKernels* axis_kernels(bool fp64, int n) {
   const AxisKernels* k = nullptr;
@@ -48,11 +50,13 @@ const AxisKernels* axis_kernels(bool fp64, int n) {
     if (!k) k = axis_kernels_f64_g1(n);
     if (!k) k = axis_kernels_f64_g2(n);
     if (!k) k = axis_kernels_f64_g3(n);
+    if (!k) k = axis_kernels_f64_g4(n);
   } else {
     if (!k) k = axis_kernels_f32_g0(n);
     if (!k) k = axis_kernels_f32_g1(n);
     if (!k) k = axis_kernels_f32_g2(n);
     if (!k) k = axis_kernels_f32_g3(n);
+    if (!k) k = axis_kernels_f32_g4(n);
   }
   return k;
 }
@@ -89,6 +93,11 @@ thread_local std::string g_last_error;
 thread_local hm_timing g_last_timing;
 thread_local bool g_have_timing = false;
 
+// Generation of the plan cache, bumped by hm_release_plans, so that the
+// record of a thread's last solve (hm_last_history) can tell that the plan
+// it points to was freed.
+unsigned g_plan_generation = 1;
+
 int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -107,13 +116,12 @@ int fail(int code, const char* fmt, ...) {
 
 constexpr int kMaxLoads = 4096;  // load cases per grid group (the y-sweep grid has 6 per load)
 
+// Line lengths with compiled transforms: the products of 3, 5 and 7 up to
+// 243, and those with a factor 11 or 13 up to 121 (solver kernels of both
+// precisions exist for exactly these).
 bool supported_length(int n) {
   if (n < 1 || n > 243) return false;
-  int m = n;
-  while (m % 7 == 0) m /= 7;
-  while (m % 5 == 0) m /= 5;
-  while (m % 3 == 0) m /= 3;
-  return m == 1;
+  return axis_kernels(true, n) != nullptr && axis_kernels(false, n) != nullptr;
 }
 
 int check_grid(const hm_grid* g) {
@@ -123,7 +131,10 @@ int check_grid(const hm_grid* g) {
     if (g->n[d] < 1) return fail(HM_E_ARG, "n[%d] = %d must be positive", d, g->n[d]);
     if (g->n[d] % 2 == 0) return fail(HM_E_SIZE, "n[%d] = %d must be odd", d, g->n[d]);
     if (!supported_length(g->n[d]))
-      return fail(HM_E_SIZE, "n[%d] = %d must be a product of 3, 5, 7 and <= 243", d, g->n[d]);
+      return fail(HM_E_SIZE,
+                  "n[%d] = %d has no compiled transform (products of 3, 5, 7 up to 243; with a factor 11 or 13 "
+                  "up to 121)",
+                  d, g->n[d]);
   }
   if (g->dim == 2 && g->n[2] != 1) return fail(HM_E_ARG, "2D grids need n[2] == 1");
   if (g->dim == 3 && (g->n[0] < 3 || g->n[1] < 3 || g->n[2] < 3))
@@ -207,6 +218,7 @@ struct Plan {
   SolverState* state = nullptr;
   SolverState* state_host = nullptr;  // pinned
   double* errhist = nullptr;
+  double* sighist = nullptr;
   int hist_cap = 0;
   char* prm = nullptr;       // parameter blob: SolveParams, loads, problems, spheres
   char* prm_host = nullptr;  // pinned staging of the blob
@@ -246,6 +258,7 @@ void free_plan(Plan* p) {
   (void)hipFree(p->errpart);
   (void)hipFree(p->state);
   (void)hipFree(p->errhist);
+  (void)hipFree(p->sighist);
   (void)hipFree(p->prm);
   (void)hipFree(p->mid);
   (void)hipFree(p->coef);
@@ -378,6 +391,7 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, int phys, Plan** ou
   a.dim = dim;
   a.n_load = n_load;
   a.cond = cond ? 1 : 0;
+
   if (cond)
     set_schedule(p, &p->ck[0]->x, &p->ck[1]->y, &p->ck[2]->z);
   else if (p->aniso)
@@ -403,12 +417,19 @@ void set_schedule(Plan* p, const XKern* X, const YKern* Y, const ZKern* Z) {
 int ensure_hist(Plan* p, int cap) {
   if (p->hist_cap >= cap) return HM_OK;
   if (p->errhist) (void)hipFree(p->errhist);
+  if (p->sighist) (void)hipFree(p->sighist);
   p->errhist = nullptr;
+  p->sighist = nullptr;
   p->hist_cap = 0;
+  p->args.errhist = nullptr;
+  p->args.sighist = nullptr;
+  p->args.hist_cap = 0;
   int rc = device_alloc((void**)&p->errhist, (size_t)p->n_load * cap * sizeof(double), "error history");
+  if (!rc) rc = device_alloc((void**)&p->sighist, (size_t)p->n_load * cap * 6 * sizeof(double), "stress history");
   if (rc) return rc;
   p->hist_cap = cap;
   p->args.errhist = p->errhist;
+  p->args.sighist = p->sighist;
   p->args.hist_cap = cap;
   drop_graphs(p);
   return HM_OK;
@@ -1141,6 +1162,26 @@ int run_cg(Group& g, const hm_solve_opts* opts, hipStream_t s) {
   return poll_done(p, s, &done);
 }
 
+struct LastSolve {
+  Plan* p = nullptr;
+  unsigned generation = 0;
+  int n_load = 0;
+  std::vector<int> iters;
+};
+thread_local LastSolve g_last_solve;
+
+void record_last_solve(std::vector<Group>& G) {
+  g_last_solve.p = nullptr;
+  if (G.size() != 1) return;
+  Plan* p = G[0].p;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  g_last_solve.p = p;
+  g_last_solve.generation = g_plan_generation;
+  g_last_solve.n_load = p->n_load;
+  g_last_solve.iters.resize(p->n_load);
+  for (int l = 0; l < p->n_load; ++l) g_last_solve.iters[l] = p->state_host[l].iters;
+}
+
 // Solves every group to its stop (or max_iter): iterate 0 directly, then
 // blocks of check_every iterations (one captured graph over all active
 // groups, or direct launches), polling the device-side stop flags between
@@ -1173,7 +1214,9 @@ int run_groups(std::vector<Group>& G, const std::vector<ProblemIn>& all, const h
   }
   if (opts->method == HM_CONJUGATE_GRADIENT) {
     if (G.size() != 1) return fail(HM_E_ARG, "conjugate gradients solve one grid group");
-    return run_cg(G[0], opts, s);
+    if ((rc = run_cg(G[0], opts, s))) return rc;
+    record_last_solve(G);
+    return HM_OK;
   }
   if (opts->profile) {
     if (G.size() != 1) return fail(HM_E_ARG, "profiling times a single grid group");
@@ -1259,11 +1302,13 @@ int run_groups(std::vector<Group>& G, const std::vector<ProblemIn>& all, const h
     bool d = false;
     if ((rc = poll_done(g.p, s, &d))) return rc;
   }
+  record_last_solve(G);
   return HM_OK;
 }
 
 // Status of one load case.
 int load_status(const SolverState& st) { return st.done ? st.status : HM_NOT_CONVERGED; }
+
 
 
 // Unit Mandel strains (tensor components) of a dimension: 6 in 3D, 3 in 2D.
@@ -1672,19 +1717,51 @@ int hm_schedule_count(const hm_grid* grid, hm_prec prec, int* nx, int* ny, int* 
   return HM_OK;
 }
 
+int hm_last_history(int n_load, int cap, double* err, double* sig) {
+  const LastSolve& L = g_last_solve;
+  if (!L.p) return fail(HM_E_ARG, "no single-cell solve on this thread");
+  if (!err) return fail(HM_E_ARG, "err is NULL");
+  if (cap < 1) return fail(HM_E_ARG, "cap must be >= 1");
+  Plan* p = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (L.generation != g_plan_generation) return fail(HM_E_ARG, "the plans of the last solve were released");
+    p = L.p;
+  }
+  if (n_load != L.n_load) return fail(HM_E_ARG, "the last solve had %d load cases, not %d", L.n_load, n_load);
+  const double nan = NAN;
+  for (int l = 0; l < n_load; ++l) {
+    const int cnt = std::min(std::min(cap, L.iters[l] + 1), p->hist_cap);
+    if (cnt > 0) {
+      HM_HIP(hipMemcpy(err + (size_t)l * cap, p->errhist + (size_t)l * p->hist_cap, (size_t)cnt * sizeof(double),
+                       hipMemcpyDeviceToHost));
+      if (sig)
+        HM_HIP(hipMemcpy(sig + (size_t)l * cap * 6, p->sighist + (size_t)l * p->hist_cap * 6,
+                         (size_t)cnt * 6 * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    for (int i = std::max(cnt, 0); i < cap; ++i) {
+      err[(size_t)l * cap + i] = nan;
+      if (sig)
+        for (int c = 0; c < 6; ++c) sig[((size_t)l * cap + i) * 6 + c] = nan;
+    }
+  }
+  return HM_OK;
+}
+
 void hm_release_plans(void) {
   std::lock_guard<std::mutex> lock(g_mutex);
+  ++g_plan_generation;
   for (auto& kv : g_plans) free_plan(kv.second);
   g_plans.clear();
   for (auto& kv : g_series) free_series(kv.second);
   g_series.clear();
 }
 
-// The two-phase filter (labels == NULL) and the multi-phase one (labels
-// 1..nlab per sphere, spheres of different labels must not overlap).
-static int filter_impl(const hm_grid* grid, const hm_sphere* spheres, int n_spheres, const int* labels, int nlab,
-                       double radius_vox, int subsamples, hm_rule rule, hm_prec prec, uint32_t* d_count,
-                       void* d_frac, int32_t* d_incl, void* stream) {
+// Checks the filter arguments and fills the lattice sphere table (host,
+// n_spheres entries) and the kernel arguments except the device pointers.
+static int filter_prepare(const hm_grid* grid, const hm_sphere* spheres, int n_spheres, const int* labels, int nlab,
+                          double radius_vox, int subsamples, hm_rule rule, hm_prec prec, uint32_t* d_count,
+                          void* d_frac, LatSphere* tab, FilterArgs& a) {
   int rc;
   if ((rc = check_grid(grid))) return rc;
   if ((rc = check_spheres(grid, spheres, n_spheres))) return rc;
@@ -1695,7 +1772,6 @@ static int filter_impl(const hm_grid* grid, const hm_sphere* spheres, int n_sphe
   if (!point && !(radius_vox > 0.0 && radius_vox * subsamples <= 64.0))
     return fail(HM_E_ARG, "radius_vox must be > 0 with radius_vox * subsamples <= 64");
   if (!d_count || !d_frac) return fail(HM_E_ARG, "d_count and d_frac must not be NULL");
-  FilterArgs a;
   memset(&a, 0, sizeof a);
   a.nsph = n_spheres;
   a.dim = grid->dim;
@@ -1705,7 +1781,6 @@ static int filter_impl(const hm_grid* grid, const hm_sphere* spheres, int n_sphe
     a.n[d] = grid->n[d];
     a.P[d] = 2LL * grid->n[d] * subsamples;
   }
-  std::vector<LatSphere> tab((size_t)(n_spheres > 0 ? n_spheres : 1));
   for (int k = 0; k < n_spheres; ++k) {
     for (int d = 0; d < 3; ++d) {
       const double c = spheres[k].c[d] * s2;
@@ -1758,6 +1833,21 @@ static int filter_impl(const hm_grid* grid, const hm_sphere* spheres, int n_sphe
       }
     }
   }
+  return HM_OK;
+}
+
+// The two-phase filter (labels == NULL) and the multi-phase one (labels
+// 1..nlab per sphere, spheres of different labels must not overlap).
+static int filter_impl(const hm_grid* grid, const hm_sphere* spheres, int n_spheres, const int* labels, int nlab,
+                       double radius_vox, int subsamples, hm_rule rule, hm_prec prec, uint32_t* d_count,
+                       void* d_frac, int32_t* d_incl, void* stream) {
+  int rc;
+  if (n_spheres < 0) return fail(HM_E_ARG, "n_spheres < 0");
+  std::vector<LatSphere> tab((size_t)(n_spheres > 0 ? n_spheres : 1));
+  FilterArgs a;
+  if ((rc = filter_prepare(grid, spheres, n_spheres, labels, nlab, radius_vox, subsamples, rule, prec, d_count,
+                           d_frac, tab.data(), a)))
+    return rc;
   hipStream_t s = (hipStream_t)stream;
   LatSphere* dtab = nullptr;
   int* dlab = nullptr;

@@ -121,7 +121,8 @@ struct SolveArgs {
   double* taupart;  // [n_load][g2][6]  per-block sums of tau
   double* errpart;  // [n_load][ny * ntx4]  per-block equilibrium sums
   SolverState* state;   // [n_load]
-  double* errhist;      // [n_load][hist_cap]
+  double* errhist;      // [n_load][hist_cap]  error of every evaluated iterate
+  double* sighist;      // [n_load][hist_cap][6]  <sigma> of every evaluated iterate
   const SolveParams* prm;
   void* eps_out;        // export target T[n_load][6][N]
   const void* twx;      // twiddles exp(-2 pi i k / n), per axis, cx<T>[n]

@@ -163,7 +163,7 @@ __global__ __launch_bounds__(NT) void k_cxsweep(SolveArgs a) {
   // each thread reads and then overwrites the same three real slots of its
   // voxel (component 2 shares a complex slot with the neighbouring line,
   // but in the other half), so the voxel pass needs no barrier of its own
-  T acc[3] = {T(0), T(0), T(0)};
+  double acc[3] = {0.0, 0.0, 0.0};  // FP64 thread partials
 #pragma unroll
   for (int i = 0; i < RV; ++i) {
     const int l = wv + NW * i;
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(NT) void k_cxsweep(SolveArgs a) {
       if (line < nlines) {
         cond_tau<T>(rows[i][m], g, tau);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c] += tau[c];
+        for (int c = 0; c < 3; ++c) acc[c] += (double)tau[c];
       }
 #pragma unroll
       for (int c = 0; c < 3; ++c) bufr[slot(x, l, c)] = tau[c];
@@ -330,8 +330,8 @@ __global__ __launch_bounds__(NT) void k_czsweep(SolveArgs a) {
     const double x0 = twopi * kx, x1 = twopi * ay, x2 = twopi * az;
     double dd;
     if constexpr (sizeof(T) == 4) {
-      const float dx = av[q].x - cur[q].x, dy = av[q].y - cur[q].y;
-      dd = (double)(dx * dx + dy * dy);
+      const double dx = (double)av[q].x - (double)cur[q].x, dy = (double)av[q].y - (double)cur[q].y;
+      dd = dx * dx + dy * dy;
     } else {
       const double dx = av[q].x - cur[q].x, dy = av[q].y - cur[q].y;
       dd = dx * dx + dy * dy;

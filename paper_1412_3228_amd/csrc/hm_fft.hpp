@@ -1,6 +1,8 @@
 // Workgroup-cooperative mixed-radix Stockham FFT on lines staged in LDS;
-// radices are products of 3, 5 and 7 (composite ones computed in registers).  The discrete Fourier transforms of Section 2 run on odd grids, so
-// every line length is a product of odd radices; no power-of-two tricks.
+// radices are the primes 3, 5, 7, 11, 13 and products of 3, 5 and 7
+// (composite ones computed in registers).  The discrete Fourier transforms
+// of Section 2 run on odd grids, so every line length is a product of odd
+// radices; no power-of-two tricks.
 //
 // Layout: a workgroup transforms L lines of length N held in LDS as
 // buf[j * LD + l] (element j of line l, row stride LD >= L; an odd LD spreads
@@ -65,7 +67,9 @@ __device__ __forceinline__ void dft_small(cx<T>* x) {
   for (int k = 0; k < R; ++k) x[k] = y[k];
 }
 
-constexpr int smallest_factor(int r) { return r % 3 == 0 ? 3 : (r % 5 == 0 ? 5 : (r % 7 == 0 ? 7 : r)); }
+constexpr int smallest_factor(int r) {
+  return r % 3 == 0 ? 3 : (r % 5 == 0 ? 5 : (r % 7 == 0 ? 7 : (r % 11 == 0 ? 11 : (r % 13 == 0 ? 13 : r))));
+}
 
 // In-register DFT of any radix R whose prime factors are 3, 5, 7, computed
 // as A x B with A the smallest factor: with n = B n1 + n2 and k = k1 + A k2,
@@ -75,7 +79,7 @@ constexpr int smallest_factor(int r) { return r % 3 == 0 ? 3 : (r % 5 == 0 ? 5 :
 // B k1 + k2, and a final register permutation restores natural order.
 template <typename T, int R, int SIGN>
 __device__ __forceinline__ void dft_radix(cx<T>* x) {
-  if constexpr (R == 3 || R == 5 || R == 7) {
+  if constexpr (R == 3 || R == 5 || R == 7 || R == 11 || R == 13) {
     dft_small<T, R, SIGN>(x);
   } else {
     constexpr int A = smallest_factor(R);
@@ -112,12 +116,15 @@ __device__ __forceinline__ void dft_radix(cx<T>* x) {
 // registers, so doubles get smaller ones.
 template <typename T> constexpr int max_radix() { return sizeof(T) == 8 ? 9 : 27; }
 
-// Compile-time radix schedule of a length: its prime factors (7s, then 5s,
-// then 3s) merged greedily into radices no larger than RMAX, largest first
-// (the first pass needs no twiddles).
+// Compile-time radix schedule of a length: its prime factors (13s, 11s,
+// 7s, 5s, then 3s) merged greedily into radices no larger than RMAX,
+// largest first (the first pass needs no twiddles).  An 11 or 13 is always a
+// radix of its own (11 x 3 exceeds every RMAX).
 template <int N, int RMAX> struct FftPlan {
   static constexpr int nprime() {
     int n = N, c = 0;
+    while (n % 13 == 0) { n /= 13; ++c; }
+    while (n % 11 == 0) { n /= 11; ++c; }
     while (n % 7 == 0) { n /= 7; ++c; }
     while (n % 5 == 0) { n /= 5; ++c; }
     while (n % 3 == 0) { n /= 3; ++c; }
@@ -125,6 +132,8 @@ template <int N, int RMAX> struct FftPlan {
   }
   static constexpr int prime(int i) {
     int n = N, c = 0;
+    while (n % 13 == 0) { if (c == i) return 13; n /= 13; ++c; }
+    while (n % 11 == 0) { if (c == i) return 11; n /= 11; ++c; }
     while (n % 7 == 0) { if (c == i) return 7; n /= 7; ++c; }
     while (n % 5 == 0) { if (c == i) return 5; n /= 5; ++c; }
     while (n % 3 == 0) { if (c == i) return 3; n /= 3; ++c; }
@@ -168,7 +177,7 @@ template <int N, int RMAX> struct FftPlan {
     for (int q = 0; q < p; ++q) s *= radix(q);
     return s;
   }
-  static_assert(nprime() >= 0, "line length must be a product of 3, 5 and 7");
+  static_assert(nprime() >= 0, "line length must be a product of 3, 5, 7, 11 and 13");
 };
 
 // Ordering of LDS accesses between the lanes of one wavefront: LDS executes

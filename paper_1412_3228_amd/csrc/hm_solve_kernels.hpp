@@ -445,7 +445,7 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
 #pragma unroll
       for (int m = 0; m < KX; ++m) material_row<T>(MAT, mv[i][m], rows[i][m]);
   }
-  T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};  // thread partials, then FP64 block sums
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // FP64 thread partials, then FP64 block sums
 #pragma unroll
   for (int i = 0; i < RV; ++i) {
     const int l = wv + NW * i;
@@ -474,7 +474,7 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
         else
           row_tau<T>(MAT.aniso && mv[i][m] >= 0, rows[i][m], e, tau);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) acc[c] += tau[c];
+        for (int c = 0; c < 6; ++c) acc[c] += (double)tau[c];
       }
 #pragma unroll
       for (int p = 0; p < 3; ++p) buf[x * LD + p * L + l] = cx<T>{tau[2 * p], tau[2 * p + 1]};
@@ -763,12 +763,12 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
     const double x0 = twopi * kx, x1 = twopi * ay, x2 = twopi * az;
     double dd;
     if constexpr (sizeof(T) == 4) {
-      // single-precision differences of single-precision values, squared and
-      // summed in single precision; the weighted total stays in FP64
-      const float d0x = z[q].a0.x - pv[0].x, d0y = z[q].a0.y - pv[0].y;
-      const float d1x = z[q].a1.x - pv[1].x, d1y = z[q].a1.y - pv[1].y;
-      const float d2x = z[q].a2.x - pv[2].x, d2y = z[q].a2.y - pv[2].y;
-      dd = (double)(d0x * d0x + d0y * d0y + d1x * d1x + d1y * d1y + d2x * d2x + d2y * d2y);
+      // differences of the single-precision values taken, squared and
+      // summed in FP64
+      const double d0x = (double)z[q].a0.x - (double)pv[0].x, d0y = (double)z[q].a0.y - (double)pv[0].y;
+      const double d1x = (double)z[q].a1.x - (double)pv[1].x, d1y = (double)z[q].a1.y - (double)pv[1].y;
+      const double d2x = (double)z[q].a2.x - (double)pv[2].x, d2y = (double)z[q].a2.y - (double)pv[2].y;
+      dd = d0x * d0x + d0y * d0y + d1x * d1x + d1y * d1y + d2x * d2x + d2y * d2y;
     } else {
       const double d0x = z[q].a0.x - pv[0].x, d0y = z[q].a0.y - pv[0].y;
       const double d1x = z[q].a1.x - pv[1].x, d1y = z[q].a1.y - pv[1].y;
@@ -925,7 +925,7 @@ __global__ __launch_bounds__(64 * NW) void k_xsweep_wave(SolveArgs a) {
   T rows[QV][8];
 #pragma unroll
   for (int q = 0; q < QV; ++q) material_row<T>(MAT, mv[q], rows[q]);
-  T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < QV; ++q) {
     const int idx = lane + 64 * q;
@@ -947,7 +947,7 @@ __global__ __launch_bounds__(64 * NW) void k_xsweep_wave(SolveArgs a) {
     if (line < nlines) {
       row_tau<T>(MAT.aniso && mv[q] >= 0, rows[q], e, tau);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) acc[c] += tau[c];
+      for (int c = 0; c < 6; ++c) acc[c] += (double)tau[c];
     }
 #pragma unroll
     for (int p = 0; p < 3; ++p) buf[x * LD + p * LW + l] = cx<T>{tau[2 * p], tau[2 * p + 1]};
@@ -1215,7 +1215,11 @@ __global__ __launch_bounds__(NT) void k_finalize(SolveArgs a) {
   const double res = sqrt(S);
   const double e = den > 0.0 ? res / den : (S == 0.0 ? 0.0 : INFINITY);
   const int i = st->iter;
-  if (i < a.hist_cap) a.errhist[(size_t)load * a.hist_cap + i] = e;
+  if (i < a.hist_cap) {
+    a.errhist[(size_t)load * a.hist_cap + i] = e;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a.sighist[((size_t)load * a.hist_cap + i) * 6 + c] = sig[c];
+  }
   if (i == 0) {
     st->err0 = e;
     st->res0 = res;
@@ -1404,7 +1408,11 @@ __global__ __launch_bounds__(NT) void k_cg_scalar(SolveArgs a) {
   const double rms = sqrt(fmax(rr, 0.0) * (double)a.nx / N);
   const double e = fro > 0.0 ? rms / fro : (rr == 0.0 ? 0.0 : INFINITY);
   const int i = STEP == CGS_INIT ? 0 : st->iter;
-  if (i < a.hist_cap) a.errhist[(size_t)load * a.hist_cap + i] = e;
+  if (i < a.hist_cap) {
+    a.errhist[(size_t)load * a.hist_cap + i] = e;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a.sighist[((size_t)load * a.hist_cap + i) * 6 + k] = sig[k];
+  }
   if (i == 0) {
     st->err0 = e;
     st->res0 = rms;
@@ -1506,7 +1514,8 @@ template <typename T, int N, int V> struct YTile {
 template <typename T, int N, int V> struct ZTile {
   static constexpr int W0 = 128 / (int)sizeof(cx<T>);
   static constexpr int W1 = 256 / (int)sizeof(cx<T>);
-  static constexpr int QT = V == 2 ? 1 : (sizeof(T) == 8 ? 2 : 4) / (N % 7 == 0 ? 2 : 1);
+  static constexpr int QT =
+      V == 2 ? 1 : (sizeof(T) == 8 ? 2 : 4) / ((N % 7 == 0 || N % 11 == 0 || N % 13 == 0) ? 2 : 1);
   static constexpr int W = V == 1 ? ((W1 * N + QT - 1) / QT <= 1024 ? W1 : W0 / 2) : W0;
   static constexpr int lds3 = N * ((3 * W) | 1) * (int)sizeof(cx<T>);
   static constexpr int lds2 = N * ((2 * W) | 1) * (int)sizeof(cx<T>);
@@ -1606,6 +1615,20 @@ AxisKernels make_axis_kernels() {
     if constexpr (6 * N * (W | 1) * (int)sizeof(cx<T>) <= 64 * 1024)
       k.z[k.nzv++] = ZKern{&launch_z_wave<T, N, W>, W, 384, -1, instance_name<4, T, N, W>("zsweep_wave")};
   }
+  return k;
+}
+
+// One schedule per sweep (the first variant of each): the lengths with a
+// factor 11 or 13, which the resolution study of Section 3 needs but the
+// benchmark workloads do not.
+template <typename T, int N>
+AxisKernels make_axis_kernels_basic() {
+  AxisKernels k;
+  k.n = N;
+  k.x[0] = make_x<T, N, 0>();
+  k.y[0] = make_y<T, N, 0>();
+  k.z[0] = make_z<T, N, 0>();
+  k.nxv = k.nyv = k.nzv = 1;
   return k;
 }
 

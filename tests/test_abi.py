@@ -58,9 +58,10 @@ def test_argument_errors_without_gpu():
     sph = (_lib.HmSphere * 1)()
     rc = lib.hm_filter(ctypes.byref(g), sph, 0, 1.0, 8, 1, 0, None, None, None, None)
     assert rc == _lib.HM_E_SIZE and b"odd" in lib.hm_last_error()
-    g.n[0] = 11
-    rc = lib.hm_filter(ctypes.byref(g), sph, 0, 1.0, 8, 1, 0, None, None, None, None)
-    assert rc == _lib.HM_E_SIZE
+    for bad in (17, 143, 245):  # a prime above 13, a length with no compiled transform, beyond 243
+        g.n[0] = bad
+        rc = lib.hm_filter(ctypes.byref(g), sph, 0, 1.0, 8, 1, 0, None, None, None, None)
+        assert rc == _lib.HM_E_SIZE and b"no compiled transform" in lib.hm_last_error()
     g.n[0] = 15
     rc = lib.hm_filter(ctypes.byref(g), sph, 0, 1.0, 7, 1, 0, None, None, None, None)
     assert rc == _lib.HM_E_ARG and b"even" in lib.hm_last_error()

@@ -5,7 +5,7 @@ Disk of radius pi/15 centred in the unit square, E_inclusion / E_matrix =
 (linear, so C_1111 carries it), fixed-point tolerance 1e-4, FP64.  Each
 treatment -- no filter (indicator at the pixel centre), or the Voigt,
 Reuss and 2-layer filters at several radii (pixel units) -- is solved at
-the odd 3/5/7-smooth resolutions from 7 to 125.  N_1% is the smallest swept
+the 25 odd resolutions from 7 to 125 whose prime factors are at most 13.  N_1% is the smallest swept
 resolution from which every finer swept resolution is within 1 % of the
 converged stress, taken as the median of the four treatments at radius 0.55
 on a 243 x 243 grid.  Section 2 reports, for the two efficient filters of
@@ -13,8 +13,8 @@ each contrast, an optimum radius of 0.5-0.55 at which N_1% is divided by
 2.6 to 7.2.  Checked here: for each contrast the filter with the smallest
 N_1% reaches it at radius 0.55 (of 0.3, 0.55, 1, 1.5), and the unfiltered
 N_1% over that one lies in the printed 2.6-7.2 range.  The swept sizes are
-sparser than the paper's (every size from 6 to 128); the whole table is
-printed.
+sparser than the paper's (every size from 6 to 128: the transforms need
+prime factors of at most 13); the whole table is printed.
 """
 import numpy as np
 import pytest

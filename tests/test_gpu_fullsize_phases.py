@@ -7,8 +7,9 @@ at the sizes bench.py measures them:
 * three-phase cell (20 spheres, two inclusion phases): per-phase counts at
   sampled voxels bit-exact against the oracle; making phase 2 identical to
   phase 1 reproduces the two-phase solve of the union (merging identical
-  phases changes nothing); the converged tensor is symmetric and lies
-  between the softest and the stiffest phase; mixed within 1e-4 of FP64.
+  phases changes nothing); the tightly converged (1e-9) FP64 tensor is
+  symmetric and inside the Voigt and Reuss bounds of the mean fractions;
+  the mixed tensor is within 1e-5 of it.
 """
 import numpy as np
 import pytest
@@ -73,18 +74,29 @@ def test_three_phase_cell_properties(hm):
     b = hm.hm_effective_tensor(w.n, 3, (ph[0], ph[1]), w.rule, fu, iu, w.spheres, tol=0.0, max_iter=30,
                                autotune=False)
     assert rel(a["C"], b["C"]) < 1e-12
-    log("nphase 125^3: three phases, fp64 and mixed")
-    o64 = hm.hm_effective_tensor_phases(w.n, 3, ph, w.rule, frac, tol=1e-4, max_iter=5000, check_every=16,
+    log("nphase 125^3: three phases, fp64 (tight) and mixed")
+    o64 = hm.hm_effective_tensor_phases(w.n, 3, ph, w.rule, frac, tol=1e-9, max_iter=20000, check_every=32,
                                         use_graph=True)
     _, f32 = hm.hm_filter_phases(w.n, 3, w.spheres, lab, 3, w.radius_vox, w.subsamples, w.rule, "mixed", DEV)
     o32 = hm.hm_effective_tensor_phases(w.n, 3, ph, w.rule, f32, prec="mixed", tol=1e-4, max_iter=5000,
                                         check_every=16, stall_window=20, use_graph=True)
     C = o64["C"]
+    log("nphase 125^3: fp64 iters %s, mixed statuses %s errors %s, mixed vs fp64 %.2e"
+        % ([r["iters"] for r in o64["reports"]], [r["status"] for r in o32["reports"]],
+           ["%.1e" % r["err"] for r in o32["reports"]], rel(o32["C"], C)))
     assert o64["status"] == 0
-    assert np.allclose(C, C.T, rtol=0, atol=1e-4 * np.max(np.abs(C)))
-    # between the softest and stiffest phase (Mandel order)
-    cs = [rules.to_mandel(rules.iso_tensor(*p)) for p in ph]
+    assert all(r["status"] in (0, 2) for r in o32["reports"])
+    assert np.allclose(C, C.T, rtol=0, atol=1e-8 * np.max(np.abs(C)))
+    # Voigt and Reuss bounds of the mean phase fractions (eqs. 3-4 applied
+    # to the cell averages): the filtered field's own Voigt bound is the
+    # Voigt tensor of the mean fractions, and its Reuss bound lies above
+    # the Reuss tensor of the mean fractions
+    fm = frac.cpu().numpy().mean(axis=1)
+    f_all = np.array([1.0 - fm.sum(), fm[0], fm[1]])
+    cs = [rules.iso_tensor(*p) for p in ph]
+    up = rules.to_mandel(NP.voigt(f_all, cs))
+    lo = rules.to_mandel(NP.reuss(f_all, cs))
     Cs = 0.5 * (C + C.T)
-    assert np.min(np.linalg.eigvalsh(cs[1] - Cs)) > 0.0
-    assert np.min(np.linalg.eigvalsh(Cs - cs[2])) > 0.0
-    assert rel(o32["C"], C) < 1e-4
+    assert np.min(np.linalg.eigvalsh(up - Cs)) > 0.0
+    assert np.min(np.linalg.eigvalsh(Cs - lo)) > 0.0
+    assert rel(o32["C"], C) < 1e-5

@@ -1,0 +1,288 @@
+"""Oracle parity of every compiled transform length on every axis.
+
+The sweeps are compiled per line length (one instantiation per length and
+precision), so each length the solver accepts beyond the small ones that the
+other parity tests use is checked here on slab cells that put it on one axis
+(the other two 9 and 15 voxels thick), at sizes the oracle runs in seconds:
+
+* the solve (Section 2, eqs. 1-a, 1-b, 2) after k = 3 iterations for every
+  homogenisation rule (eqs. 3-5) and both precisions: strain field, mean
+  stress and equilibrium error of two load cases, FP64 within 1e-10 and the
+  mixed path within 2e-5 of the oracle.  The fractions are a seeded field
+  (a quarter pure matrix, a quarter pure inclusion, the rest fractional) and
+  the normal-sphere ids seeded sphere indices, both given to the two sides
+  as inputs, so that every voxel class and table path runs at every length;
+* the filter counts and fractions at sampled voxels of the same cells,
+  bit-exact (integer counts);
+* every compiled tile schedule of the 125- and 243-point sweeps (the
+  autotuner's candidates; each sweep's variants depend only on its own axis
+  length, so the slab cells reach every one of them);
+* a batch of slab cells with 105- and 135-point lines (several grids, two
+  cells sharing one grid) solved in one call, against the oracle's
+  effective tensors at fixed iterations;
+* the gradient by the adjoint identity on 135-point slab cells against the
+  oracle's Hill gradient (FP64 within 1e-9; the mixed path's phase and
+  FP32 fraction-field derivatives within 1e-4);
+* the 65 x 65 disk of Figures 2-4 (a length with a factor 13): filter
+  counts bit-exact and k = 5 iterates of every rule in both precisions.
+"""
+import concurrent.futures
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import COMPS, log, oracle_fields_to_comps, rel
+from oracle import filter as ofilter, gradient as ogradient, solver as osolver
+from workloads import fig1_disk_case, random_fraction_case, thin_grid_case
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+LENGTHS = (49, 75, 81, 105, 125, 135, 147, 175, 189, 225, 243,
+           11, 13, 33, 39, 55, 65, 77, 91, 99, 117, 121)  # the second row: radix-11 and radix-13 passes
+RULES = ("none", "voigt", "reuss", "laminate")
+K = 3
+E2 = np.array([[0.01, -0.004, 0.002, 0.001, -0.003, 0.005], [0.0, 0.0, 0.0, 0.0, 0.0, 0.01]])
+# oracle runs, computed by a thread pool (NumPy releases the interpreter
+# lock in its transforms and contractions) while the GPU tests run
+_JOBS = {}
+_POOL = None
+
+
+def _job(key, fn, *args):
+    global _POOL
+    if _POOL is None:
+        _POOL = concurrent.futures.ThreadPoolExecutor(max_workers=min(16, len(os.sched_getaffinity(0))))
+    if key not in _JOBS:
+        _JOBS[key] = _POOL.submit(fn, *args)
+    return _JOBS[key]
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import paper_1412_3228_amd as hm_mod
+    assert torch.cuda.is_available() and hm_mod.device_ok()
+    # queue every oracle run of the module in the order the tests need them
+    for L, ax in _cases():
+        for rule in RULES:
+            _oracle_job(thin_grid_case(L, ax), rule)
+    for i, w in enumerate(_batch_cells()):
+        _job(("batch", i), _batch_oracle, i, w)
+    for axis in (0, 2):
+        _job(("adjoint", axis), _adjoint_oracle, axis)
+    for rule in RULES:
+        _job(("disk65", rule), _disk65_oracle, rule)
+    yield hm_mod
+    hm_mod.release_plans()
+
+
+def _inputs(w, rule):
+    """Seeded fractions (0/1 only for rule none) and normal-sphere ids."""
+    f = random_fraction_case(17 + w.n[0] + 3 * w.n[1], w.n).reshape(-1)
+    frac = (f > 0) & (f < 1)
+    f = np.where(frac, np.clip(f, 1e-3, 1.0 - 1e-3), f)
+    if rule == "none":
+        f = (f >= 0.5).astype(np.float64)
+        frac = np.zeros_like(frac)
+    rng = np.random.default_rng(w.n[0] * 7 + w.n[2])
+    incl = np.where(frac, rng.integers(0, len(w.spheres), f.size), -1).astype(np.int32)
+    return f, incl
+
+
+def _rule_oracle(w, rule):
+    f, incl = _inputs(w, rule)
+    vox = ofilter.all_voxels(w.n)
+    nrm = ofilter.interface_normals(w.n, 3, w.spheres, incl.astype(np.int64), vox) if rule == "laminate" else None
+    fld = osolver.StiffnessField(w.n, 3, w.phases, rule, f, nrm)
+    c0 = osolver.reference_medium(w.phases)
+    return [osolver.solve(fld, e, c0, 0.0, K) for e in E2]
+
+
+def _oracle_job(w, rule):
+    return _job((w.n, rule), _rule_oracle, w, rule)
+
+
+def _oracle(w, rule):
+    return _oracle_job(w, rule).result()
+
+
+def _compare(out, refs, tol, what):
+    for l, r in enumerate(refs):
+        sig = np.array([r["sig_mean"][i, j] for (i, j) in COMPS])
+        e = out["eps"][l].cpu().numpy().astype(np.float64)
+        errs = (rel(out["sig_mean"][l], sig), rel(e, oracle_fields_to_comps(r["eps"])),
+                abs(out["reports"][l]["err"] - r["err"]) / r["err"])
+        assert max(errs) < tol, (what, l, errs)
+
+
+def _cases():
+    return [(L, ax) for L in LENGTHS for ax in (0, 1, 2)]
+
+
+@pytest.mark.parametrize("L,axis", _cases())
+def test_length_on_axis_matches_oracle(hm, L, axis):
+    w = thin_grid_case(L, axis)
+    log("length %d on axis %d: grid %s, %d spheres" % (L, axis, w.n, len(w.spheres)))
+    for rule in RULES:
+        f, incl = _inputs(w, rule)
+        refs = _oracle(w, rule)
+        for prec, dt, tol in (("fp64", torch.float64, 1e-10), ("mixed", torch.float32, 2e-5)):
+            out = hm.hm_solve(w.n, 3, w.phases, rule, torch.tensor(f, dtype=dt, device=DEV),
+                              torch.tensor(incl, device=DEV), w.spheres, E2, prec=prec, tol=0.0, max_iter=K,
+                              want_eps=True, autotune=False)
+            assert all(r["iters"] == K for r in out["reports"])
+            _compare(out, refs, tol, (rule, prec))
+
+
+@pytest.mark.parametrize("L,axis", [(L, ax) for L in (49, 135, 243) for ax in (0, 1, 2)])
+def test_filter_on_slab_cells_bit_exact_at_sampled_voxels(hm, L, axis):
+    w = thin_grid_case(L, axis)
+    log("filter on %s" % (w.n,))
+    cnt, frac, incl = hm.hm_filter(w.n, 3, w.spheres, w.radius_vox, w.subsamples, w.rule, "fp64", DEV)
+    _, f32, _ = hm.hm_filter(w.n, 3, w.spheres, w.radius_vox, w.subsamples, w.rule, "mixed", DEV)
+    c = cnt.cpu().numpy()
+    rng = np.random.default_rng(L + axis)
+    M = ofilter.stencil_offsets(w.radius_vox, w.subsamples, 3).shape[0]
+    mid = np.nonzero((c > 0) & (c < M))[0]
+    pick = np.concatenate([rng.choice(c.size, 150, replace=False), rng.choice(mid, 150, replace=False)])
+    vox = ofilter.all_voxels(w.n)[pick]
+    ref, M2 = ofilter.counts_at(w.n, 3, w.spheres, w.radius_vox, w.subsamples, vox)
+    assert M2 == M and np.array_equal(c[pick], ref)
+    assert np.array_equal(frac.cpu().numpy()[pick], ref.astype(np.float64) / np.float64(M))
+    assert np.array_equal(f32.cpu().numpy()[pick], ref.astype(np.float32) / np.float32(M))
+    sel = pick[(c[pick] > 0) & (c[pick] < M)]
+    nref = ofilter.normal_sphere(w.n, 3, w.spheres, w.subsamples, ofilter.all_voxels(w.n)[sel])
+    assert np.array_equal(incl.cpu().numpy()[sel], nref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("L,axis", [(L, ax) for L in (125, 243) for ax in (0, 1, 2)])
+def test_every_schedule_of_the_long_axis_matches_oracle(hm, prec, L, axis):
+    w = thin_grid_case(L, axis)
+    counts = hm.schedule_count(w.n, 3, prec)
+    log("schedules %s %s: %s variants" % (prec, w.n, counts))
+    f, incl = _inputs(w, "laminate")
+    refs = _oracle(w, "laminate")
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    fd, idv = torch.tensor(f, dtype=dt, device=DEV), torch.tensor(incl, device=DEV)
+    tol = 1e-10 if prec == "fp64" else 2e-5
+    for v in range(counts[axis]):
+        sch = [0, 0, 0]
+        sch[axis] = v
+        out = hm.hm_solve(w.n, 3, w.phases, "laminate", fd, idv, w.spheres, E2, prec=prec, tol=0.0, max_iter=K,
+                          want_eps=True, schedule=tuple(sch))
+        _compare(out, refs, tol, ("schedule", tuple(sch)))
+
+
+def _batch_cells():
+    return [thin_grid_case(105, 0, seed=21, contrast=10.0, rule="laminate"),
+            thin_grid_case(105, 0, seed=22, contrast=0.05, rule="reuss"),
+            thin_grid_case(135, 1, seed=23, contrast=30.0, rule="voigt"),
+            thin_grid_case(135, 2, seed=24, contrast=0.2, rule="laminate"),
+            thin_grid_case(105, 2, seed=25, contrast=4.0, rule="laminate", thin=(15, 9))]
+
+
+def _batch_inputs(i, w):
+    f = random_fraction_case(90 + i, w.n).reshape(-1)
+    mixed = (f > 0) & (f < 1)
+    f = np.where(mixed, np.clip(f, 1e-3, 1.0 - 1e-3), f)
+    incl = np.where(mixed, np.random.default_rng(i).integers(0, len(w.spheres), f.size), -1).astype(np.int32)
+    return f, incl
+
+
+def _batch_oracle(i, w):
+    f, incl = _batch_inputs(i, w)
+    vox = ofilter.all_voxels(w.n)
+    nrm = ofilter.interface_normals(w.n, 3, w.spheres, incl.astype(np.int64), vox)
+    fld = osolver.StiffnessField(w.n, 3, w.phases, w.rule, f, nrm if w.rule == "laminate" else None)
+    return osolver.effective_tensor(fld, osolver.reference_medium(w.phases), 0.0, K, 3)[0]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_with_105_and_135_lines_matches_oracle(hm, prec):
+    cells = _batch_cells()
+    log("batch of %d slab cells (%s): %s" % (len(cells), prec, [w.n for w in cells]))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    probs, refs = [], []
+    for i, w in enumerate(cells):
+        f, incl = _batch_inputs(i, w)
+        probs.append({"n": w.n, "dim": 3, "phases": w.phases, "rule": w.rule,
+                      "frac": torch.tensor(f, dtype=dt, device=DEV), "incl": torch.tensor(incl, device=DEV),
+                      "spheres": w.spheres})
+        refs.append(_job(("batch", i), _batch_oracle, i, w).result())
+    out = hm.hm_effective_tensor_batch(probs, prec=prec, tol=0.0, max_iter=K, check_every=2, use_graph=True)
+    tol = 1e-10 if prec == "fp64" else 2e-5
+    for i, (res, C) in enumerate(zip(out["results"], refs)):
+        assert all(r["iters"] == K for r in res["reports"])
+        e = rel(res["C"], C)
+        log("batch cell %d %s: %.2e" % (i, cells[i].n, e))
+        assert e < tol
+
+
+def _adjoint_oracle(axis):
+    """Oracle filter, tightly converged fields and Hill gradient of a 135-point slab cell."""
+    w = thin_grid_case(135, axis, seed=31, contrast=3.0, rule="laminate")
+    vox = ofilter.all_voxels(w.n)
+    cnt, M = ofilter.counts_at(w.n, 3, w.spheres, w.radius_vox, w.subsamples, vox)
+    f64 = cnt.astype(np.float64) / np.float64(M)
+    mixed = (cnt > 0) & (cnt < M)
+    incl = np.full(f64.size, -1, dtype=np.int64)
+    incl[mixed] = ofilter.normal_sphere(w.n, 3, w.spheres, w.subsamples, vox[mixed])
+    nrm = ofilter.interface_normals(w.n, 3, w.spheres, incl, vox)
+    fld = osolver.StiffnessField(w.n, 3, w.phases, "laminate", f64, nrm)
+    _, reps = osolver.effective_tensor(fld, osolver.reference_medium(w.phases), 1e-12, 3000, 3, keep_fields=True)
+    G = np.random.default_rng(3 + axis).standard_normal((6, 6))
+    rph, rfr = ogradient.hill_gradient(fld, [r["eps"] for r in reps], G, w.phases, nrm)
+    return {"w": w, "cnt": cnt, "M": M, "f64": f64, "incl": incl, "G": G, "rph": rph, "rfr": rfr}
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_adjoint_on_135_point_slab_matches_oracle_gradient(hm, axis):
+    o = _job(("adjoint", axis), _adjoint_oracle, axis).result()
+    w, f64, incl, G, rph, rfr = o["w"], o["f64"], o["incl"], o["G"], o["rph"], o["rfr"]
+    flt_cnt, M = o["cnt"], o["M"]
+    log("adjoint on %s" % (w.n,))
+    idv = torch.tensor(incl.astype(np.int32), device=DEV)
+    fd = torch.tensor(f64, device=DEV)
+    out = hm.hm_effective_tensor(w.n, 3, w.phases, "laminate", fd, idv, w.spheres, prec="fp64", tol=1e-12,
+                                 max_iter=3000, check_every=8, want_eps=True)
+    dph, dfr = hm.hm_solve_adjoint(w.n, 3, w.phases, "laminate", fd, idv, w.spheres, G, out["eps"])
+    log("fp64: phases %.2e, fraction field %.2e" % (rel(dph, rph), rel(dfr.cpu().numpy(), rfr)))
+    assert rel(dph, rph) < 1e-9
+    assert rel(dfr.cpu().numpy(), rfr) < 1e-9
+    f32 = torch.tensor(flt_cnt.astype(np.float32) / np.float32(M), device=DEV)
+    m = hm.hm_effective_tensor(w.n, 3, w.phases, "laminate", f32, idv, w.spheres, prec="mixed", tol=1e-7,
+                               max_iter=3000, check_every=8, stall_window=20, want_eps=True)
+    d32, r32 = hm.hm_solve_adjoint(w.n, 3, w.phases, "laminate", f32, idv, w.spheres, G, m["eps"], prec="mixed")
+    log("mixed (statuses %s, errors %s): phases %.2e, fraction field %.2e"
+        % ([r["status"] for r in m["reports"]], ["%.1e" % r["err"] for r in m["reports"]], rel(d32, rph),
+           rel(r32.cpu().numpy(), rfr)))
+    assert rel(d32, rph) < 1e-4
+    assert rel(r32.cpu().numpy(), rfr) < 1e-4
+
+
+def _disk65_oracle(rule):
+    w = fig1_disk_case(65, 1e-3 if rule == "voigt" else 1e3, rule, 0.55)
+    flt = ofilter.filter_field(w)
+    vox = ofilter.all_voxels(w.n)
+    nrm = ofilter.interface_normals(w.n, 2, w.spheres, flt["incl"], vox) if rule == "laminate" else None
+    fld = osolver.StiffnessField(w.n, 2, w.phases, rule, flt["frac"], nrm)
+    refs = [osolver.solve(fld, e, osolver.reference_medium(w.phases), 0.0, 5) for e in E2]
+    return flt, refs
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_65_point_disk_matches_oracle(hm, rule):
+    w = fig1_disk_case(65, 1e-3 if rule == "voigt" else 1e3, rule, 0.55)
+    log("65 x 65 disk, %s" % rule)
+    flt, refs = _job(("disk65", rule), _disk65_oracle, rule).result()
+    for prec, tol in (("fp64", 1e-10), ("mixed", 2e-5)):
+        cnt, frac, incl = hm.hm_filter(w.n, 2, w.spheres, w.radius_vox, w.subsamples, rule, prec, DEV)
+        assert np.array_equal(cnt.cpu().numpy(), flt["count"])
+        if prec == "fp64":
+            assert np.array_equal(frac.cpu().numpy(), flt["frac"])
+            assert np.array_equal(incl.cpu().numpy(), flt["incl"])
+        out = hm.hm_solve(w.n, 2, w.phases, rule, frac, incl, w.spheres, E2, prec=prec, tol=0.0, max_iter=5,
+                          want_eps=True, autotune=False)
+        _compare(out, refs, tol, ("disk65", rule, prec))

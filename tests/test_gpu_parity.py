@@ -289,3 +289,27 @@ def test_every_compiled_schedule_matches_oracle(hm, prec, n):
             e = out["eps"][col].cpu().numpy().astype(np.float64)
             err = rel(e, oracle_fields_to_comps(r["eps"]))
             assert err < tol, (sch, col, err)
+
+
+def test_history_matches_oracle_iterates(hm):
+    """hm_last_history: e_i and <sigma_i> of every iterate against the oracle's."""
+    w = small_sphere_case(n=(15, 9, 21), fraction=0.15, contrast=20.0, rule="laminate",
+                          radius_vox=1.0, subsamples=4, offset=(0.25, 0.5, -0.75))
+    log("iterate history")
+    _, _, _, frac, incl = _gpu_filter(hm, w)
+    ref_f = ofilter.filter_field(w)
+    E = np.array([[0.01, -0.004, 0.002, 0.001, -0.003, 0.005], [0.0, 0.0, 0.0, 0.0, 0.0, 0.01]])
+    K = 5
+    hm.hm_solve(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, E, prec="fp64", tol=0.0, max_iter=K,
+                check_every=2, use_graph=True)
+    err, sig = hm.last_history(2, K + 3)
+    assert np.all(np.isnan(err[:, K + 1:])) and np.all(np.isnan(sig[:, K + 1:]))
+    for k in range(K + 1):
+        refs = oracle_solve(w, ref_f["frac"], ref_f["incl"], E, 0.0, k)
+        for l, r in enumerate(refs):
+            s_ref = np.array([r["sig_mean"][i, j] for (i, j) in [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]])
+            assert rel(sig[l, k], s_ref) < 1e-10
+            assert abs(err[l, k] - r["err"]) <= 1e-10 * r["err"] + 1e-13
+    from paper_1412_3228_amd import HmError
+    with pytest.raises(HmError):
+        hm.last_history(3, 4)

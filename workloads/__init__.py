@@ -24,6 +24,7 @@ from .microstructures import (  # noqa: F401
     FIG1_DISK_RADIUS,
     workload_aniso,
     workload_nphase,
+    thin_grid_case,
     cubic_mandel,
     iso_mandel,
     rotation_from_seed,

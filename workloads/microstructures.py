@@ -97,7 +97,7 @@ def rsa_spheres(rng: np.random.Generator, n: Sequence[int], radii: Sequence[floa
     for idx in order:
         r = float(radii[idx])
         for _ in range(max_tries):
-            c = _snap(rng.random(3) * n_arr)
+            c = np.mod(_snap(rng.random(3) * n_arr), n_arr)
             ok = True
             for c2, r2 in zip(placed, prad):
                 d = _min_image(c - c2, n_arr)
@@ -321,9 +321,11 @@ def random_fraction_case(seed: int, n=(9, 7, 5)) -> np.ndarray:
     return f
 
 
-# Resolutions of the resolution study: the odd sizes with prime factors 3,
-# 5 and 7 between 7 and 125 (the paper sweeps every size from 6 to 128).
-FIG1_RESOLUTIONS = (7, 9, 15, 21, 25, 27, 35, 45, 49, 63, 75, 81, 105, 125)
+# Resolutions of the resolution study: the odd sizes between 7 and 125 whose
+# prime factors are 3, 5, 7, 11 and 13 (the paper sweeps every size from 6
+# to 128).
+FIG1_RESOLUTIONS = (7, 9, 11, 13, 15, 21, 25, 27, 33, 35, 39, 45, 49, 55, 63, 65, 75, 77, 81, 91, 99, 105, 117,
+                    121, 125)
 FIG1_DISK_RADIUS = math.pi / 15.0  # cell lengths (Section 2 numerical setup)
 
 
@@ -436,4 +438,35 @@ def workload_nphase(seed: int = 6, n: int = 125, count: int = 20, rule: str = "v
         loads=_unit_mandel_loads(3),
         tol=1e-4,
         meta={"labels": labels, "phases": phases, "seed": seed},
+    )
+
+
+def thin_grid_case(length: int, axis: int, seed: int = 12, contrast: float = 10.0, rule: str = "laminate",
+                   radius_vox: float = 1.0, subsamples: int = 4, thin=(9, 15), fraction: float = 0.15) -> Workload:
+    """A slab cell that is `length` voxels long along `axis` and thin (9 and
+    15 voxels) along the other two, holding a seeded row of small
+    non-overlapping spheres (radii in [2.5, 4] voxels, fraction about 0.15):
+    every line length of the solver's transforms can then be put on any axis
+    at a size the oracle runs in seconds."""
+    n = [0, 0, 0]
+    others = [a for a in range(3) if a != axis]
+    n[axis] = int(length)
+    n[others[0]], n[others[1]] = int(thin[0]), int(thin[1])
+    rng = np.random.Generator(np.random.PCG64(seed + 1000 * axis + length))
+    vol = float(n[0] * n[1] * n[2])
+    radii = []
+    while sum(4.0 / 3.0 * math.pi * r ** 3 for r in radii) < fraction * vol:
+        radii.append(float(rng.uniform(2.5, 4.0)))
+    sph = rsa_spheres(rng, n, radii, gap=1.0)
+    return Workload(
+        name="thin-%dx%dx%d" % tuple(n),
+        dim=3,
+        n=tuple(n),
+        spheres=sph,
+        phases=(lame(1.0, 0.3), lame(contrast, 0.3)),
+        radius_vox=radius_vox,
+        subsamples=subsamples,
+        rule=rule,
+        loads=_unit_mandel_loads(3),
+        tol=1e-4,
     )
