@@ -508,15 +508,23 @@ int tune_plan(Plan* p, hipStream_t s) {
   if (err == hipSuccess) err = hipMemsetAsync(p->hist, 0, (size_t)p->n_load * 3 * plane * cplx, s);
   hipLaunchKernelGGL((k_reset_state<64>), dim3((p->n_load + 63) / 64), dim3(64), 0, s, p->state, p->n_load);
   if (err == hipSuccess) err = hipGetLastError();
+  // two warm-up launches, then the fastest of three rounds of three launches
+  // (single launches of a few hundred microseconds vary by several percent
+  // from one to the next, which made a one-round choice change run to run)
   auto time_it = [&](solve_launch_fn f, const SolveArgs& a, float* best) -> hipError_t {
-    hipError_t e = f(a, s);  // warm-up
-    if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = f(a, s);
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    *best = ms;
+    hipError_t e = f(a, s);
+    if (e == hipSuccess) e = f(a, s);
+    float bestms = 1e30f;
+    for (int round = 0; round < 3 && e == hipSuccess; ++round) {
+      e = hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = f(a, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      bestms = std::min(bestms, ms);
+    }
+    *best = bestms;
     return e;
   };
   const XKern* bx = &p->kx->x[0];
