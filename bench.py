@@ -14,10 +14,14 @@ the FP64 path's figure and the ratio are reported beside it, with each
 path's effective-tensor error against a tightly converged FP64 solve.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-       python bench.py --kernel-pass   (a few profiled iterations, for rocprofv3)
-       python bench.py --summarize TRACE_DIR FETCH_DIR WRITE_DIR --out FILE
+       python bench.py --kernel-pass [c2|c3]
+           (a few profiled iterations of the 125^3 cell and its variants, or of
+           the 243^3 cell, for rocprofv3)
+       python bench.py --summarize TRACE_DIR FETCH_DIR WRITE_DIR --out FILE [--pass c2|c3]
            (turns the rocprofv3 CSVs of three --kernel-pass runs into the
            text summary kept under profiles/)
+       python bench.py --summarize-sq TRACE_DIR SQA_DIR SQB_DIR --out FILE [--pass c2|c3]
+           (instruction, occupancy and VALU-busy counters of the sweeps)
 """
 from __future__ import annotations
 
@@ -68,14 +72,23 @@ def _short(name):
     return name.split("(")[0][:60]
 
 
-def summarize(trace_dir, fetch_dir, write_dir, out):
+PASS_TITLES = {
+    "c2": "centred-sphere 125^3 cell (elastic: 6 load cases; conduction: 3 load cases), with the anisotropic, "
+          "three-phase and Fourier-series kernels",
+    "c3": "243^3 cell with 40 spheres (6 load cases), mixed and FP64",
+}
+
+
+def _csv_rows(d, pat):
+    fs = glob.glob(os.path.join(d, "**", pat), recursive=True)
+    return list(csv.DictReader(open(fs[0]))) if fs else []
+
+
+def summarize(trace_dir, fetch_dir, write_dir, out, which="c2"):
     """Writes the per-kernel duration and calibrated HBM traffic summary."""
-    def rows(d, pat):
-        fs = glob.glob(os.path.join(d, "**", pat), recursive=True)
-        return list(csv.DictReader(open(fs[0]))) if fs else []
-    stats = rows(trace_dir, "*kernel_stats.csv")
-    fetch = rows(fetch_dir, "*counter_collection.csv")
-    write = rows(write_dir, "*counter_collection.csv")
+    stats = _csv_rows(trace_dir, "*kernel_stats.csv")
+    fetch = _csv_rows(fetch_dir, "*counter_collection.csv")
+    write = _csv_rows(write_dir, "*counter_collection.csv")
     calib = 1 << 28  # bytes of the calibration copy in --kernel-pass
 
     def per_kernel(rr, counter):
@@ -89,16 +102,15 @@ def summarize(trace_dir, fetch_dir, write_dir, out):
     cal_w = [v for k, vs in wk.items() if "copyBuffer" in k for v in vs if v > 1e5]
     sf = calib / 1024.0 / (sum(cal_f) / len(cal_f))
     sw = calib / 1024.0 / (sum(cal_w) / len(cal_w))
-    lines = ["# rocprofv3 summary: solver sweeps, centred-sphere 125^3 cell (elastic: 6 load cases; "
-             "conduction: 3 load cases)",
+    lines = ["# rocprofv3 summary: solver sweeps, %s" % PASS_TITLES[which],
              "# commands (run from /tmp with TMPDIR=/tmp, repository at $R, output under $OUT):",
              "#   rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/trace -o kp -- "
-             "python3 -u $R/bench.py --kernel-pass",
+             "python3 -u $R/bench.py --kernel-pass %s" % which,
              "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/fetch -o kp -- "
-             "python3 -u $R/bench.py --kernel-pass",
+             "python3 -u $R/bench.py --kernel-pass %s" % which,
              "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/write -o kp -- "
-             "python3 -u $R/bench.py --kernel-pass",
-             "#   python3 bench.py --summarize <trace> <fetch> <write> --out <this file>",
+             "python3 -u $R/bench.py --kernel-pass %s" % which,
+             "#   python3 bench.py --summarize <trace> <fetch> <write> --pass %s --out <this file>" % which,
              "# calibration: a %d-byte device copy reads FETCH_SIZE x %.4f and WRITE_SIZE x %.4f of its bytes;"
              % (calib, 1.0 / sf, 1.0 / sw),
              "# traffic below = counter (KiB) x 1024 x scale (fetch %.4f, write %.4f)" % (sf, sw),
@@ -114,6 +126,70 @@ def summarize(trace_dir, fetch_dir, write_dir, out):
         wm = sum(w) / len(w) * 1024 * sw / 1e6 if w else float("nan")
         lines.append("kernel: %s | %s | %.2f | %.1f | %.1f | %.1f" % (k, r["Calls"], float(r["AverageNs"]) / 1e3,
                                                                   fm, wm, fm + wm))
+    with open(out, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+SQ_PASS_A = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_INSTS_SALU",
+             "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
+SQ_PASS_B = ("SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES",
+             "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_ANY", "SQ_WAIT_ANY", "SQ_INSTS_SMEM")
+
+
+def summarize_sq(trace_dir, sqa_dir, sqb_dir, out, which="c2", n_cu=256):
+    """Per-kernel instruction counts, register use and VALU-busy fraction of
+    the sweeps (two --pmc passes of --kernel-pass and its kernel trace)."""
+    trace = _csv_rows(trace_dir, "*kernel_trace.csv")
+    stats = {_short(r["Name"]): r for r in _csv_rows(trace_dir, "*kernel_stats.csv")}
+    regs = {}
+    for r in trace:
+        k = _short(r["Kernel_Name"])
+        regs[k] = (r.get("Arch_VGPR_Count", "?"), r.get("Accum_VGPR_Count", "?"), r.get("LDS_Block_Size", "?"),
+                   r.get("Scratch_Size", "?"), r.get("Workgroup_Size", r.get("Workgroup_Size_X", "?")))
+
+    def agg(d):
+        a, n = {}, {}
+        for r in _csv_rows(d, "*counter_collection.csv"):
+            k = _short(r["Kernel_Name"])
+            a.setdefault(k, {}).setdefault(r["Counter_Name"], 0.0)
+            a[k][r["Counter_Name"]] += float(r["Counter_Value"])
+            n.setdefault(k, set()).add(r["Dispatch_Id"])
+        return a, n
+    A, na = agg(sqa_dir)
+    B, nb = agg(sqb_dir)
+    lines = ["# rocprofv3 counters of the sweeps: %s" % PASS_TITLES[which],
+             "# commands (run from /tmp with TMPDIR=/tmp, repository at $R, output under $OUT):",
+             "#   rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/trace -o kp -- "
+             "python3 -u $R/bench.py --kernel-pass %s" % which,
+             "#   rocprofv3 --pmc %s --output-format csv -d $OUT/sqa -o kp -- python3 -u $R/bench.py --kernel-pass %s"
+             % (" ".join(SQ_PASS_A), which),
+             "#   rocprofv3 --pmc %s --output-format csv -d $OUT/sqb -o kp -- python3 -u $R/bench.py --kernel-pass %s"
+             % (" ".join(SQ_PASS_B), which),
+             "#   python3 bench.py --summarize-sq <trace> <sqa> <sqb> --pass %s --out <this file>" % which,
+             "# valu_busy = SQ_ACTIVE_INST_VALU / (CUs x GUI-active cycles of one XCD): the share of the time the",
+             "# SIMDs issue vector ALU work (an FP32 or FP64 wave instruction takes 4 cycles on 16 lanes);",
+             "# waves_per_simd = SQ_WAVE_CYCLES x 4 / (4 SIMDs x CUs x GUI cycles); per-wave counts per dispatch",
+             "source_hash: %s" % kernel_source_hash(),
+             "# kernel | avg_us | vgpr | agpr | lds_bytes | scratch | wg | waves | valu/wave | lds/wave | "
+             "vmem_rd/wave | vmem_wr/wave | valu_busy | lds_busy | waves_per_simd | lds_bank_conflict/lds_cycle"]
+    for k in sorted(A, key=lambda k: -float(stats.get(k, {}).get("TotalDurationNs", 0) or 0)):
+        if not any(t in k for t in ("sweep", "finalize")):
+            continue
+        a, b = A[k], B.get(k, {})
+        n = len(na[k])
+        w = a.get("SQ_WAVES", 0.0) or 1.0
+        gui = a.get("GRBM_GUI_ACTIVE", 0.0) / n / 8.0  # summed over the 8 XCDs
+        valu_busy = b.get("SQ_ACTIVE_INST_VALU", float("nan")) / max(1, len(nb.get(k, [1]))) / n_cu / gui if gui else 0
+        lds_busy = b.get("SQ_ACTIVE_INST_LDS", float("nan")) / max(1, len(nb.get(k, [1]))) / n_cu / gui if gui else 0
+        wps = b.get("SQ_WAVE_CYCLES", float("nan")) * 4.0 / max(1, len(nb.get(k, [1]))) / (4 * n_cu * gui) if gui else 0
+        conf = b.get("SQ_LDS_BANK_CONFLICT", 0.0) / max(1.0, b.get("SQ_ACTIVE_INST_LDS", 0.0))
+        rg = regs.get(k, ("?",) * 5)
+        us = float(stats[k]["AverageNs"]) / 1e3 if k in stats else float("nan")
+        lines.append("kernel: %s | %.2f | %s | %s | %s | %s | %s | %.0f | %.0f | %.0f | %.1f | %.1f | %.3f | %.3f | "
+                     "%.2f | %.3f" % (k, us, rg[0], rg[1], rg[2], rg[3], rg[4], w / n, a.get("SQ_INSTS_VALU", 0) / w,
+                                      a.get("SQ_INSTS_LDS", 0) / w, a.get("SQ_INSTS_VMEM_RD", 0) / w,
+                                      a.get("SQ_INSTS_VMEM_WR", 0) / w, valu_busy, lds_busy, wps, conf))
     with open(out, "w") as fo:
         fo.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -622,14 +698,20 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--kernel-pass", action="store_true",
-                    help="run a few profiled iterations of each path (for rocprofv3)")
+    ap.add_argument("--kernel-pass", nargs="?", const="c2", choices=("c2", "c3"),
+                    help="run a few profiled iterations of each path (for rocprofv3): the 125^3 cell and its "
+                         "variants (c2) or the 243^3 cell (c3)")
+    ap.add_argument("--pass", dest="which", default="c2", choices=("c2", "c3"))
+    ap.add_argument("--summarize-sq", nargs=3, metavar=("TRACE", "SQA", "SQB"))
     ap.add_argument("--n", type=int, default=125)
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"))
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "hbm_traffic_sweeps_c2_125.txt"))
     args = ap.parse_args()
     if args.summarize:
-        summarize(*args.summarize, args.out)
+        summarize(*args.summarize, args.out, args.which)
+        return
+    if args.summarize_sq:
+        summarize_sq(*args.summarize_sq, args.out, args.which)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -643,6 +725,23 @@ def main():
     n = works[CONTRASTS[0]].n
     N = works[CONTRASTS[0]].nvox
 
+    if args.kernel_pass == "c3":
+        from workloads import workload_c3
+        w = workload_c3()
+        for prec in ("fp64", "mixed"):
+            cnt, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, prec, dev)
+            hm.hm_effective_tensor(w.n, w.dim, w.phases, w.rule, frac, incl, w.spheres, prec=prec, tol=0.0,
+                                   max_iter=5, check_every=6, profile=True)
+            print(json.dumps({"kernel_pass": "c3 " + prec, "timing": hm.last_timing()}), flush=True)
+            del cnt, frac, incl
+            hm.release_plans()
+        x = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        _sync()
+        print(json.dumps({"calibration_copy_bytes": int(x.numel())}), flush=True)
+        return
     if args.kernel_pass:
         for prec in ("fp64", "mixed"):
             w = works[CONTRASTS[0]]
@@ -754,6 +853,13 @@ def main():
                                "r=1 voxel with 8^3 sub-samples, 6 unit Mandel strains batched, tol 1e-4" % n[0],
                    "grid": list(n), "load_cases": 6, "voxels": N},
         "mixed_over_fp64": mixed["value"] / fp64["value"],
+        # the ratio above compares the two paths at their own stops: FP64 at
+        # e < tol, mixed at its single-precision stall (status 2); both
+        # effective tensors are then within these errors of the tight FP64 one
+        "ceff_rel_err_at_stop": {p: max(paths[p]["ceff_rel_err_vs_fp64_tol1e-9"].values()) for p in paths},
+        "ceff_within_1e-5_both": bool(all(v <= 1e-5 for p in paths
+                                          for v in paths[p]["ceff_rel_err_vs_fp64_tol1e-9"].values())),
+        "stop_status": {p: {c: sorted(set(v)) for c, v in paths[p]["status"].items()} for p in paths},
         "equal_ceff_error": eq,
         "paths": paths,
         "roofline": mixed["roofline"],

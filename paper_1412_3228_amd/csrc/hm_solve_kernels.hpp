@@ -588,19 +588,33 @@ template <typename T> __device__ __forceinline__ T pick(int k, T v0, T v1, T v2)
 }
 
 // a_k += tau_c (d_ki n_j + d_kj n_i) for i != j, a_i += tau_c n_i for i == j.
+// With c known at compile time (the unrolled loops) only the nonzero
+// products are formed; in a rolled loop (c varies) the weights select them.
+template <typename C, typename T> __device__ __forceinline__ void cfma(C& a, C v, T w) {
+  a.x += v.x * w;
+  a.y += v.y * w;
+}
 template <typename T>
-__device__ __forceinline__ void fold_component(int c, cx<T> v, Slot<T>& z) {
+__device__ __forceinline__ void fold_component_rolled(int c, cx<T> v, Slot<T>& z) {
   const int i = comp_i(c), j = comp_j(c);
   const T ni = pick(i, z.n0, z.n1, z.n2), nj = pick(j, z.n0, z.n1, z.n2);
   const T w0 = (i == 0 ? nj : T(0)) + (j == 0 && i != j ? ni : T(0));
   const T w1 = (i == 1 ? nj : T(0)) + (j == 1 && i != j ? ni : T(0));
   const T w2 = (i == 2 ? nj : T(0)) + (j == 2 && i != j ? ni : T(0));
-  z.a0.x += v.x * w0;
-  z.a0.y += v.y * w0;
-  z.a1.x += v.x * w1;
-  z.a1.y += v.y * w1;
-  z.a2.x += v.x * w2;
-  z.a2.y += v.y * w2;
+  cfma(z.a0, v, w0);
+  cfma(z.a1, v, w1);
+  cfma(z.a2, v, w2);
+}
+template <typename T>
+__device__ __forceinline__ void fold_component(int c, cx<T> v, Slot<T>& z) {
+  switch (c) {
+    case 0: cfma(z.a0, v, z.n0); break;
+    case 1: cfma(z.a1, v, z.n1); break;
+    case 2: cfma(z.a2, v, z.n2); break;
+    case 3: cfma(z.a1, v, z.n2); cfma(z.a2, v, z.n1); break;
+    case 4: cfma(z.a0, v, z.n2); cfma(z.a2, v, z.n0); break;
+    default: cfma(z.a0, v, z.n1); cfma(z.a1, v, z.n0); break;
+  }
 }
 
 // The z-sweep parks several frequency slots per thread in registers, so its
@@ -730,7 +744,12 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
     for (int g = 0; g < CG; ++g)
 #pragma unroll
       for (int q = 0; q < Q; ++q)
-        if (tid + q * NT < SL) fold_component<T>(gi * CG + g, buf[lds[q] + g * W], z[q]);
+        if (tid + q * NT < SL) {
+          if constexpr (UN > 1)
+            fold_component<T>(gi * CG + g, buf[lds[q] + g * W], z[q]);
+          else
+            fold_component_rolled<T>(gi * CG + g, buf[lds[q] + g * W], z[q]);
+        }
     __syncthreads();
    }
   }

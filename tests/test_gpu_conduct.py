@@ -166,7 +166,7 @@ def test_bad_input_is_refused(hm):
         hm.hm_conduct_solve(w.n, w.dim, K2, "none", frac, incl, w.spheres, G, max_iter=3)
     assert e.value.code == -5
     f11 = torch.zeros(11 * 9 * 9, dtype=torch.float64, device=DEV)
-    with pytest.raises(hm.HmError) as e:  # 11 is not a product of 3, 5 and 7
+    with pytest.raises(hm.HmError) as e:  # no conduction transform of length 11
         hm.hm_conduct_solve((11, 9, 9), 3, K2, "voigt", f11, None, w.spheres, G, max_iter=3)
     assert e.value.code == -2
 

@@ -71,7 +71,7 @@ def test_smallest_grids_match_oracle(hm, shape, method):
     assert rel(out["eps"][0].cpu().numpy(), oracle_fields_to_comps(r["eps"])) < 1e-10
 
 
-@pytest.mark.parametrize("shape", [(1, 1, 1), (4, 9, 9), (245, 5, 5), (11, 9, 9)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (4, 9, 9), (245, 5, 5), (17, 9, 9), (143, 9, 9)])
 def test_unsupported_sizes_are_refused(hm, shape):
     from paper_1412_3228_amd import HmError
     with pytest.raises(HmError) as ei:

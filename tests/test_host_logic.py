@@ -4,6 +4,7 @@ accounting and profile-name normalisation, and the seeded workloads
 import math
 
 import numpy as np
+import pytest
 
 import bench
 from workloads import cubic_mandel, iso_mandel, lame, rotation_from_seed, workload_aniso, workload_c2, workload_nphase
@@ -60,3 +61,34 @@ def test_workloads_are_seeded_and_valid():
     assert np.allclose(np.linalg.eigvalsh(iso_mandel(lam, mu)), sorted([2 * mu] * 5 + [3 * lam + 2 * mu]))
     c2 = workload_c2(100.0)
     assert math.isclose(4.0 / 3.0 * math.pi * c2.spheres[0, 3] ** 3 / 125 ** 3, 0.25, rel_tol=1e-6)
+
+
+def test_effective_tensor_trajectory_and_iterations_to_error():
+    # two load cases: the first stops after iterate 2, the second runs to 4
+    nan = float("nan")
+    hsig = np.full((6, 5, 6), nan)
+    for J in range(6):
+        last = 2 if J == 0 else 4
+        for i in range(last + 1):
+            hsig[J, i] = (1.0 + 0.1 * (J + 1) / (i + 1)) * np.eye(6)[J]
+    traj = bench.ceff_trajectory(hsig)
+    assert traj.shape == (5, 6, 6)
+    # a stopped load case keeps its last column; shear columns carry sqrt(2)
+    assert np.allclose(traj[4, :, 0], traj[2, :, 0])
+    assert traj[4, 3, 3] == pytest.approx(np.sqrt(2.0) * (1.0 + 0.4 / 5))
+    Cref = traj[-1]
+    e = np.linalg.norm(traj - Cref, axis=(1, 2)) / np.linalg.norm(Cref)
+    assert bench.iterations_to(traj, Cref, 0.0) == 4
+    k = bench.iterations_to(traj, Cref, float(e[2]))
+    assert k == 2 and np.all(e[k:] <= e[2])
+    assert bench.iterations_to(traj, Cref * 2.0, 1e-3) is None
+
+
+def test_floor_fraction_and_design_bytes():
+    assert bench.floor_fraction(8e12 / 52.0, "mixed") == pytest.approx(1.0)
+    assert bench.floor_fraction(1e10, "fp64") == pytest.approx(104.0 * 1e10 / 8e12)
+    n = (125, 125, 125)
+    plane = 125 * 125 * 63
+    # four sweeps over the six-component half spectrum plus the history and the ids
+    want = (4 * 2 * 6 * plane * 8 + 2 * 3 * plane * 8 + 4 * 125 ** 3) / 125 ** 3
+    assert bench.design_bytes_per_voxel_it(n, "mixed") == pytest.approx(want)
