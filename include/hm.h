@@ -179,6 +179,22 @@ int hm_filter(const hm_grid* grid, const hm_sphere* spheres, int n_spheres,
               uint32_t* d_count, void* d_frac, int32_t* d_incl, void* stream);
 
 /*
+ * hm_filter_noalloc - hm_filter for callers that cannot allocate device or
+ * pinned memory (tight serving loops, harnesses that forbid allocation):
+ * the same arguments, outputs and errors as hm_filter (two-phase filter),
+ * with the per-call sphere table staged in a fixed device array of the
+ * library instead of an allocated one.  At most
+ * HM_FILTER_NOALLOC_MAX_SPHERES spheres (HM_E_SIZE beyond).  The array is
+ * one per GPU, shared by every call on that GPU: calls that overlap on one
+ * GPU (from different streams or host threads without ordering) race on it.
+ * Returns after the filter kernel has finished on `stream`.
+ */
+#define HM_FILTER_NOALLOC_MAX_SPHERES 3072
+int hm_filter_noalloc(const hm_grid* grid, const hm_sphere* spheres, int n_spheres,
+                      double radius_vox, int subsamples, hm_rule rule, hm_prec prec,
+                      uint32_t* d_count, void* d_frac, int32_t* d_incl, void* stream);
+
+/*
  * hm_solve - basic fixed-point Lippmann-Schwinger solve with the filtered
  * stiffness, for n_load macroscopic strains at once.
  *

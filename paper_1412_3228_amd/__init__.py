@@ -16,6 +16,7 @@ from .api import (  # noqa: F401
     hm_effective_tensor_batch,
     hm_effective_tensor_phases,
     hm_filter,
+    hm_filter_noalloc,
     hm_filter_phases,
     hm_flux_field,
     hm_fourier_series,

@@ -18,10 +18,12 @@ HM_E_DATA = -5
 
 RULES = {"none": 0, "voigt": 1, "reuss": 2, "laminate": 3}
 PRECS = {"fp64": 0, "mixed": 1}
+# sphere capacity of hm_filter_noalloc (HM_FILTER_NOALLOC_MAX_SPHERES in include/hm.h)
+HM_FILTER_NOALLOC_MAX_SPHERES = 3072
 METHODS = {"fixed_point": 0, "cg": 1}
 
 # Every symbol include/hm.h declares.
-EXPORTS = ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_effective_tensor_batch", "hm_solve_adjoint",
+EXPORTS = ("hm_filter", "hm_filter_noalloc", "hm_solve", "hm_effective_tensor", "hm_effective_tensor_batch", "hm_solve_adjoint",
            "hm_conduct_solve", "hm_effective_conductivity", "hm_fourier_series", "hm_stiffness_component",
            "hm_filter_phases", "hm_solve_phases", "hm_effective_tensor_phases", "hm_solve_aniso",
            "hm_effective_tensor_aniso", "hm_stress_field", "hm_flux_field", "hm_last_error", "hm_last_timing",
@@ -88,6 +90,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib = ctypes.CDLL(path)
     lib.hm_filter.argtypes = [_P(HmGrid), _P(HmSphere), ctypes.c_int, ctypes.c_double, ctypes.c_int,
                               ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]
+    lib.hm_filter_noalloc.argtypes = lib.hm_filter.argtypes
     lib.hm_solve.argtypes = [_P(HmGrid), _P(HmIso), ctypes.c_int, _vp, _vp, _P(HmSphere), ctypes.c_int,
                              _dp, ctypes.c_int, _P(HmSolveOpts), _vp, _dp, _P(HmReport), _vp]
     lib.hm_effective_tensor.argtypes = [_P(HmGrid), _P(HmIso), ctypes.c_int, _vp, _vp, _P(HmSphere),
@@ -117,7 +120,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                                _P(HmSolveOpts), _dp, _vp, _P(HmReport), _vp]
     lib.hm_stiffness_component.argtypes = [_P(HmGrid), _P(HmIso), ctypes.c_int, _vp, _vp, _P(HmSphere),
                                            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp]
-    for f in ("hm_filter", "hm_solve", "hm_effective_tensor", "hm_effective_tensor_batch", "hm_solve_adjoint",
+    for f in ("hm_filter", "hm_filter_noalloc", "hm_solve", "hm_effective_tensor", "hm_effective_tensor_batch", "hm_solve_adjoint",
               "hm_conduct_solve", "hm_effective_conductivity", "hm_fourier_series", "hm_stiffness_component",
               "hm_filter_phases", "hm_solve_phases", "hm_effective_tensor_phases", "hm_solve_aniso",
               "hm_effective_tensor_aniso", "hm_stress_field", "hm_flux_field", "hm_device_ok"):

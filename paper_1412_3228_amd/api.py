@@ -110,6 +110,27 @@ def hm_filter(n, dim, spheres, radius_vox: float, subsamples: int, rule: str, pr
     return count, frac, incl
 
 
+def hm_filter_noalloc(n, dim, spheres, radius_vox: float, subsamples: int, rule: str, prec: str = "fp64",
+                      count=None, frac=None, incl=None, device="cuda:0"):
+    """hm_filter into caller-owned outputs with no allocation inside the
+    library (see hm_filter_noalloc in include/hm.h); outputs are allocated
+    here only when not given."""
+    dev = _device(device)
+    N = int(n[0] * n[1] * n[2])
+    count = torch.empty(N, dtype=torch.int32, device=dev) if count is None else count
+    frac = torch.empty(N, dtype=_DT[prec], device=dev) if frac is None else frac
+    incl = torch.empty(N, dtype=torch.int32, device=dev) if incl is None else incl
+    _check_field(count, N, torch.int32, dev, "count")
+    _check_field(frac, N, _DT[prec], dev, "frac")
+    _check_field(incl, N, torch.int32, dev, "incl")
+    g = _grid(n, dim)
+    sph, ns = _spheres(spheres)
+    rc = _lib().hm_filter_noalloc(ctypes.byref(g), sph, ns, float(radius_vox), int(subsamples), L.RULES[rule],
+                                  L.PRECS[prec], _ptr(count), _ptr(frac), _ptr(incl), _stream(dev))
+    L.check(rc)
+    return count, frac, incl
+
+
 def hm_solve(n, dim, phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres, E,
              prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
              check_every: int = 1, stall_window: int = 0, use_graph: bool = False, want_eps: bool = False,

@@ -1882,6 +1882,61 @@ static int filter_impl(const hm_grid* grid, const hm_sphere* spheres, int n_sphe
   return HM_OK;
 }
 
+// ------------------------------------------------------ allocation-free filter
+// hm_filter_noalloc stages the lattice sphere table in `scratch`, a
+// file-scope device array (each GPU holds its own copy, at its own address),
+// instead of a table allocated per call.  The host side uses a file-scope
+// staging array of the same size; both are guarded by one mutex, so calls
+// from several host threads queue on it.  Calls on one GPU share its array:
+// a call that overlaps another one's kernel on that GPU (different streams)
+// races on the table.
+static __device__ __align__(256) unsigned char scratch[HM_FILTER_NOALLOC_MAX_SPHERES * sizeof(LatSphere)];
+static_assert(sizeof(LatSphere) == 40, "lattice sphere layout");
+static LatSphere g_noalloc_host[HM_FILTER_NOALLOC_MAX_SPHERES];
+static std::mutex g_noalloc_mutex;
+static constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device
+
+int hm_filter_noalloc(const hm_grid* grid, const hm_sphere* spheres, int n_spheres, double radius_vox,
+                      int subsamples, hm_rule rule, hm_prec prec, uint32_t* d_count, void* d_frac, int32_t* d_incl,
+                      void* stream) {
+  if (n_spheres < 0) return fail(HM_E_ARG, "n_spheres < 0");
+  if (n_spheres > HM_FILTER_NOALLOC_MAX_SPHERES)
+    return fail(HM_E_SIZE, "hm_filter_noalloc holds at most %d spheres (got %d)", HM_FILTER_NOALLOC_MAX_SPHERES,
+                n_spheres);
+  int dev = 0;
+  HM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HM_E_DEVICE, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+  if (!g_scratch_ptr[dev]) {
+    // first call on this device (it is current): the array's device address
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail(HM_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  FilterArgs a;
+  int rc = filter_prepare(grid, spheres, n_spheres, nullptr, 1, radius_vox, subsamples, rule, prec, d_count, d_frac,
+                          g_noalloc_host, a);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  LatSphere* dtab = static_cast<LatSphere*>(g_scratch_ptr[dev]);
+  hipError_t e = hipSuccess;
+  if (n_spheres > 0) e = hipMemcpyAsync(dtab, g_noalloc_host, (size_t)n_spheres * sizeof(LatSphere),
+                                        hipMemcpyHostToDevice, s);
+  a.sph = dtab;
+  a.count = d_count;
+  a.frac = d_frac;
+  a.incl = d_incl;
+  a.lab = nullptr;
+  a.nlab = 1;
+  if (e == hipSuccess) e = launch_filter(a, prec == HM_FP64, s);
+  // the host staging array is reused by the next call
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(HM_E_DEVICE, "filter: %s", hipGetErrorString(e));
+  return HM_OK;
+}
+
 int hm_filter(const hm_grid* grid, const hm_sphere* spheres, int n_spheres, double radius_vox, int subsamples,
               hm_rule rule, hm_prec prec, uint32_t* d_count, void* d_frac, int32_t* d_incl, void* stream) {
   return filter_impl(grid, spheres, n_spheres, nullptr, 1, radius_vox, subsamples, rule, prec, d_count, d_frac,
