@@ -128,8 +128,9 @@ typedef struct {
 typedef struct {
   int iterations; /* iterations averaged                                   */
   int n_load;     /* load cases of the solve                               */
-  double ms[5];   /* xsweep, forward ysweep, zsweep, inverse ysweep,
-                     finalize (milliseconds per launch)                     */
+  double ms[5];   /* xsweep, forward ysweep, zsweep, inverse ysweep
+                     (milliseconds per launch); ms[4] is the gap after the
+                     inverse ysweep, which ends the iteration itself        */
   int x_lines;    /* schedule in use: grid lines per xsweep block,         */
   int y_width;    /*   kx columns per ysweep block,                        */
   int z_width;    /*   kx columns per zsweep block                         */
@@ -203,7 +204,10 @@ int hm_filter_noalloc(const hm_grid* grid, const hm_sphere* spheres, int n_spher
  * frequency set J with xi = 2 pi a.  c~ per voxel: the phase tensor where
  * f is exactly 0 or 1, else `rule` applied to f (HM_RULE_LAMINATE uses the
  * normal from the centre of sphere d_incl[v] to the voxel centre; e_1 when
- * d_incl[v] < 0).  c0 is isotropic with Lame parameters c0_alpha times the
+ * d_incl[v] < 0).  The cell has length 1 along every axis (so a voxel is
+ * 1/n[d] long on axis d) while spheres, the filter and the normal are in
+ * voxel units: on a grid with unequal n[d] a sphere is an ellipsoid in the
+ * cell's metric and the laminate normal is taken in voxel units.  c0 is isotropic with Lame parameters c0_alpha times the
  * mean of the phases' smallest and largest values (Figure 3 caption).
  * Iterate i evaluates sigma_i = c~ : eps_i and its stress-equilibrium error
  * e_i = sqrt(sum_xi |xi . sigma^_i(xi)|^2) / |sigma^_i(0)| (Section 2 setup;

@@ -215,6 +215,9 @@ struct Plan {
   void* hist = nullptr;
   double* taupart = nullptr;
   double* errpart = nullptr;
+  int* fin_count = nullptr;  // [2 n_load]: end-of-iteration arrivals per load case (0
+                             // between launches), then the stop-flag snapshots
+  double* fin_red = nullptr; // reduced sums per load case, 8 doubles
   SolverState* state = nullptr;
   SolverState* state_host = nullptr;  // pinned
   double* errhist = nullptr;
@@ -256,6 +259,8 @@ void free_plan(Plan* p) {
   (void)hipFree(p->hist);
   (void)hipFree(p->taupart);
   (void)hipFree(p->errpart);
+  (void)hipFree(p->fin_count);
+  (void)hipFree(p->fin_red);
   (void)hipFree(p->state);
   (void)hipFree(p->errhist);
   (void)hipFree(p->sighist);
@@ -363,6 +368,10 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, int phys, Plan** ou
   if (!rc) rc = device_alloc((void**)&p->taupart, (size_t)n_load * g2 * 6 * sizeof(double), "tau partials");
   if (!rc) rc = device_alloc((void**)&p->errpart, (size_t)n_load * n[1] * ntx4 * sizeof(double), "error partials");
   if (!rc) rc = device_alloc((void**)&p->state, (size_t)n_load * sizeof(SolverState), "state");
+  if (!rc) rc = device_alloc((void**)&p->fin_count, (size_t)n_load * 2 * sizeof(int), "iteration counters");
+  if (!rc) rc = device_alloc((void**)&p->fin_red, (size_t)n_load * 8 * sizeof(double), "reduced sums");
+  if (!rc && hipMemset(p->fin_count, 0, (size_t)n_load * 2 * sizeof(int)) != hipSuccess)
+    rc = fail(HM_E_DEVICE, "clearing the iteration counters");
   if (!rc) rc = upload_twiddles(p, 0, n[0]);
   if (!rc) rc = upload_twiddles(p, 1, n[1]);
   if (!rc) rc = upload_twiddles(p, 2, n[2]);
@@ -380,6 +389,9 @@ int get_plan(bool fp64, const int n[3], int dim, int n_load, int phys, Plan** ou
   a.taupart = p->taupart;
   a.errpart = p->errpart;
   a.state = p->state;
+  a.fin_count = p->fin_count;
+  a.fin_red = p->fin_red;
+  a.done_snap = p->fin_count + n_load;
   a.twx = p->tw[0];
   a.twy = p->tw[1];
   a.twz = p->tw[2];
@@ -440,9 +452,8 @@ hipError_t launch_iteration(Plan* p, const SolveArgs& a, bool first, hipStream_t
   if ((e = (first ? p->X->first : p->X->iter)(a, s)) != hipSuccess) return e;
   if ((e = p->Y->fwd(a, s)) != hipSuccess) return e;
   if ((e = p->Z->run(a, s)) != hipSuccess) return e;
-  if ((e = p->Y->inv(a, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_finalize<kFinalizeThreads>), dim3(a.n_load), dim3(kFinalizeThreads), 0, s, a);
-  return hipGetLastError();
+  // the inverse y-sweep also ends the iteration (stop decision per load case)
+  return p->Y->inv(a, s);
 }
 
 // Copies the stop flags of the plan's load cases to the host (stream synchronised).
@@ -972,10 +983,8 @@ int profiled_loop(Plan* p, const hm_solve_opts* opts, hipStream_t s) {
       if (err == hipSuccess) err = hipEventRecord(e[3], s);
       if (err == hipSuccess) err = p->Y->inv(a, s);
       if (err == hipSuccess) err = hipEventRecord(e[4], s);
-      if (err == hipSuccess) {
-        hipLaunchKernelGGL((k_finalize<kFinalizeThreads>), dim3(a.n_load), dim3(kFinalizeThreads), 0, s, a);
-        err = hipGetLastError();
-      }
+      // the end of the iteration runs inside the inverse y-sweep: the fifth
+      // interval is empty and kept for the layout of hm_timing
       if (err == hipSuccess) err = hipEventRecord(e[5], s);
       if (err != hipSuccess) break;
     }
@@ -1006,7 +1015,7 @@ int profiled_loop(Plan* p, const hm_solve_opts* opts, hipStream_t s) {
   t.z_groups = p->Z->groups;
   const char* names[4] = {p->X->name, p->Y->fwd_name, p->Z->name, p->Y->inv_name};
   for (int q = 0; q < 4; ++q) snprintf(t.kernel[q], sizeof t.kernel[q], "%s", names[q]);
-  snprintf(t.kernel[4], sizeof t.kernel[4], "finalize<%d>", kFinalizeThreads);
+  snprintf(t.kernel[4], sizeof t.kernel[4], "(inside the inverse ysweep)");
   for (int i = 0; i < nit; ++i)
     for (int q = 0; q < 5; ++q) t.ms[q] += dur[(size_t)5 * i + q];
   for (int q = 0; q < 5; ++q) t.ms[q] /= nit > 0 ? nit : 1;

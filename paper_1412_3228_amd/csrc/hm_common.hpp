@@ -143,6 +143,13 @@ struct SolveArgs {
   CgState* cgs;      // [n_load]
   double* cgpart;    // [n_load][cg_blocks]
   int cond;          // 1: conduction (3 gradient components), 0: elasticity
+  // end of iteration inside the inverse y-sweep (fixed point only):
+  // reducer arrivals per load case (0 between launches), the published sums
+  // (six tau sums and the error sum, 8 doubles per load case) and the stop
+  // flags as the forward y-sweep found them
+  int* fin_count;
+  double* fin_red;
+  int* done_snap;
 };
 
 }  // namespace hm

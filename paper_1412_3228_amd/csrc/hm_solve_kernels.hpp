@@ -521,9 +521,16 @@ __global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
   }
 }
 
+template <int NT>
+__device__ __forceinline__ void fin_reduce_publish(const SolveArgs& a, int load, int k);
+
 // ---------------------------------------------------------------- ysweep --
 // A block owns W adjacent kx columns of one (load, component, z) plane;
-// NC components per load (6 strain, or 3 gradient components).
+// NC components per load (6 strain, or 3 gradient components).  The inverse
+// sweep of the fixed point also ends the iteration: its first 7 n_load
+// blocks in launch order each reduce one of the seven sums of a load case
+// before their own transform, and the last of a load case's seven takes
+// its stop decision.
 template <typename T, int NY, int W, int NT, int SIGN, int NC = 6>
 __global__ __launch_bounds__(NT) void k_ysweep(SolveArgs a) {
   constexpr int SL = NY * W;
@@ -533,7 +540,24 @@ __global__ __launch_bounds__(NT) void k_ysweep(SolveArgs a) {
   const int tid = threadIdx.x;
   const int z = blockIdx.y;
   const int load = blockIdx.z / NC, comp = blockIdx.z - NC * (blockIdx.z / NC);
-  if (a.state[load].done) return;
+  int done;
+  if constexpr (SIGN < 0) {
+    done = a.state[load].done;
+    // the inverse sweep reads the stop flag as it is now, while its own
+    // blocks take this iteration's stop decision
+    if (blockIdx.x == 0 && blockIdx.y == 0 && comp == 0 && tid == 0) a.done_snap[load] = done;
+  } else if (a.cg) {
+    done = a.state[load].done;
+  } else {
+    done = a.done_snap[load];
+    // a grid of fewer than 7 n_load blocks (small 2D cells) takes turns
+    const int nall = gridDim.x * gridDim.y * gridDim.z;
+    for (int j = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z); j < 7 * a.n_load; j += nall) {
+      fin_reduce_publish<NT>(a, j / 7, j - 7 * (j / 7));
+      __syncthreads();  // the reduction's shared words are reused by the next turn
+    }
+  }
+  if (done) return;
   const int H = a.H, Hp = a.Hp;
   const int kx0 = blockIdx.x * W;
   cx<T>* base = static_cast<cx<T>*>(a.spec) + ((size_t)(load * NC + comp) * a.nz + z) * (size_t)NY * Hp + kx0;
@@ -1152,93 +1176,88 @@ __device__ __forceinline__ void neumaier_merge(double& s, double& c, double s2, 
   c += c2;
 }
 
+// Deterministic compensated block reduction of one of a load case's seven
+// sums (k < 6: tau component k over the x-sweep partials; k = 6: the error
+// sum over the z-sweep partials), valid in thread 0: a thread-strided
+// compensated sum in index order with four loads in flight, then a fixed
+// shuffle tree per wavefront and the wavefronts in order (the result does
+// not depend on timing).  Every thread of the block calls it.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_finalize(SolveArgs a) {
+__device__ __forceinline__ double finalize_reduce(const SolveArgs& a, int load, int k) {
   constexpr int NW = NT / 64;
-  constexpr int K = 7;  // six tau component sums and the error sum
-  __shared__ double ws[NW][K], wc[NW][K];
-  const int load = blockIdx.x;
-  SolverState* st = a.state + load;
+  __shared__ double ws[NW], wc[NW];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  // The block is alone on its compute unit, so its time is a chain of
-  // memory latencies: the first partials, the stop flag and the parameter
-  // chain are all requested before any of them is used.
-  const double* tp = a.taupart + (size_t)load * a.g2 * 6;
   const size_t ne = (size_t)a.ny * a.ntx4;
-  const double* ep = a.errpart + (size_t)load * ne;
-  double t0[6], e0 = 0.0;
+  const double* src = k < 6 ? a.taupart + (size_t)load * a.g2 * 6 + k : a.errpart + (size_t)load * ne;
+  const size_t n = k < 6 ? (size_t)a.g2 : ne, st = k < 6 ? 6 : 1;
+  double s = 0.0, c = 0.0;
+  size_t i = tid;
+#pragma unroll 1
+  for (; i + 3 * NT < n; i += 4 * NT) {
+    const double x0 = src[i * st], x1 = src[(i + NT) * st], x2 = src[(i + 2 * NT) * st],
+                 x3 = src[(i + 3 * NT) * st];
+    neumaier_add(s, c, x0);
+    neumaier_add(s, c, x1);
+    neumaier_add(s, c, x2);
+    neumaier_add(s, c, x3);
+  }
+#pragma unroll 1
+  for (; i < n; i += NT) neumaier_add(s, c, src[i * st]);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) t0[k] = tid < a.g2 ? tp[(size_t)tid * 6 + k] : 0.0;
-  if ((size_t)tid < ne) e0 = ep[tid];
-  const int done = st->done;
+  for (int off = 32; off > 0; off >>= 1) {
+    const double so = __shfl_down(s, off, 64), co = __shfl_down(c, off, 64);
+    if (lane < off) neumaier_merge(s, c, so, co);
+  }
+  if (lane == 0) {
+    ws[wv] = s;
+    wc[wv] = c;
+  }
+  __syncthreads();
+  if (tid != 0) return 0.0;
+  double sk = ws[0], ck = wc[0];
+#pragma unroll 1
+  for (int w = 1; w < NW; ++w) neumaier_merge(sk, ck, ws[w], wc[w]);
+  return sk + ck;
+}
+
+// The end of an iteration for one load case, from its published sums, by
+// one whole wavefront (lane c < 6 owns component c, so that few registers
+// are live: this runs inside the inverse y-sweep): the mean stress (or
+// flux), the error, the history and the stop decision.
+__device__ __forceinline__ void finalize_decide(const SolveArgs& a, int load, int lane) {
+  SolverState* st = a.state + load;
   const SolveParams& S0 = *a.prm;
   const LoadParams& LP = S0.loads[load];
   const ProblemParams& P = S0.probs[LP.prob];
-  if (done) return;
-  // one pass over the partials: thread-strided compensated sums, then a
-  // fixed shuffle tree per wavefront and the wavefronts in order (the
-  // result does not depend on timing)
-  double s[K], c[K];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    s[k] = t0[k];
-    c[k] = 0.0;
-  }
-  s[6] = e0;
-  c[6] = 0.0;
-  for (int i = tid + NT; i < a.g2; i += NT)
-#pragma unroll
-    for (int k = 0; k < 6; ++k) neumaier_add(s[k], c[k], tp[(size_t)i * 6 + k]);
-  for (size_t i = (size_t)tid + NT; i < ne; i += NT) neumaier_add(s[6], c[6], ep[i]);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const double so = __shfl_down(s[k], off, 64), co = __shfl_down(c[k], off, 64);
-      if (lane < off) neumaier_merge(s[k], c[k], so, co);
-    }
-  }
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      ws[wv][k] = s[k];
-      wc[wv][k] = c[k];
-    }
-  __syncthreads();
-  if (tid != 0) return;
-  double tsum[6], S;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double sk = ws[0][k], ck = wc[0][k];
-    for (int w = 1; w < NW; ++w) neumaier_merge(sk, ck, ws[w][k], wc[w][k]);
-    if (k < 6)
-      tsum[k] = sk + ck;
-    else
-      S = sk + ck;
-  }
+  const double* r = a.fin_red + (size_t)load * 8;
+  const int c = lane < 6 ? lane : 0;
+  const double t = __hip_atomic_load(r + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double S = __hip_atomic_load(r + 6, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const double N = (double)a.nx * (double)a.ny * (double)a.nz;
   const double* E = LP.E;
-  const double trE = E[0] + E[1] + E[2];
-  double sig[6];
+  double sc;
   if (a.cond) {
     // mean flux <q> = k0 G + <tau>; shear slots stay zero
-#pragma unroll
-    for (int c = 0; c < 6; ++c) sig[c] = c < 3 ? tsum[c] / N + P.rl * E[c] : 0.0;
+    sc = c < 3 ? t / N + P.rl * E[c] : 0.0;
   } else {
-#pragma unroll
-    for (int c = 0; c < 6; ++c) sig[c] = tsum[c] / N + (c < 3 ? P.rl * trE : 0.0) + 2.0 * P.rm * E[c];
+    sc = t / N + (c < 3 ? P.rl * (E[0] + E[1] + E[2]) : 0.0) + 2.0 * P.rm * E[c];
   }
+  double sig[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sig[k] = __shfl(sc, k, 64);
+  if (lane < 6) {
+    const int i = st->iter;
+    if (i < a.hist_cap) a.sighist[((size_t)load * a.hist_cap + i) * 6 + lane] = sc;
+    st->sig[lane] = sc;
+  }
+  if (lane != 0) return;
   const double fro = sqrt(sig[0] * sig[0] + sig[1] * sig[1] + sig[2] * sig[2] +
                           2.0 * (sig[3] * sig[3] + sig[4] * sig[4] + sig[5] * sig[5]));
   const double den = N * fro;
   const double res = sqrt(S);
   const double e = den > 0.0 ? res / den : (S == 0.0 ? 0.0 : INFINITY);
   const int i = st->iter;
-  if (i < a.hist_cap) {
-    a.errhist[(size_t)load * a.hist_cap + i] = e;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) a.sighist[((size_t)load * a.hist_cap + i) * 6 + c] = sig[c];
-  }
+  if (i < a.hist_cap) a.errhist[(size_t)load * a.hist_cap + i] = e;
   if (i == 0) {
     st->err0 = e;
     st->res0 = res;
@@ -1263,13 +1282,37 @@ __global__ __launch_bounds__(NT) void k_finalize(SolveArgs a) {
   }
   st->err = e;
   st->iters = i;
-#pragma unroll
-  for (int c = 0; c < 6; ++c) st->sig[c] = sig[c];
   if (status != ST_RUNNING) {
     st->status = status;
     st->done = 1;
   }
   st->iter = i + 1;
+}
+
+// The end of an iteration runs inside the inverse y-sweep, which starts
+// after the x- and z-sweeps have written every partial it reduces.  Seven
+// blocks reduce one sum each of a live load case L, publish it and arrive
+// on fin_count[L]; the seventh arrival takes the stop decision and puts the
+// counter back to 0 for the next launch.  The sweep's own blocks read L's
+// stop flag from the snapshot the forward y-sweep took, so the decision
+// may land while they run.
+template <int NT>
+__device__ __forceinline__ void fin_reduce_publish(const SolveArgs& a, int load, int k) {
+  if (a.done_snap[load]) return;
+  const double v = finalize_reduce<NT>(a, load, k);
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  int old = 0;
+  if (lane == 0) {
+    __hip_atomic_store(a.fin_red + (size_t)load * 8 + k, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    old = atomicAdd(a.fin_count + load, 1);
+  }
+  old = __shfl(old, 0, 64);
+  if (old != 6) return;
+  __threadfence();
+  finalize_decide(a, load, lane);
+  if (lane == 0) __hip_atomic_store(a.fin_count + load, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int NT>
