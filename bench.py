@@ -22,6 +22,8 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
            text summary kept under profiles/)
        python bench.py --summarize-sq TRACE_DIR SQA_DIR SQB_DIR --out FILE [--pass c2|c3]
            (instruction, occupancy and VALU-busy counters of the sweeps)
+       python bench.py --summarize-bench TRACE_DIR BENCH_LOG --out FILE
+           (kernel-trace statistics of a whole default run beside its line)
 """
 from __future__ import annotations
 
@@ -193,6 +195,41 @@ def summarize_sq(trace_dir, sqa_dir, sqb_dir, out, which="c2", n_cu=256):
     with open(out, "w") as fo:
         fo.write("\n".join(lines) + "\n")
     print("\n".join(lines))
+
+
+def summarize_bench(trace_dir, bench_log, out):
+    """Kernel-trace statistics of a whole default bench.py run beside the
+    line it printed: the dominant kernel's rocprofv3 average duration and the
+    HIP-event duration bench.py measured for it."""
+    stats = _csv_rows(trace_dir, "*kernel_stats.csv")
+    line = json.loads([ln for ln in open(bench_log).read().splitlines() if ln.startswith("{")][-1])
+    avg = {_short(r["Name"]): (int(r["Calls"]), float(r["AverageNs"]) / 1e3) for r in stats}
+    lines = ["# rocprofv3 summary of the default benchmark run (one MI355X)",
+             "# command (run from /tmp with TMPDIR=/tmp, repository at $R, output under $OUT):",
+             "#   rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/bench_trace -o kp -- "
+             "python3 -u $R/bench.py > $OUT/bench_trace.log",
+             "#   python3 bench.py --summarize-bench $OUT/bench_trace $OUT/bench_trace.log --out <this file>",
+             "source_hash: %s" % kernel_source_hash(),
+             "value: %.6g %s (mixed), fp64 %.6g" % (line["value"], line["unit"], line["paths"]["fp64"]["value"]),
+             "# dominant kernel per path: HIP events inside bench.py vs the rocprofv3 average over every call"]
+    for tag, rf in (("mixed", line["roofline"]), ("fp64", line["paths"]["fp64"]["roofline"])):
+        calls, us = avg.get(rf["instance"], (0, float("nan")))
+        lines.append("roofline %s: %s | events %.2f us | rocprofv3 %.2f us over %d calls | ratio %.3f | "
+                     "%.0f GB/s = %.3f of %.0f" % (tag, rf["instance"], rf["ms_per_launch"] * 1e3, us, calls,
+                                                  us / (rf["ms_per_launch"] * 1e3), rf["achieved"], rf["frac"],
+                                                  rf["peak"]))
+    lines.append("# kernel | calls | avg_us | total_ms (sweeps and the filter, by total time)")
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        k = _short(r["Name"])
+        if not any(t in k for t in ("sweep", "filter", "cg_", "material")):
+            continue
+        lines.append("kernel: %s | %s | %.2f | %.1f" % (k, r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                        float(r["TotalDurationNs"]) / 1e6))
+    lines.append("# the JSON line")
+    lines.append(json.dumps(line))
+    with open(out, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines[:12]))
 
 
 def measured_traffic(kernel_key):
@@ -705,6 +742,7 @@ def main():
     ap.add_argument("--summarize-sq", nargs=3, metavar=("TRACE", "SQA", "SQB"))
     ap.add_argument("--n", type=int, default=125)
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"))
+    ap.add_argument("--summarize-bench", nargs=2, metavar=("TRACE", "BENCH_LOG"))
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "hbm_traffic_sweeps_c2_125.txt"))
     args = ap.parse_args()
     if args.summarize:
@@ -712,6 +750,9 @@ def main():
         return
     if args.summarize_sq:
         summarize_sq(*args.summarize_sq, args.out, args.which)
+        return
+    if args.summarize_bench:
+        summarize_bench(*args.summarize_bench, args.out)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path (use --gpus 1)", file=sys.stderr)
