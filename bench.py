@@ -202,8 +202,19 @@ def summarize_bench(trace_dir, bench_log, out):
     line it printed: the dominant kernel's rocprofv3 average duration and the
     HIP-event duration bench.py measured for it."""
     stats = _csv_rows(trace_dir, "*kernel_stats.csv")
+    trace = _csv_rows(trace_dir, "*kernel_trace.csv")
     line = json.loads([ln for ln in open(bench_log).read().splitlines() if ln.startswith("{")][-1])
     avg = {_short(r["Name"]): (int(r["Calls"]), float(r["AverageNs"]) / 1e3) for r in stats}
+    loads = line["config"]["load_cases"]
+
+    def timed_config(inst):
+        # dispatches of the instance in the launch configuration bench.py
+        # times: one cell's load cases on the grid's z extent (the batch of
+        # 64 cells runs the same instance on groups of cells, several times
+        # larger, and the tuner times it too)
+        sel = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace
+               if _short(r["Kernel_Name"]) == inst and int(r.get("Grid_Size_Z", loads)) == loads]
+        return (len(sel), sum(sel) / len(sel)) if sel else (0, float("nan"))
     lines = ["# rocprofv3 summary of the default benchmark run (one MI355X)",
              "# command (run from /tmp with TMPDIR=/tmp, repository at $R, output under $OUT):",
              "#   rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/bench_trace -o kp -- "
@@ -211,13 +222,18 @@ def summarize_bench(trace_dir, bench_log, out):
              "#   python3 bench.py --summarize-bench $OUT/bench_trace $OUT/bench_trace.log --out <this file>",
              "source_hash: %s" % kernel_source_hash(),
              "value: %.6g %s (mixed), fp64 %.6g" % (line["value"], line["unit"], line["paths"]["fp64"]["value"]),
-             "# dominant kernel per path: HIP events inside bench.py vs the rocprofv3 average over every call"]
+             "# dominant kernel per path: HIP events inside bench.py vs the rocprofv3 average in the same launch "
+             "configuration"]
+    lines.append("# (rocprofv3 over the dispatches with grid z extent = %d load cases, i.e. one cell's solves; "
+                 "the all-call average also holds the 64-cell batch's grouped launches)" % loads)
     for tag, rf in (("mixed", line["roofline"]), ("fp64", line["paths"]["fp64"]["roofline"])):
         calls, us = avg.get(rf["instance"], (0, float("nan")))
-        lines.append("roofline %s: %s | events %.2f us | rocprofv3 %.2f us over %d calls | ratio %.3f | "
-                     "%.0f GB/s = %.3f of %.0f" % (tag, rf["instance"], rf["ms_per_launch"] * 1e3, us, calls,
-                                                  us / (rf["ms_per_launch"] * 1e3), rf["achieved"], rf["frac"],
-                                                  rf["peak"]))
+        n_t, us_t = timed_config(rf["instance"])
+        ev = rf["ms_per_launch"] * 1e3
+        lines.append("roofline %s: %s | events %.2f us | rocprofv3 %.2f us over %d dispatches | ratio %.3f | "
+                     "all %d calls %.2f us | %.0f GB/s = %.3f of %.0f"
+                     % (tag, rf["instance"], ev, us_t, n_t, us_t / ev, calls, us, rf["achieved"], rf["frac"],
+                        rf["peak"]))
     lines.append("# kernel | calls | avg_us | total_ms (sweeps and the filter, by total time)")
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
         k = _short(r["Name"])
