@@ -115,10 +115,14 @@ def normal_sphere(n, dim: int, spheres: np.ndarray, subsamples: int,
                   voxels: np.ndarray) -> np.ndarray:
     """Index of the inclusion that defines the interface normal at each voxel.
 
-    Convention (parity unpinned): the sphere whose surface is nearest to the
-    voxel centre, k = argmin_k | |d_k| - t_k | with d_k the minimum-image
-    lattice vector from the quantised centre and t_k the radius in lattice
-    units; ties go to the lowest index.
+    The sphere whose surface is nearest to the voxel centre,
+    k = argmin_k | |d_k| - t_k | with d_k the minimum-image lattice vector
+    from the quantised centre and t_k the radius in lattice units; ties go
+    to the lowest index.  Where the voxel straddles one surface only this is
+    the inclusion the paper's normal belongs to (pinned against per-sphere
+    counts); where several surfaces are within the filter's reach the
+    nearest one is a convention of this implementation (a reading, not
+    pinned).
     """
     cu, t, _ = quantise_spheres(spheres, subsamples)
     period = 2 * subsamples * np.asarray(n, dtype=np.int64)
