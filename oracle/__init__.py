@@ -14,9 +14,14 @@ filter    sub-voxel phase fractions and interface normals (Section 2)
 rules     Voigt, Reuss and 2-layer homogenisation rules (Section 2, eqs. 3-5)
 solver    Lippmann-Schwinger fixed point, Green operator, equilibrium error,
           effective tensor (Section 2, eqs. 1-2)
-gradient  derivative of the effective tensor by the Hill (energy) identity
+gradient  derivative of the effective tensor by the Hill (energy) identity,
+          cross-checked by the adjoint route through the fixed point
+thermal, nphase, aniso, extrapolate
+          conduction form, N-phase rules, anisotropic phases, Figure 4 series
 
-Parity status: every function is pinned by the tests under ``tests/`` except
-the choice of inclusion for the interface normal when several inclusions
-are near a voxel ("parity unpinned": a convention, see filter.normal_sphere).
+Parity status: every function is pinned by the tests under ``tests/``.  One
+convention has no pin because the paper does not fix it: the choice of
+inclusion for the interface normal when the surfaces of several inclusions
+are within the filter's reach of one voxel (see filter.normal_sphere); with
+one surface in reach the choice and the normal are pinned.
 """
