@@ -372,16 +372,16 @@ def equal_error(last, ref, eps_list=(1e-5, 1e-6)):
     return out
 
 
-def roofline(timings, n, prec, reports, n_frac=0, nc=6, nh=3, n_load=6, row_reals=8):
+def roofline(timings, n, prec, n_frac=0, nc=6, nh=3, n_load=6, row_reals=8):
     """Dominant kernel of the profiled solves, its algorithmic bandwidth vs peak."""
     tot = {}
     for t in timings:
         for k, ms in t["ms"].items():
             tot[k] = tot.get(k, 0.0) + ms * t["iterations"]
     dom = max(tot, key=tot.get)
-    # average number of active load cases per launch over the profiled iterations
+    # average number of active load cases per launch over the sampled iterations
     its = sum(t["iterations"] for t in timings)
-    active = sum(sum(r["iters"] + 1 for r in rep) for rep in reports) / max(1, its)
+    active = sum(t["active_loads"] * t["iterations"] for t in timings) / max(1, its)
     ms = tot[dom] / its
     bytes_launch = kernel_bytes(n, prec, dom, n_frac, nc, nh, row_reals) * active
     achieved = bytes_launch / (ms * 1e-3) / 1e9
@@ -440,7 +440,7 @@ def c3_section(hm, dev):
                      "iters": [r["iters"] for r in o["reports"]], "status": [r["status"] for r in o["reports"]],
                      "final_equilibrium_error": [r["err"] for r in o["reports"]],
                      "floor_frac": floor_fraction(value, prec),
-                     "roofline": roofline([t], w.n, prec, [o["reports"]], n_frac),
+                     "roofline": roofline([t], w.n, prec, n_frac),
                      "ms_per_kernel": t["ms"], "kernels": t["kernels"]}
         del frac, incl
         print("c3 %s done" % prec, file=sys.stderr, flush=True)
@@ -526,7 +526,7 @@ def conduction(hm, works, dev, n_frac):
     beside the metric."""
     out = {}
     for prec in ("fp64", "mixed"):
-        vit, secs, timings, reps, K = 0, 0.0, [], [], {}
+        vit, secs, timings, K = 0, 0.0, [], {}
         for c, w in works.items():
             k = (1.0, c)
             _, frac, incl = hm.hm_filter(w.n, w.dim, w.spheres, w.radius_vox, w.subsamples, w.rule, prec, dev)
@@ -539,14 +539,13 @@ def conduction(hm, works, dev, n_frac):
             secs += time.perf_counter() - t0
             vit += sum(r["iters"] + 1 for r in o["reports"]) * w.nvox
             timings.append(hm.last_timing())
-            reps.append(o["reports"])
             K[str(c)] = {"K_diag": [float(v) for v in np.diag(o["K"])],
                          "iters": [r["iters"] for r in o["reports"]],
                          "status": [r["status"] for r in o["reports"]]}
             del frac, incl
         n = next(iter(works.values())).n
         out[prec] = {"value": vit / secs, "unit": "voxel-iterations/s", "seconds": secs, "solves": K,
-                     "roofline": roofline(timings, n, prec, reps, n_frac, nc=3, nh=1, n_load=3)}
+                     "roofline": roofline(timings, n, prec, n_frac, nc=3, nh=1, n_load=3)}
     return out
 
 
@@ -583,7 +582,7 @@ def phase_cells(hm, dev):
             secs = time.perf_counter() - t0
             t = hm.last_timing()
             vit = sum(r["iters"] + 1 for r in o["reports"]) * w.nvox
-            rf = roofline([t], w.n, prec, [o["reports"]], n_frac, row_reals=(24 if name == "aniso" else 8))
+            rf = roofline([t], w.n, prec, n_frac, row_reals=(24 if name == "aniso" else 8))
             row[prec] = {"value": vit / secs, "unit": "voxel-iterations/s", "seconds": secs,
                          "iters": [r["iters"] for r in o["reports"]], "status": [r["status"] for r in o["reports"]],
                          "C_diag": [float(v) for v in np.diag(o["C"])], "xsweep_ms": t["ms"]["xsweep"],
@@ -884,11 +883,10 @@ def main():
         status = {str(c): [r["status"] for r in last[(prec, c)]["reports"]] for c in CONTRASTS}
         finals = {str(c): [r["err"] for r in last[(prec, c)]["reports"]] for c in CONTRASTS}
         timings = [st[(prec, c)]["timing"] for st in steps for c in CONTRASTS]
-        reps = [st[(prec, c)]["reports"] for st in steps for c in CONTRASTS]
         paths[prec] = {"value": vit / secs, "seconds": secs, "voxel_iterations": vit,
                        "ceff_rel_err_vs_fp64_tol1e-9": errs, "iters": iters, "status": status,
                        "final_equilibrium_error": finals,
-                       "roofline": roofline(timings, n, prec, reps, n_frac)}
+                       "roofline": roofline(timings, n, prec, n_frac)}
     for prec in ("fp64", "mixed"):
         paths[prec]["floor_frac"] = floor_fraction(paths[prec]["value"], prec)
     mixed, fp64 = paths["mixed"], paths["fp64"]

@@ -124,13 +124,15 @@ typedef struct {
 } hm_solve_opts;
 
 /* Average device duration per launch of each kernel of the iteration, over
- * the iterations a profiled solve evaluated (the longest load case). */
+ * the sampled iterations (0, 4, 8, ...: events around the kernels of those
+ * only, an event record costing a few microseconds of device time) that a
+ * profiled solve evaluated (the longest load case). */
 typedef struct {
-  int iterations; /* iterations averaged                                   */
+  int iterations; /* sampled iterations averaged                           */
   int n_load;     /* load cases of the solve                               */
   double ms[5];   /* xsweep, forward ysweep, zsweep, inverse ysweep
-                     (milliseconds per launch); ms[4] is the gap after the
-                     inverse ysweep, which ends the iteration itself        */
+                     (milliseconds per launch); ms[4] is 0: the inverse
+                     ysweep ends the iteration itself                      */
   int x_lines;    /* schedule in use: grid lines per xsweep block,         */
   int y_width;    /*   kx columns per ysweep block,                        */
   int z_width;    /*   kx columns per zsweep block                         */
@@ -139,6 +141,8 @@ typedef struct {
   char kernel[5][64]; /* instances of the five kernels (iteration mode), as
                          name<template arguments>, e.g. zsweep<float,125,
                          16,512,1,2> for k_zsweep                          */
+  double active_loads; /* load cases still iterating, averaged over the
+                          sampled iterations (what a launch processed)     */
 } hm_timing;
 
 /* Per-load-case outcome. */

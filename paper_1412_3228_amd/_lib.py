@@ -55,7 +55,7 @@ class HmTiming(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("n_load", ctypes.c_int), ("ms", ctypes.c_double * 5),
                 ("x_lines", ctypes.c_int), ("y_width", ctypes.c_int), ("z_width", ctypes.c_int),
                 ("z_threads", ctypes.c_int), ("z_groups", ctypes.c_int),
-                ("kernel", (ctypes.c_char * 64) * 5)]
+                ("kernel", (ctypes.c_char * 64) * 5), ("active_loads", ctypes.c_double)]
 
 
 class HmProblem(ctypes.Structure):

@@ -490,7 +490,8 @@ def last_timing():
     t = L.HmTiming()
     L.check(_lib().hm_last_timing(ctypes.byref(t)))
     names = ("xsweep", "ysweep_fwd", "zsweep", "ysweep_inv", "finalize")
-    return {"iterations": t.iterations, "n_load": t.n_load, "ms": {n: t.ms[i] for i, n in enumerate(names)},
+    return {"iterations": t.iterations, "n_load": t.n_load, "active_loads": t.active_loads,
+            "ms": {n: t.ms[i] for i, n in enumerate(names)},
             "schedule": {"x_lines": t.x_lines, "y_width": t.y_width, "z_width": t.z_width,
                          "z_threads": t.z_threads, "z_groups": t.z_groups},
             "kernels": {n: t.kernel[i].value.decode() for i, n in enumerate(names)}}

@@ -952,12 +952,16 @@ int prepare_material(Group& g, const std::vector<ProblemIn>& all, const hm_solve
   return fail(HM_E_DEVICE, "material table did not fit after growing");
 }
 
-// Direct launches with a HIP event before and after every kernel of one
-// group; durations are read back at each poll and averaged over the
-// iterations that the longest load case evaluated.
+// Direct launches of one group; every kProfileStride-th iteration (0, 4,
+// 8, ...) has a HIP event before and after each of its kernels (an event
+// record costs a few microseconds of device time, so the other iterations
+// run without).  Durations are read back at each poll and averaged over the
+// sampled iterations that the longest load case evaluated.
+constexpr int kProfileStride = 4;
+
 int profiled_loop(Plan* p, const hm_solve_opts* opts, hipStream_t s) {
   const int k = opts->check_every;
-  std::vector<hipEvent_t> ev((size_t)6 * k, nullptr);
+  std::vector<hipEvent_t> ev((size_t)5 * k, nullptr);
   for (auto& e : ev)
     if (hipEventCreate(&e) != hipSuccess) {
       for (auto& q : ev)
@@ -965,35 +969,37 @@ int profiled_loop(Plan* p, const hm_solve_opts* opts, hipStream_t s) {
       return fail(HM_E_DEVICE, "hipEventCreate failed");
     }
   SolveArgs a = p->args;
-  std::vector<double> dur;  // 5 per iteration
+  std::vector<int> sampled_it;   // iteration of each sampled record
+  std::vector<double> dur;       // 4 per sampled iteration
   bool done = false;
   int it = 0, rc = HM_OK;
   hipError_t err = hipSuccess;
   while (!done && it <= opts->max_iter && err == hipSuccess && rc == HM_OK) {
-    int nb = 0;
-    for (; nb < k && it <= opts->max_iter; ++nb, ++it) {
-      hipEvent_t* e = &ev[(size_t)6 * nb];
+    std::vector<int> batch;  // sampled iterations of this block, in order
+    for (int nb = 0; nb < k && it <= opts->max_iter; ++nb, ++it) {
+      const bool rec = it % kProfileStride == 0;
+      hipEvent_t* e = &ev[(size_t)5 * batch.size()];
       a.first = it == 0 ? 1 : 0;
-      err = hipEventRecord(e[0], s);
+      if (rec) err = hipEventRecord(e[0], s);
       if (err == hipSuccess) err = (it == 0 ? p->X->first : p->X->iter)(a, s);
-      if (err == hipSuccess) err = hipEventRecord(e[1], s);
+      if (rec && err == hipSuccess) err = hipEventRecord(e[1], s);
       if (err == hipSuccess) err = p->Y->fwd(a, s);
-      if (err == hipSuccess) err = hipEventRecord(e[2], s);
+      if (rec && err == hipSuccess) err = hipEventRecord(e[2], s);
       if (err == hipSuccess) err = p->Z->run(a, s);
-      if (err == hipSuccess) err = hipEventRecord(e[3], s);
+      if (rec && err == hipSuccess) err = hipEventRecord(e[3], s);
+      // the inverse y-sweep also ends the iteration (stop decision)
       if (err == hipSuccess) err = p->Y->inv(a, s);
-      if (err == hipSuccess) err = hipEventRecord(e[4], s);
-      // the end of the iteration runs inside the inverse y-sweep: the fifth
-      // interval is empty and kept for the layout of hm_timing
-      if (err == hipSuccess) err = hipEventRecord(e[5], s);
+      if (rec && err == hipSuccess) err = hipEventRecord(e[4], s);
       if (err != hipSuccess) break;
+      if (rec) batch.push_back(it);
     }
     if (err != hipSuccess) break;
     rc = poll_done(p, s, &done);
-    for (int b = 0; b < nb && rc == HM_OK; ++b) {
-      for (int q = 0; q < 5; ++q) {
+    for (size_t b = 0; b < batch.size() && rc == HM_OK && err == hipSuccess; ++b) {
+      sampled_it.push_back(batch[b]);
+      for (int q = 0; q < 4; ++q) {
         float ms = 0.0f;
-        err = hipEventElapsedTime(&ms, ev[(size_t)6 * b + q], ev[(size_t)6 * b + q + 1]);
+        err = hipEventElapsedTime(&ms, ev[5 * b + q], ev[5 * b + q + 1]);
         dur.push_back((double)ms);
       }
     }
@@ -1003,10 +1009,20 @@ int profiled_loop(Plan* p, const hm_solve_opts* opts, hipStream_t s) {
   if (rc) return rc;
   int last = 0;
   for (int l = 0; l < p->n_load; ++l) last = std::max(last, p->state_host[l].iters);
-  const int nit = std::min((int)(dur.size() / 5), last + 1);
+  int nit = 0;
+  double ms[4] = {0.0, 0.0, 0.0, 0.0}, active = 0.0;
+  for (size_t i = 0; i < sampled_it.size(); ++i) {
+    if (sampled_it[i] > last) break;
+    for (int q = 0; q < 4; ++q) ms[q] += dur[4 * i + q];
+    // a load case runs the kernels of iterations 0 .. iters
+    for (int l = 0; l < p->n_load; ++l) active += p->state_host[l].iters >= sampled_it[i] ? 1.0 : 0.0;
+    ++nit;
+  }
   hm_timing t;
   memset(&t, 0, sizeof t);
   t.iterations = nit;
+  for (int q = 0; q < 4; ++q) t.ms[q] = nit > 0 ? ms[q] / nit : 0.0;
+  t.active_loads = nit > 0 ? active / nit : 0.0;
   t.n_load = p->n_load;
   t.x_lines = p->X->lines;
   t.y_width = p->Y->width;
@@ -1016,9 +1032,6 @@ int profiled_loop(Plan* p, const hm_solve_opts* opts, hipStream_t s) {
   const char* names[4] = {p->X->name, p->Y->fwd_name, p->Z->name, p->Y->inv_name};
   for (int q = 0; q < 4; ++q) snprintf(t.kernel[q], sizeof t.kernel[q], "%s", names[q]);
   snprintf(t.kernel[4], sizeof t.kernel[4], "(inside the inverse ysweep)");
-  for (int i = 0; i < nit; ++i)
-    for (int q = 0; q < 5; ++q) t.ms[q] += dur[(size_t)5 * i + q];
-  for (int q = 0; q < 5; ++q) t.ms[q] /= nit > 0 ? nit : 1;
   g_last_timing = t;
   g_have_timing = true;
   return HM_OK;
