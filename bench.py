@@ -56,11 +56,15 @@ PROFILE_GLOB = os.path.join(ROOT, "profiles", "hbm_traffic_*.txt")
 
 
 def kernel_source_hash():
-    """sha256 over the sources of the solver kernels (counters go stale when it changes)."""
+    """sha256 over the code of the solver kernels, comments and blank lines
+    left out (counters go stale when it changes)."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1412_3228_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1412_3228_amd", "csrc", name)) as f:
+            for line in f:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

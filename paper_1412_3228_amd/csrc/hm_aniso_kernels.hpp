@@ -1,8 +1,8 @@
 // Anisotropic phases: the rules of Section 2 for two general phase tensors
 // (Voigt eq. 3, Reuss eq. 4, 2-layer eq. 5), tabulated once per solve as
 // general rows of c~ - c0, and the x-sweep instances that read them.  The
-// y- and z-sweeps and finalize are the elastic ones (the reference medium
-// stays isotropic).
+// y- and z-sweeps and the end of the iteration are the elastic ones (the
+// reference medium stays isotropic).
 //
 // Mandel form throughout (order 11, 22, 33, 23, 13, 12, sqrt(2) on shear
 // rows and columns): an orthonormal basis of symmetric tensors, so

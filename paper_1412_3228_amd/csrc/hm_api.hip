@@ -2,8 +2,8 @@
 // (per precision, grid and load count: workspace, twiddles, launch
 // arguments, captured graphs) and the host side of the fixed-point loop.
 //
-// The loop launches xsweep, ysweep(forward), zsweep, ysweep(inverse) and
-// finalize per iteration; finalize decides on the device whether a load case
+// The loop launches xsweep, ysweep(forward), zsweep and ysweep(inverse) per
+// iteration; the inverse y-sweep decides on the device whether a load case
 // stops (Section 2 setup: stress-equilibrium criterion), and the sweeps of a
 // stopped load case return at once, so the host only polls the stop flags
 // every `check_every` iterations and the iteration counts are exact.
@@ -1096,13 +1096,13 @@ hipError_t cg_vector(const Plan* p, int op, const SolveArgs& a, hipStream_t s) {
 }
 
 hipError_t cg_scalar(int step, const SolveArgs& a, hipStream_t s) {
-  const dim3 grid(a.n_load), block(kFinalizeThreads);
+  const dim3 grid(a.n_load), block(kCgScalarThreads);
   if (step == CGS_INIT)
-    hipLaunchKernelGGL((k_cg_scalar<kFinalizeThreads, CGS_INIT>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_cg_scalar<kCgScalarThreads, CGS_INIT>), grid, block, 0, s, a);
   else if (step == CGS_ALPHA)
-    hipLaunchKernelGGL((k_cg_scalar<kFinalizeThreads, CGS_ALPHA>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_cg_scalar<kCgScalarThreads, CGS_ALPHA>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((k_cg_scalar<kFinalizeThreads, CGS_BETA>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_cg_scalar<kCgScalarThreads, CGS_BETA>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ template <typename C> __device__ __forceinline__ C c_mul(C a, C b) {
 }
 template <typename C, typename T> __device__ __forceinline__ C c_scale(C a, T s) { return C{a.x * s, a.y * s}; }
 
-// Stop codes written by the finalize kernel (mirror the public HM_* codes).
+// Stop codes written at the end of an iteration (mirror the public HM_* codes).
 enum : int { ST_RUNNING = -1, ST_CONVERGED = 0, ST_NOT_CONVERGED = 1, ST_STALLED = 2, ST_DIVERGED = 3 };
 // Data flags raised while the material table is built.
 enum : int { FLAG_NONE_FRACTIONAL = 1, FLAG_BAD_INCL = 2 };

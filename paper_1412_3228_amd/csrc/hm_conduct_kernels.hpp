@@ -16,8 +16,8 @@
 // Storage and sweeps are those of the elastic solver with three components
 // per load: x-half-spectra cx<T>[load][3][nz][ny][Hp]; xsweep (inverse
 // x-DFT, tau, forward x-DFT), ysweep (shared kernel, NC = 3), zsweep
-// (z-DFTs and Gamma0^), ysweep inverse, finalize (shared, conduction
-// branch).  The xsweep packs components 0 and 1 of a line into one complex
+// (z-DFTs and Gamma0^), ysweep inverse with the end of the iteration
+// (shared, conduction branch).  The xsweep packs components 0 and 1 of a line into one complex
 // line and component 2 of two neighbouring lines into another.
 //
 // Equilibrium error: for xi != 0, xi . q^_i = |xi| (a_i - a_(i-1)) with

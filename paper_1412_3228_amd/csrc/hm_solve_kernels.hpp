@@ -4,14 +4,15 @@
 // Storage between iterations: the x-spectrum of the strain, i.e. for every
 // (load, component, z, y) the half line kx = 0..(nx-1)/2 of the DFT along x
 // (the other half follows by Hermitian symmetry of real data).  One
-// iteration is four sweeps over that array plus a tiny finalize kernel:
+// iteration is four sweeps over that array:
 //   xsweep  inverse x-DFT -> strain at the grid points -> polarization
 //           tau = (c~ - c0) : eps -> forward x-DFT; per-block sums of tau
 //   ysweep  forward y-DFT of every (component, z, kx) line
 //   zsweep  forward z-DFT, eps^ = -Gamma0^ : tau^ (eps^(0) = E), the
 //           equilibrium-error partial sums, inverse z-DFT
-//   ysweep  inverse y-DFT
-//   finalize  error, mean stress, stop decision (one block per load case)
+//   ysweep  inverse y-DFT; seven of its blocks per load case reduce the
+//           partial sums and the last takes the error, the mean stress and
+//           the stop decision
 // The six real strain components are transformed as three complex lines
 // (11 + i 22, 33 + i 23, 13 + i 12), which is exact for real data of any
 // (odd) length.  The 1/N of the inverse transform is applied in zsweep.
@@ -35,8 +36,8 @@ namespace hm {
 
 enum : int { MODE_FIRST = 0, MODE_ITER = 1, MODE_EXPORT = 2 };
 
-// Block size of the finalize kernel (one block per load case).
-constexpr int kFinalizeThreads = 1024;
+// Block size of the CG scalar kernels (one block per load case).
+constexpr int kCgScalarThreads = 1024;
 
 // Deterministic block sum (fixed shuffle tree, then waves in order); the
 // result is valid in thread 0.
@@ -1160,7 +1161,7 @@ __global__ __launch_bounds__(384) void k_zsweep_wave(SolveArgs a) {
   if (tid == 0) a.errpart[(size_t)load * ((size_t)ny * a.ntx4) + (size_t)ky * a.ntx4 + tile] = tot;
 }
 
-// -------------------------------------------------------------- finalize --
+// ------------------------------------------------------ end of iteration --
 __device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
   const double t = s + x;
   if (fabs(s) >= fabs(x))
