@@ -1464,7 +1464,7 @@ std::vector<double> dirichlet_matrix(int n, int m) {
 // Matrices and temporaries of one (device, precision, n, m) series, kept
 // until hm_release_plans.
 struct SeriesPlan {
-  void* k[3] = {nullptr, nullptr, nullptr};  // x transposed, y, z
+  void* k[3] = {nullptr, nullptr, nullptr};  // x, y, z matrices, each transposed (n_d x m_d)
   void* t1 = nullptr;                        // after the x pass
   void* t2 = nullptr;                        // after the y pass (3D)
 };
@@ -1592,8 +1592,8 @@ int hm_fourier_series(const hm_grid* grid, const int m[3], hm_prec prec, const v
     } else {
       q = new SeriesPlan();
       int rc = upload_matrix(dirichlet_matrix(nx, m[0]), m[0], nx, true, fp64, &q->k[0]);
-      if (!rc) rc = upload_matrix(dirichlet_matrix(ny, m[1]), m[1], ny, false, fp64, &q->k[1]);
-      if (!rc) rc = upload_matrix(dirichlet_matrix(nz, m[2]), m[2], nz, false, fp64, &q->k[2]);
+      if (!rc) rc = upload_matrix(dirichlet_matrix(ny, m[1]), m[1], ny, true, fp64, &q->k[1]);
+      if (!rc) rc = upload_matrix(dirichlet_matrix(nz, m[2]), m[2], nz, true, fp64, &q->k[2]);
       if (!rc) rc = device_alloc(&q->t1, (size_t)nz * ny * m[0] * rb, "series x pass");
       if (!rc && zpass) rc = device_alloc(&q->t2, (size_t)nz * m[1] * m[0] * rb, "series y pass");
       if (rc) {

@@ -7,10 +7,9 @@
 //   D_n(t) = (1/n) sum_{a in J} exp(2 pi i a t) = sin(pi n t) / (n sin(pi t)).
 // On a finer grid of m_d points per axis this is three dense contractions
 // with (m_d x n_d) matrices, one axis at a time: no transform length
-// restrictions on n or m.  The host fills the matrices; each pass here is
-// a blocked matrix product on the vector ALUs (FP64 matrix cores run at
-// the vector rate on this chip, and FP32 ones need no more than the
-// contraction's 2 flops per loaded operand).
+// restrictions on n or m.  The host fills the matrices; the pass along
+// contiguous lines is a blocked product on the vector ALUs (lines staged in
+// LDS), the strided passes run on the matrix cores.
 //
 // Stiffness component: the filtered stiffness of Section 2 (eqs. 3-5) at
 // each voxel applied to a unit Mandel strain, one Mandel entry kept.
@@ -24,100 +23,156 @@
 
 namespace hm {
 
-constexpr int kPassThreads = 256;
-constexpr int kLinePass = 8;    // lines per block of the contiguous pass
-constexpr int kStridedOut = 16; // outputs per thread of the strided pass
-constexpr int kStridedCols = 2; // columns per thread of the strided pass
+// Matrix-core form of the contractions: one 16 x 16 x 4 MFMA takes a 16 x 4
+// tile A (lane l holds row l % 16, column l / 16) and a 4 x 16 tile B (lane
+// l holds row l / 16, column l % 16) and accumulates a 16 x 16 tile of C,
+// four values per lane: rows l / 16 + 4 m (FP64) or 4 (l / 16) + m (FP32)
+// of column l % 16.  A wave owns RT x CT such tiles, a block of four waves
+// twice that in each direction (measured on the 125^3 -> 375^3 series:
+// FP64 2 x 4, FP32 4 x 4).
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  static constexpr int RT = 2, CT = 4;
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int m) { return lane / 16 + 4 * m; }
+};
+template <> struct Mfma<float> {
+  static constexpr int RT = 4, CT = 4;
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int m) { return 4 * (lane / 16) + m; }
+};
 
-// Contiguous lines (I == 1): a block stages kLinePass input lines in LDS and
-// its threads run along the outputs j'; the matrix is read transposed
-// (Kt[j][j'], so consecutive threads read consecutive entries) and each
-// entry serves all staged lines.
+
+// Contiguous lines (I == 1): C = In Kt with In[o][j] the (O x n) lines and
+// Kt the transposed matrix (n x mj): A tiles are 16 lines x 4 samples (a
+// wave's reads of one line over successive steps share cache lines), B
+// tiles 4 samples x 16 outputs j' (16 lanes read 16 consecutive entries),
+// and each row of C is stored 16 consecutive j' at a time.
 template <typename T>
-__global__ __launch_bounds__(kPassThreads) void k_series_lines(const T* in, T* out, const T* Kt, long long O,
-                                                               int n, int mj) {
-  extern __shared__ unsigned char smem[];
-  T* rows = reinterpret_cast<T*>(smem);  // [kLinePass][n]
-  const long long o0 = (long long)blockIdx.y * kLinePass;
-  const int jp = blockIdx.x * kPassThreads + threadIdx.x;
-  for (int e = threadIdx.x; e < kLinePass * n; e += kPassThreads) {
-    const int l = e / n, j = e - (e / n) * n;
-    rows[e] = o0 + l < O ? in[(o0 + l) * n + j] : T(0);
+__global__ __launch_bounds__(256) void k_series_lines(const T* __restrict__ in, T* __restrict__ out,
+                                                      const T* __restrict__ Kt, long long O, int n, int mj) {
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int RT = M::RT, CT = M::CT;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long long r0 = (long long)blockIdx.y * (2 * 16 * RT) + (wv >> 1) * 16 * RT;
+  const int c0 = blockIdx.x * (2 * 16 * CT) + (wv & 1) * 16 * CT;
+  const int lr = lane % 16, lk = lane / 16;
+  // this lane's lines (clamped inside the field; their results past O are
+  // not stored) and outputs (zero past mj)
+  long long arow[RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a) arow[a] = r0 + 16 * a + lr < O ? r0 + 16 * a + lr : O - 1;
+  bool cok[CT];
+#pragma unroll
+  for (int b = 0; b < CT; ++b) cok[b] = c0 + 16 * b + lr < mj;
+  v4 acc[RT][CT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) acc[a][b] = v4{T(0), T(0), T(0), T(0)};
+#pragma unroll 2
+  for (int k0 = 0; k0 < n; k0 += 4) {
+    const int k = k0 + lk;
+    const bool kok = k < n;
+    T av[RT], bv[CT];
+#pragma unroll
+    for (int a = 0; a < RT; ++a) av[a] = kok ? in[(size_t)arow[a] * n + k] : T(0);
+#pragma unroll
+    for (int b = 0; b < CT; ++b) bv[b] = (kok && cok[b]) ? Kt[(size_t)k * mj + c0 + 16 * b + lr] : T(0);
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int b = 0; b < CT; ++b) acc[a][b] = M::mac(av[a], bv[b], acc[a][b]);
   }
-  __syncthreads();
-  if (jp >= mj) return;
-  T acc[kLinePass];
 #pragma unroll
-  for (int l = 0; l < kLinePass; ++l) acc[l] = T(0);
-  for (int j = 0; j < n; ++j) {
-    const T k = Kt[(size_t)j * mj + jp];
+  for (int a = 0; a < RT; ++a)
 #pragma unroll
-    for (int l = 0; l < kLinePass; ++l) acc[l] += rows[l * n + j] * k;
-  }
+    for (int m = 0; m < 4; ++m) {
+      const long long row = r0 + 16 * a + M::row(lane, m);
+      if (row >= O) continue;
 #pragma unroll
-  for (int l = 0; l < kLinePass; ++l)
-    if (o0 + l < O) out[(o0 + l) * mj + jp] = acc[l];
+      for (int b = 0; b < CT; ++b)
+        if (cok[b]) out[(size_t)row * mj + c0 + 16 * b + lr] = acc[a][b][m];
+    }
 }
 
-// Strided axis (I > 1): threads run along i (coalesced), each computes
-// kStridedOut consecutive outputs j' for kStridedCols columns i (256 apart,
-// so every load stays coalesced).  The matrix entries are the same for every
-// thread of the block, so they are read through the scalar cache (read-only,
-// no aliasing) and each one feeds kStridedCols multiply-adds; each loaded
-// input value feeds kStridedOut.  (Tile measured on the 125^3 -> 375^3
-// series: 16 x 2 beat 32 x 1, 16 x 1, 8 x 4, 16 x 4 and 12 x 3.)
+// Strided axis (I > 1): for each o, C = K In of the (mj x n) matrix and
+// the (n x I) slab In[j][i] = in[o][j][i]: A tiles are 16 rows j' x 4 of K
+// (stored transposed, so 16 lanes read 16 consecutive rows), B tiles 4 x 16
+// consecutive i of the slab, one block per row block and column block
+// (blocks that walk the row blocks of their columns, or read K row-major,
+// were slower).  The contraction runs in steps of 4 with zeros past n; rows
+// or columns past the edges are not stored.
 template <typename T>
-__global__ __launch_bounds__(kPassThreads) void k_series_strided(const T* __restrict__ in, T* __restrict__ out,
-                                                                 const T* __restrict__ K, long long I, int n,
-                                                                 int mj) {
-  const long long ib = (long long)blockIdx.x * kPassThreads * kStridedCols + threadIdx.x;
-  const int j0 = blockIdx.y * kStridedOut;
+__global__ __launch_bounds__(256) void k_series_strided(const T* __restrict__ in, T* __restrict__ out,
+                                                        const T* __restrict__ Kt, long long I, int n, int mj) {
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int RT = M::RT, CT = M::CT;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * (2 * 16 * RT) + (wv >> 1) * 16 * RT;
+  const long long c0 = (long long)blockIdx.x * (2 * 16 * CT) + (wv & 1) * 16 * CT;
   const long long o = blockIdx.z;
-  bool ok[kStridedCols];
+  const T* src = in + (size_t)o * n * I;
+  T* dst = out + (size_t)o * mj * I;
+  const int lr = lane % 16, lk = lane / 16;
+  // this lane's K rows (clamped inside the matrix; their products past mj
+  // are not stored) and In columns (zero past I)
+  int arow[RT];
 #pragma unroll
-  for (int c = 0; c < kStridedCols; ++c) ok[c] = ib + (long long)kPassThreads * c < I;
-  T acc[kStridedOut][kStridedCols];
+  for (int a = 0; a < RT; ++a) arow[a] = min(r0 + 16 * a + lr, mj - 1);
+  bool cok[CT];
 #pragma unroll
-  for (int t = 0; t < kStridedOut; ++t)
+  for (int b = 0; b < CT; ++b) cok[b] = c0 + 16 * b + lr < I;
+  v4 acc[RT][CT];
 #pragma unroll
-    for (int c = 0; c < kStridedCols; ++c) acc[t][c] = T(0);
-  const T* src = in + (size_t)o * n * I + ib;
-  // rows past mj repeat the last row (their results are not stored)
-  const T* kr = K + (size_t)j0 * n;
-  const int tmax = mj - 1 - j0;
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) acc[a][b] = v4{T(0), T(0), T(0), T(0)};
 #pragma unroll 2
-  for (int j = 0; j < n; ++j) {
-    T v[kStridedCols];
+  for (int k0 = 0; k0 < n; k0 += 4) {
+    const int k = k0 + lk;
+    const bool kok = k < n;
+    T av[RT], bv[CT];
 #pragma unroll
-    for (int c = 0; c < kStridedCols; ++c) v[c] = ok[c] ? src[(size_t)j * I + kPassThreads * c] : T(0);
+    for (int a = 0; a < RT; ++a) av[a] = kok ? Kt[(size_t)k * mj + arow[a]] : T(0);
 #pragma unroll
-    for (int t = 0; t < kStridedOut; ++t) {
-      const T k = kr[(size_t)(t < tmax ? t : tmax) * n + j];
+    for (int b = 0; b < CT; ++b) bv[b] = (kok && cok[b]) ? src[(size_t)k * I + c0 + 16 * b + lr] : T(0);
 #pragma unroll
-      for (int c = 0; c < kStridedCols; ++c) acc[t][c] += k * v[c];
-    }
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int b = 0; b < CT; ++b) acc[a][b] = M::mac(av[a], bv[b], acc[a][b]);
   }
-  T* dst = out + (size_t)o * mj * I + ib;
 #pragma unroll
-  for (int t = 0; t < kStridedOut; ++t)
+  for (int a = 0; a < RT; ++a)
 #pragma unroll
-    for (int c = 0; c < kStridedCols; ++c)
-      if (j0 + t < mj && ok[c]) dst[(size_t)(j0 + t) * I + kPassThreads * c] = acc[t][c];
+    for (int m = 0; m < 4; ++m) {
+      const int row = r0 + 16 * a + M::row(lane, m);
+      if (row >= mj) continue;
+#pragma unroll
+      for (int b = 0; b < CT; ++b)
+        if (cok[b]) dst[(size_t)row * I + c0 + 16 * b + lr] = acc[a][b][m];
+    }
 }
 
 template <typename T> hipError_t series_pass(const AxisPass& p, hipStream_t s) {
   const T* in = static_cast<const T*>(p.in);
   T* out = static_cast<T*>(p.out);
   const T* K = static_cast<const T*>(p.K);
+  constexpr int BR = 2 * 16 * Mfma<T>::RT, BC = 2 * 16 * Mfma<T>::CT;
   if (p.I == 1) {
-    const dim3 grid((unsigned)((p.mj + kPassThreads - 1) / kPassThreads), (unsigned)((p.O + kLinePass - 1) / kLinePass));
-    hipLaunchKernelGGL((k_series_lines<T>), grid, dim3(kPassThreads), (size_t)kLinePass * p.n * sizeof(T), s, in, out,
-                       K, p.O, p.n, p.mj);
+    const dim3 grid((unsigned)((p.mj + BC - 1) / BC), (unsigned)((p.O + BR - 1) / BR));
+    hipLaunchKernelGGL((k_series_lines<T>), grid, dim3(256), 0, s, in, out, K, p.O, p.n, p.mj);
   } else {
-    const long long cols = (long long)kPassThreads * kStridedCols;
-    const dim3 grid((unsigned)((p.I + cols - 1) / cols), (unsigned)((p.mj + kStridedOut - 1) / kStridedOut),
-                    (unsigned)p.O);
-    hipLaunchKernelGGL((k_series_strided<T>), grid, dim3(kPassThreads), 0, s, in, out, K, p.I, p.n, p.mj);
+    const dim3 grid((unsigned)((p.I + BC - 1) / BC), (unsigned)((p.mj + BR - 1) / BR), (unsigned)p.O);
+    hipLaunchKernelGGL((k_series_strided<T>), grid, dim3(256), 0, s, in, out, K, p.I, p.n, p.mj);
   }
   return hipGetLastError();
 }

@@ -10,7 +10,8 @@ namespace hm {
 
 // One separable pass of the series: out[o][j'][i] = sum_j K[j'][j] in[o][j][i]
 // (i contiguous, extent I; j contracted, extent n; j' extent mj; o extent O).
-// K is row-major (mj x n).  When I == 1 the pass runs along contiguous lines.
+// K is stored transposed: K[j][j'] (n x mj).  When I == 1 the pass runs
+// along contiguous lines.
 struct AxisPass {
   const void* in;
   void* out;
