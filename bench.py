@@ -50,8 +50,10 @@ METRIC = "voxel-iterations/s of LS fixed point, mixed vs FP64 at equal C_eff err
 CONTRASTS = (100.0, 0.01)
 
 
+# the sources of the solver sweeps (the sweep counters under profiles/ go
+# stale when their code changes)
 KERNEL_SOURCES = ("hm_solve_kernels.hpp", "hm_conduct_kernels.hpp", "hm_aniso_kernels.hpp", "hm_fft.hpp",
-                  "hm_material.hpp", "hm_common.hpp", "hm_extrapolate.hip")
+                  "hm_material.hpp", "hm_common.hpp")
 PROFILE_GLOB = os.path.join(ROOT, "profiles", "hbm_traffic_*.txt")
 
 
