@@ -334,8 +334,12 @@ template <typename T> __device__ __forceinline__ void gen_tau(const T* coef, int
 // kx or x, so row indices are wave-uniform and need no per-lane division.
 // GEN: general (anisotropic) material rows, gathered per voxel in the
 // polarization pass instead of before it.
+// Single-precision blocks of 4 or more lines are held to 5 waves per SIMD
+// (96 registers): the radix-27 form then fits without spills.
+template <typename T, int L> constexpr int xsweep_min_waves() { return sizeof(T) == 4 && L >= 4 ? 5 : 1; }
+
 template <typename T, int NX, int L, int NT, int MODE, int RMAX = max_radix<T>(), bool GEN = false>
-__global__ __launch_bounds__(NT) void k_xsweep(SolveArgs a) {
+__global__ __launch_bounds__(NT, (xsweep_min_waves<T, L>())) void k_xsweep(SolveArgs a) {
   constexpr int LL = 3 * L;
   constexpr int LD = LL | 1;  // odd row stride: element rows spread over the banks
   constexpr int H = (NX + 1) / 2;
