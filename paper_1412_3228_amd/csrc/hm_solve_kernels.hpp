@@ -1540,7 +1540,7 @@ template <int TAG, typename T, int... A> const char* instance_name(const char* b
   (void)once;
   return buf;
 }
-constexpr int kMaxVariants = 8;
+constexpr int kMaxVariants = 10;
 struct AxisKernels {
   int n;
   int nxv, nyv, nzv;
@@ -1575,9 +1575,10 @@ template <typename T, int N, int V> struct YTile {
 // Variant 2 transforms CG = 3 (or 2) components per LDS pass at width
 // 128 B when that fits in 56 KB of LDS; it holds one frequency slot per
 // thread (so needs W N <= 1024).
-// Prefetch depth D: 1, except variant 3 (single precision only), which is
-// variant 0 with depth 2.  LDS rows are padded to an odd stride, except in
-// variants 4 and 5 (variants 0 and 3 with rows of exactly W values).
+// Prefetch depth D: 1, except variants 3 and 6 (single precision only),
+// which are variant 0 with depth 2 and 3 (a fourth was measured no faster).
+// LDS rows are padded to an odd stride, except in variants 4, 5 and 7
+// (variants 0, 3 and 6 with rows of exactly W values).
 template <typename T, int N, int V> struct ZTile {
   static constexpr int W0 = 128 / (int)sizeof(cx<T>);
   static constexpr int W1 = 256 / (int)sizeof(cx<T>);
@@ -1589,8 +1590,8 @@ template <typename T, int N, int V> struct ZTile {
   static constexpr int CG =
       (V == 2 && W * N <= 1024) ? (lds3 <= 56 * 1024 ? 3 : (lds2 <= 56 * 1024 ? 2 : 1)) : 1;
   static constexpr int NT = clamp_int(round64((W * N + QT - 1) / QT), 64, 1024);
-  static constexpr int D = (V == 3 || V == 5) ? 2 : 1;
-  static constexpr int PAD = V >= 4 ? 0 : 1;
+  static constexpr int D = (V == 3 || V == 5) ? 2 : (V >= 6 ? 3 : 1);
+  static constexpr int PAD = (V == 4 || V == 5 || V == 7) ? 0 : 1;
 };
 
 template <typename T, int NX, int MODE, int V>
@@ -1665,6 +1666,8 @@ AxisKernels make_axis_kernels() {
   if constexpr (sizeof(T) == 4) k.z[k.nzv++] = make_z<T, N, 3>();
   k.z[k.nzv++] = make_z<T, N, 4>();
   if constexpr (sizeof(T) == 4) k.z[k.nzv++] = make_z<T, N, 5>();
+  if constexpr (sizeof(T) == 4) k.z[k.nzv++] = make_z<T, N, 6>();
+  if constexpr (sizeof(T) == 4) k.z[k.nzv++] = make_z<T, N, 7>();
   // wavefront x-sweeps: (2 lines per wave, 2 waves) and (1 line per wave, 4 waves)
   if constexpr (2 * N * ((6 | 1)) * (int)sizeof(cx<T>) <= 56 * 1024) {
     k.x[k.nxv++] = XKern{&launch_x_wave<T, N, MODE_FIRST, 2, 2>, &launch_x_wave<T, N, MODE_ITER, 2, 2>,
