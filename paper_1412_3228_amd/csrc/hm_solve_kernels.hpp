@@ -1663,11 +1663,14 @@ AxisKernels make_axis_kernels() {
   k.z[1] = make_z<T, N, 1>();
   k.nzv = 2;
   if constexpr (ZTile<T, N, 2>::CG > 1) k.z[k.nzv++] = make_z<T, N, 2>();
-  if constexpr (sizeof(T) == 4) k.z[k.nzv++] = make_z<T, N, 3>();
+  // deeper prefetch: always in single precision; in double precision only up
+  // to 128 points, beyond which the extra slots spill
+  constexpr bool deep = sizeof(T) == 4 || N <= 128;
+  if constexpr (deep) k.z[k.nzv++] = make_z<T, N, 3>();
   k.z[k.nzv++] = make_z<T, N, 4>();
-  if constexpr (sizeof(T) == 4) k.z[k.nzv++] = make_z<T, N, 5>();
-  if constexpr (sizeof(T) == 4) k.z[k.nzv++] = make_z<T, N, 6>();
-  if constexpr (sizeof(T) == 4) k.z[k.nzv++] = make_z<T, N, 7>();
+  if constexpr (deep) k.z[k.nzv++] = make_z<T, N, 5>();
+  if constexpr (deep) k.z[k.nzv++] = make_z<T, N, 6>();
+  if constexpr (deep) k.z[k.nzv++] = make_z<T, N, 7>();
   // wavefront x-sweeps: (2 lines per wave, 2 waves) and (1 line per wave, 4 waves)
   if constexpr (2 * N * ((6 | 1)) * (int)sizeof(cx<T>) <= 56 * 1024) {
     k.x[k.nxv++] = XKern{&launch_x_wave<T, N, MODE_FIRST, 2, 2>, &launch_x_wave<T, N, MODE_ITER, 2, 2>,
