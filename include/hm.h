@@ -124,9 +124,10 @@ typedef struct {
 } hm_solve_opts;
 
 /* Average device duration per launch of each kernel of the iteration, over
- * the sampled iterations (0, 4, 8, ...: events around the kernels of those
+ * the sampled iterations (1, 5, 9, ...: events around the kernels of those
  * only, an event record costing a few microseconds of device time) that a
- * profiled solve evaluated (the longest load case). */
+ * profiled solve evaluated (the longest load case); iterations = 0 and all
+ * durations 0 when the solve stopped at iterate 0. */
 typedef struct {
   int iterations; /* sampled iterations averaged                           */
   int n_load;     /* load cases of the solve                               */

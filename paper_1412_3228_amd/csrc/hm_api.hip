@@ -952,11 +952,14 @@ int prepare_material(Group& g, const std::vector<ProblemIn>& all, const hm_solve
   return fail(HM_E_DEVICE, "material table did not fit after growing");
 }
 
-// Direct launches of one group; every kProfileStride-th iteration (0, 4,
-// 8, ...) has a HIP event before and after each of its kernels (an event
-// record costs a few microseconds of device time, so the other iterations
-// run without).  Durations are read back at each poll and averaged over the
-// sampled iterations that the longest load case evaluated.
+// Direct launches of one group; every kProfileStride-th iteration from
+// iteration 1 on (1, 5, 9, ...) has a HIP event before and after each of its
+// kernels (an event record costs a few microseconds of device time, so the
+// other iterations run without).  Iteration 0 is never sampled: its x-sweep
+// starts from the uniform strain, and the first launch of a kernel also
+// waits for its code object to load.  Durations are read back at each poll
+// and averaged over the sampled iterations that the longest load case
+// evaluated.
 constexpr int kProfileStride = 4;
 
 int profiled_loop(Plan* p, const hm_solve_opts* opts, hipStream_t s) {
@@ -977,7 +980,7 @@ int profiled_loop(Plan* p, const hm_solve_opts* opts, hipStream_t s) {
   while (!done && it <= opts->max_iter && err == hipSuccess && rc == HM_OK) {
     std::vector<int> batch;  // sampled iterations of this block, in order
     for (int nb = 0; nb < k && it <= opts->max_iter; ++nb, ++it) {
-      const bool rec = it % kProfileStride == 0;
+      const bool rec = it % kProfileStride == 1;
       hipEvent_t* e = &ev[(size_t)5 * batch.size()];
       a.first = it == 0 ? 1 : 0;
       if (rec) err = hipEventRecord(e[0], s);

@@ -260,9 +260,10 @@ def test_profiled_solve_matches_and_reports_timing(hm):
                                tol=1e-6, max_iter=500, check_every=7, profile=True)
     assert np.array_equal(a["C"], b["C"])
     t = hm.last_timing()
-    # events around the kernels of iterations 0, 4, 8, ... up to the last one evaluated
+    # events around the kernels of iterations 1, 5, 9, ... up to the last one evaluated
     its = [r["iters"] for r in b["reports"]]
-    sampled = list(range(0, max(its) + 1, 4))
+    sampled = list(range(1, max(its) + 1, 4))
+    assert len(sampled) >= 2
     assert t["iterations"] == len(sampled)
     assert t["active_loads"] == pytest.approx(np.mean([sum(n >= i for n in its) for i in sampled]), rel=1e-12)
     assert all(t["ms"][k] > 0 for k in ("xsweep", "ysweep_fwd", "zsweep", "ysweep_inv"))
