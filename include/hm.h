@@ -416,7 +416,9 @@ int hm_effective_tensor_phases(const hm_grid* grid, const hm_iso* phases, int n_
  *          matrix then the inclusion phase, row-major, symmetric positive
  *          definite; order 11, 22, 33, 23, 13, 12 with sqrt(2) on shear
  *          rows and columns), other inputs and outputs as hm_solve /
- *          hm_effective_tensor (autotune is ignored; schedule -1 or 0).
+ *          hm_effective_tensor (autotune times the y- and z-sweep
+ *          schedules, the x-sweep being the one general-row form; with
+ *          autotune == 0, schedule must be -1 or 0).
  * The tables of these solves hold 24 reals per fractional voxel and two
  * rows for the pure phases.
  */

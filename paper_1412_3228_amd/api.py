@@ -262,7 +262,8 @@ def hm_filter_phases(n, dim, spheres, labels, n_phases: int, radius_vox: float, 
 
 def hm_solve_phases(n, dim, phases, rule: str, frac: torch.Tensor, E, prec: str = "fp64", tol: float = 1e-4,
                     max_iter: int = 10000, c0_alpha: float = 1.0, check_every: int = 1, stall_window: int = 0,
-                    use_graph: bool = False, want_eps: bool = False, method: str = "fixed_point"):
+                    use_graph: bool = False, want_eps: bool = False, method: str = "fixed_point",
+                    autotune: bool = True):
     """hm_solve for a cell of len(phases) phases; frac is (len(phases) - 1, N)."""
     dev = frac.device
     N = int(n[0] * n[1] * n[2])
@@ -273,7 +274,7 @@ def hm_solve_phases(n, dim, phases, rule: str, frac: torch.Tensor, E, prec: str 
     rep = (L.HmReport * nl)()
     eps = torch.empty((nl, 6, N), dtype=_DT[prec], device=dev) if want_eps else None
     g = _grid(n, dim)
-    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, False, False, None, method)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, False, autotune, None, method)
     rc = _lib().hm_solve_phases(ctypes.byref(g), _phase_array(phases), len(phases), L.RULES[rule], _ptr(frac),
                                 Ea.ctypes.data_as(L._dp), nl, ctypes.byref(o), _ptr(eps),
                                 sig.ctypes.data_as(L._dp), rep, _stream(dev))
@@ -284,7 +285,7 @@ def hm_solve_phases(n, dim, phases, rule: str, frac: torch.Tensor, E, prec: str 
 def hm_effective_tensor_phases(n, dim, phases, rule: str, frac: torch.Tensor, prec: str = "fp64",
                                tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
                                check_every: int = 1, stall_window: int = 0, use_graph: bool = False,
-                               method: str = "fixed_point", profile: bool = False):
+                               method: str = "fixed_point", profile: bool = False, autotune: bool = True):
     """Effective Mandel tensor of a cell of len(phases) phases."""
     dev = frac.device
     N = int(n[0] * n[1] * n[2])
@@ -293,7 +294,7 @@ def hm_effective_tensor_phases(n, dim, phases, rule: str, frac: torch.Tensor, pr
     C = np.zeros((k, k))
     rep = (L.HmReport * k)()
     g = _grid(n, dim)
-    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, False, None, method)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, autotune, None, method)
     rc = _lib().hm_effective_tensor_phases(ctypes.byref(g), _phase_array(phases), len(phases), L.RULES[rule],
                                            _ptr(frac), ctypes.byref(o), C.ctypes.data_as(L._dp), None, rep,
                                            _stream(dev))
@@ -309,7 +310,7 @@ def _mandel_pair(C_phases) -> np.ndarray:
 def hm_solve_aniso(n, dim, C_phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor], spheres, E,
                    prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000, c0_alpha: float = 1.0,
                    check_every: int = 1, stall_window: int = 0, use_graph: bool = False, want_eps: bool = False,
-                   method: str = "fixed_point"):
+                   method: str = "fixed_point", autotune: bool = True):
     """hm_solve for two anisotropic phases given as Mandel matrices (2, 6, 6)."""
     dev = frac.device
     N = int(n[0] * n[1] * n[2])
@@ -323,7 +324,7 @@ def hm_solve_aniso(n, dim, C_phases, rule: str, frac: torch.Tensor, incl: Option
     eps = torch.empty((nl, 6, N), dtype=_DT[prec], device=dev) if want_eps else None
     g = _grid(n, dim)
     sph, ns = _spheres(spheres)
-    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, False, False, None, method)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, False, autotune, None, method)
     rc = _lib().hm_solve_aniso(ctypes.byref(g), Cp.ctypes.data_as(L._dp), L.RULES[rule], _ptr(frac), _ptr(incl),
                                sph, ns, Ea.ctypes.data_as(L._dp), nl, ctypes.byref(o), _ptr(eps),
                                sig.ctypes.data_as(L._dp), rep, _stream(dev))
@@ -334,7 +335,8 @@ def hm_solve_aniso(n, dim, C_phases, rule: str, frac: torch.Tensor, incl: Option
 def hm_effective_tensor_aniso(n, dim, C_phases, rule: str, frac: torch.Tensor, incl: Optional[torch.Tensor],
                               spheres, prec: str = "fp64", tol: float = 1e-4, max_iter: int = 10000,
                               c0_alpha: float = 1.0, check_every: int = 1, stall_window: int = 0,
-                              use_graph: bool = False, method: str = "fixed_point", profile: bool = False):
+                              use_graph: bool = False, method: str = "fixed_point", profile: bool = False,
+                              autotune: bool = True):
     """Effective Mandel tensor for two anisotropic phases."""
     dev = frac.device
     N = int(n[0] * n[1] * n[2])
@@ -346,7 +348,7 @@ def hm_effective_tensor_aniso(n, dim, C_phases, rule: str, frac: torch.Tensor, i
     rep = (L.HmReport * k)()
     g = _grid(n, dim)
     sph, ns = _spheres(spheres)
-    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, False, None, method)
+    o = _opts(prec, tol, max_iter, c0_alpha, check_every, stall_window, use_graph, profile, autotune, None, method)
     rc = _lib().hm_effective_tensor_aniso(ctypes.byref(g), Cp.ctypes.data_as(L._dp), L.RULES[rule], _ptr(frac),
                                           _ptr(incl), sph, ns, ctypes.byref(o), C.ctypes.data_as(L._dp), None, rep,
                                           _stream(dev))

@@ -508,7 +508,9 @@ int build_graph(Plan* p, int k) {
 // Times every compiled schedule of the three sweeps on this plan's own
 // workspace (iteration mode, all load cases active) and keeps the fastest.
 // Runs once per plan, before the first solve; the workspace is zeroed first
-// and the solver state is reset by the caller afterwards.
+// and the solver state is reset by the caller afterwards.  An anisotropic
+// plan has one x-sweep (the general-row one); its y- and z-sweeps are the
+// elastic ones and are chosen the same way.
 int tune_plan(Plan* p, hipStream_t s) {
   hipEvent_t e0, e1;
   HM_HIP(hipEventCreate(&e0));
@@ -538,11 +540,11 @@ int tune_plan(Plan* p, hipStream_t s) {
     *best = bestms;
     return e;
   };
-  const XKern* bx = &p->kx->x[0];
+  const XKern* bx = p->aniso ? &p->ak->x : &p->kx->x[0];
   const YKern* by = &p->ky->y[0];
   const ZKern* bz = &p->kz->z[0];
   float tbest = 1e30f, t = 0.0f;
-  for (int v = 0; v < p->kx->nxv && err == hipSuccess; ++v) {
+  for (int v = 0; v < (p->aniso ? 0 : p->kx->nxv) && err == hipSuccess; ++v) {
     set_schedule(p, &p->kx->x[v], by, bz);
     SolveArgs a = p->args;
     a.first = 0;
@@ -1225,9 +1227,16 @@ int run_groups(std::vector<Group>& G, const std::vector<ProblemIn>& all, const h
     if ((rc = ensure_hist(g.p, opts->max_iter + 1))) return rc;
     if ((rc = upload_params(g, all, opts, s))) return rc;
     if ((rc = prepare_material(g, all, opts, s))) return rc;
-    if (g.p->cond || g.p->aniso) {
-      // conduction and anisotropic plans have one compiled schedule
+    if (g.p->cond) {
+      // conduction plans have one compiled schedule
       if (opts->schedule >= 0 && opts->schedule != 0) return fail(HM_E_ARG, "conduction solves have one schedule");
+    } else if (g.p->aniso && !opts->autotune) {
+      // anisotropic plans: the tuned schedule, or else the first one
+      if (opts->schedule >= 0 && opts->schedule != 0) return fail(HM_E_ARG, "anisotropic solves pin no schedule");
+      if (g.p->tuned) {
+        set_schedule(g.p, &g.p->ak->x, &g.p->ky->y[0], &g.p->kz->z[0]);
+        g.p->tuned = false;
+      }
     } else if (opts->autotune) {
       if (!g.p->tuned && (rc = tune_plan(g.p, s))) return rc;
     } else if (opts->schedule >= 0) {
