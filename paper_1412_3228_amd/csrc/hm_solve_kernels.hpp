@@ -544,7 +544,11 @@ __global__ __launch_bounds__(NT) void k_ysweep(SolveArgs a) {
   __shared__ cx<T> s_tw[NY];
   const int tid = threadIdx.x;
   const int z = blockIdx.y;
-  const int load = blockIdx.z / NC, comp = blockIdx.z - NC * (blockIdx.z / NC);
+  // load cases in reverse block order: the x- and z-sweeps walk them
+  // forward, so each sweep starts on the load cases the previous one wrote
+  // last, which the last-level cache still holds when the state is not much
+  // larger than it
+  const int load = a.n_load - 1 - blockIdx.z / NC, comp = blockIdx.z - NC * (blockIdx.z / NC);
   int done;
   if constexpr (SIGN < 0) {
     done = a.state[load].done;
