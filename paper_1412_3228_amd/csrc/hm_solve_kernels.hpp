@@ -269,6 +269,26 @@ template <typename T> __device__ __forceinline__ void load_row8(const T* r, T v[
   }
 }
 
+// The traction history is read and written once per iteration, by the
+// z-sweep only: its accesses are marked non-temporal, so that the caches
+// keep the spectrum, which every sweep reads and writes.
+typedef float v2f __attribute__((ext_vector_type(2)));
+template <typename T> __device__ __forceinline__ cx<T> load_stream(const cx<T>* p) {
+  if constexpr (sizeof(T) == 4) {
+    const v2f u = __builtin_nontemporal_load(reinterpret_cast<const v2f*>(p));
+    return cx<T>{u.x, u.y};
+  } else {
+    const v2d u = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(p));
+    return cx<T>{u.x, u.y};
+  }
+}
+template <typename T> __device__ __forceinline__ void store_stream(cx<T>* p, cx<T> v) {
+  if constexpr (sizeof(T) == 4)
+    __builtin_nontemporal_store(v2f{v.x, v.y}, reinterpret_cast<v2f*>(p));
+  else
+    __builtin_nontemporal_store(v2d{v.x, v.y}, reinterpret_cast<v2d*>(p));
+}
+
 // Stiffness row (a1 - lambda0, a2 - 2 mu0, a3, a4, a5, n) of the voxel with
 // material id mv: a pure phase, or a row of the table (one global gather).
 template <typename T> __device__ __forceinline__ void material_row(const VoxelMaterial<T>& M, int mv, T r[8]) {
@@ -769,7 +789,8 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
     } else if (CG == 1 && nx - NG < HR) {
 #pragma unroll
       for (int q = 0; q < Q; ++q)
-        ring[r][0][q] = (ok[q] && hist_live) ? hp[(size_t)(nx - NG) * plane + off[q]] : cx<T>{T(0), T(0)};
+        ring[r][0][q] = (ok[q] && hist_live) ? load_stream<T>(hp + (size_t)(nx - NG) * plane + off[q])
+                                             : cx<T>{T(0), T(0)};
     }
     __syncthreads();
     fft_lines<T, NZ, LW, NT, -1, LD, 9>(buf, s_tw, tid);
@@ -807,11 +828,11 @@ __global__ __launch_bounds__(NT, 4) void k_zsweep(SolveArgs a) {
       if (h < HR)
         pv[h] = ring[(NG + h) % D][0][q];  // fetched in the forward loop
       else
-        pv[h] = hist_live ? h0[(size_t)h * plane] : cx<T>{T(0), T(0)};
+        pv[h] = hist_live ? load_stream<T>(h0 + (size_t)h * plane) : cx<T>{T(0), T(0)};
     }
-    h0[0] = z[q].a0;
-    h0[plane] = z[q].a1;
-    h0[2 * plane] = z[q].a2;
+    store_stream<T>(h0, z[q].a0);
+    store_stream<T>(h0 + plane, z[q].a1);
+    store_stream<T>(h0 + 2 * plane, z[q].a2);
     const double x0 = twopi * kx, x1 = twopi * ay, x2 = twopi * az;
     double dd;
     if constexpr (sizeof(T) == 4) {
@@ -1096,7 +1117,7 @@ __global__ __launch_bounds__(384) void k_zsweep_wave(SolveArgs a) {
     const bool ok = s < SL && kx0 + w < H && !a.first && !a.cg;
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-      h[q][d] = ok ? hp[(size_t)d * plane + (size_t)kz * zs + w] : cx<T>{T(0), T(0)};
+      h[q][d] = ok ? load_stream<T>(hp + (size_t)d * plane + (size_t)kz * zs + w) : cx<T>{T(0), T(0)};
   }
   load_twiddles<T, NZ, NT>(s_tw, static_cast<const cx<T>*>(a.twz), tid);
 #pragma unroll
@@ -1146,9 +1167,9 @@ __global__ __launch_bounds__(384) void k_zsweep_wave(SolveArgs a) {
     const double d2x = (double)a2.x - (double)h[q][2].x, d2y = (double)a2.y - (double)h[q][2].y;
     if (!a.cg) {
       S += (kx == 0 ? 1.0 : 2.0) * q2 * (d0x * d0x + d0y * d0y + d1x * d1x + d1y * d1y + d2x * d2x + d2y * d2y);
-      hp[go] = a0;
-      hp[plane + go] = a1;
-      hp[2 * plane + go] = a2;
+      store_stream<T>(hp + go, a0);
+      store_stream<T>(hp + plane + go, a1);
+      store_stream<T>(hp + 2 * plane + go, a2);
     }
     rg[o] = gamma_entry<T>(n0, n0, a0, a0, na, inv2mu, cc, m);
     rg[RS + o] = gamma_entry<T>(n1, n1, a1, a1, na, inv2mu, cc, m);
