@@ -69,15 +69,25 @@ extern "C" {
 #define HM_E_DEVICE (-4)   /* HIP runtime error                         */
 #define HM_E_DATA (-5)     /* device input inconsistent with the rule   */
 
+/* Enumerations are int-sized.  In C++ their underlying type is fixed to
+ * int, so that any int a caller passes is a value of the type and the
+ * library's range checks (which reject unknown values with HM_E_ARG) are
+ * well defined. */
+#ifdef __cplusplus
+#define HM_ENUM enum : int
+#else
+#define HM_ENUM enum
+#endif
+
 /* Homogenisation rule of the filter (Section 2, eqs. 3-5). */
-typedef enum {
+typedef HM_ENUM {
   HM_RULE_NONE = 0,     /* no filter: c~ = phase tensor at the grid point  */
   HM_RULE_VOIGT = 1,    /* eq. 3: fraction-weighted mean of stiffnesses    */
   HM_RULE_REUSS = 2,    /* eq. 4: inverse of the mean of compliances       */
   HM_RULE_LAMINATE = 3  /* eq. 5: two-phase laminate ("2-layer") rule      */
 } hm_rule;
 
-typedef enum { HM_FP64 = 0, HM_MIXED = 1 } hm_prec;
+typedef HM_ENUM { HM_FP64 = 0, HM_MIXED = 1 } hm_prec;
 
 typedef struct {
   int dim;  /* 2 or 3 */
@@ -96,7 +106,7 @@ typedef struct {
   double r;
 } hm_sphere;
 
-typedef enum { HM_FIXED_POINT = 0, HM_CONJUGATE_GRADIENT = 1 } hm_method;
+typedef HM_ENUM { HM_FIXED_POINT = 0, HM_CONJUGATE_GRADIENT = 1 } hm_method;
 
 typedef struct {
   hm_prec prec;     /* HM_FP64 or HM_MIXED                                   */

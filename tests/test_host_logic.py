@@ -92,3 +92,28 @@ def test_floor_fraction_and_design_bytes():
     # four sweeps over the six-component half spectrum plus the history and the ids
     want = (4 * 2 * 6 * plane * 8 + 2 * 3 * plane * 8 + 4 * 125 ** 3) / 125 ** 3
     assert bench.design_bytes_per_voxel_it(n, "mixed") == pytest.approx(want)
+
+
+def test_abi_argument_battery():
+    """Every entry point rejects each bad argument with its code and message,
+    and calls with valid arguments fail cleanly at the first device call
+    when no GPU is usable (tests/host_battery.py)."""
+    import os
+
+    import host_battery
+
+    L = host_battery.load_decls()
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libhm.so not built")
+    if L.load(L.LIB_PATH).hm_device_ok():
+        pytest.skip("a GPU is usable here: the battery's stand-in device pointers must not reach it")
+    # on a thread of its own: the library's last-error and timing state is
+    # per thread, and other tests expect this thread's to be untouched
+    import threading
+
+    res = {}
+    t = threading.Thread(target=lambda: res.update(out=host_battery.run()))
+    t.start()
+    t.join()
+    n, bad = res["out"]
+    assert n > 50 and not bad, bad
