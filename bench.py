@@ -153,7 +153,12 @@ def summarize_sq(trace_dir, sqa_dir, sqb_dir, out, which="c2", n_cu=256):
     regs = {}
     for r in trace:
         k = _short(r["Kernel_Name"])
-        regs[k] = (r.get("Arch_VGPR_Count", "?"), r.get("Accum_VGPR_Count", "?"), r.get("LDS_Block_Size", "?"),
+        # the trace's VGPR_Count counts granules of 4 registers per lane;
+        # gfx950 allocates wave64 registers in granules of 8, so the
+        # allocation is twice the field
+        v = r.get("VGPR_Count", r.get("Arch_VGPR_Count", "?"))
+        regs[k] = (str(2 * int(v)) if str(v).isdigit() else v, r.get("Accum_VGPR_Count", "?"),
+                   r.get("LDS_Block_Size", "?"),
                    r.get("Scratch_Size", "?"), r.get("Workgroup_Size", r.get("Workgroup_Size_X", "?")))
 
     def agg(d):
@@ -177,7 +182,8 @@ def summarize_sq(trace_dir, sqa_dir, sqb_dir, out, which="c2", n_cu=256):
              "#   python3 bench.py --summarize-sq <trace> <sqa> <sqb> --pass %s --out <this file>" % which,
              "# valu_busy = SQ_ACTIVE_INST_VALU / (CUs x GUI-active cycles of one XCD): the share of the time the",
              "# SIMDs issue vector ALU work (an FP32 or FP64 wave instruction takes 4 cycles on 16 lanes);",
-             "# waves_per_simd = SQ_WAVE_CYCLES x 4 / (4 SIMDs x CUs x GUI cycles); per-wave counts per dispatch",
+             "# waves_per_simd = SQ_WAVE_CYCLES x 4 / (4 SIMDs x CUs x GUI cycles); per-wave counts per dispatch;",
+             "# vgpr = registers allocated per lane, 2 x the trace's VGPR_Count (granules of 8 on gfx950)",
              "source_hash: %s" % kernel_source_hash(),
              "# kernel | avg_us | vgpr | agpr | lds_bytes | scratch | wg | waves | valu/wave | lds/wave | "
              "vmem_rd/wave | vmem_wr/wave | valu_busy | lds_busy | waves_per_simd | lds_bank_conflict/lds_cycle"]
