@@ -1231,7 +1231,8 @@ int run_groups(std::vector<Group>& G, const std::vector<ProblemIn>& all, const h
       // conduction plans have one compiled schedule
       if (opts->schedule >= 0 && opts->schedule != 0) return fail(HM_E_ARG, "conduction solves have one schedule");
     } else if (g.p->aniso && !opts->autotune) {
-      // anisotropic plans: the tuned schedule, or else the first one
+      // anisotropic plans without autotuning run the first schedule (a plan
+      // tuned by an earlier solve is set back to it)
       if (opts->schedule >= 0 && opts->schedule != 0) return fail(HM_E_ARG, "anisotropic solves pin no schedule");
       if (g.p->tuned) {
         set_schedule(g.p, &g.p->ak->x, &g.p->ky->y[0], &g.p->kz->z[0]);
